@@ -1,0 +1,226 @@
+/*
+ * dem.h -- C ABI of the MI355X DEM + fluid-coupling library.
+ *
+ * The library advances the coarse-grained CFD-DEM particle phase of
+ * Kazidenov, Khamitov & Amanbek, "Coarse-graining of CFD-DEM for simulation
+ * of sand production in the modified cohesive contact model"
+ * (arXiv:2211.06142):
+ *   - Newton-Euler motion of spheres (section 2.1, eq 1-2), velocity Verlet;
+ *   - modified JKR cohesive normal law: bonds break at the pull-off point C
+ *     and never re-form, new contacts are Hertz (section 2.3, eq 12-13,
+ *     Table 1, Fig. 2); damping from the restitution coefficient (eq 32-33);
+ *   - tangential spring-dashpot with Coulomb cap and contact torque
+ *     (section 2.1, eq 4-5, eq 35), optional rolling resistance;
+ *   - fluid-particle coupling of unresolved CFD-DEM "model A": porosity of
+ *     each fluid cell, Di Felice drag on each particle, drag source of each
+ *     cell (section 2.2, eq 6-11), buoyancy and pressure-gradient force;
+ *   - the fine-to-coarse scaling of section 2.4 (eq 14-35, Table 3) applied
+ *     by the coarse-grain factor k: only the surface energy changes
+ *     (gamma_g = k gamma_p), drag on a grain is k^3 times the drag on a fine
+ *     particle of diameter d/k.
+ *
+ * Conventions (all calls)
+ *   - SI units; 3-vectors interleaved (x0,y0,z0,x1,...), FP64 unless stated.
+ *   - Every call returns dem_status; no exception or longjmp crosses the ABI.
+ *   - A context is single-stream and not thread-safe.  All device work is
+ *     ordered on the HIP stream given to dem_init; calls return after the work
+ *     they queue has completed unless stated otherwise.
+ *   - Pointers marked "host or device" are inspected with
+ *     hipPointerGetAttributes; both kinds are accepted.
+ *   - Device faults found during stepping (pair capacity overflow, non-finite
+ *     force, a particle moving more than half the skin in one step) are latched
+ *     in a device status word and returned by the call that observes them;
+ *     the context then refuses further steps (DEM_E_STATE) until destroyed.
+ *   - Batches: a context may hold several independent samples (systems that
+ *     never interact), each with its own dem_params; particles of sample s are
+ *     the contiguous range [offsets[s], offsets[s+1]) of every per-particle
+ *     array and its fluid cells follow those of sample s-1.
+ */
+#ifndef DEM_H
+#define DEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DEM_OK = 0,
+  DEM_E_INVAL = -1,     /* invalid argument; no state was changed              */
+  DEM_E_NOMEM = -2,     /* device allocation failed                            */
+  DEM_E_CAPACITY = -3,  /* pair capacity exceeded and DEM_FLAG_AUTO_REGROW off  */
+  DEM_E_NONFINITE = -4, /* a force or torque became NaN or infinite            */
+  DEM_E_DEVICE = -5,    /* a HIP runtime call failed                           */
+  DEM_E_STATE = -6      /* call not valid in this state (see dem_status_str)   */
+} dem_status;
+
+#define DEM_MAX_WALLS 8
+
+enum { DEM_WALL_PLANE = 0, DEM_WALL_CYL_IN = 1, DEM_WALL_CYL_OUT = 2 };
+enum { DEM_NORMAL_JKR_MOD = 0, DEM_NORMAL_HERTZ = 1, DEM_NORMAL_LINEAR = 2 };
+enum { DEM_VOID_CIC = 0, DEM_VOID_CENTROID = 1 };
+enum { DEM_OUTLET_NONE = 0, DEM_OUTLET_CAVITY = 1 };
+enum { DEM_PREC_FP64 = 0, DEM_PREC_MIXED = 1 };
+enum { DEM_CG_SSW = 0, DEM_CG_SSP = 1 };
+enum { DEM_FLAG_AUTO_REGROW = 1u };
+
+/* A wall.  PLANE: p[0..2] unit normal pointing into the particle side, p[3]
+ * offset (signed distance of a point x is n.x - p[3]).  CYL_IN: particles
+ * inside a z-axis cylinder, p[0], p[1] axis position, p[2] radius.  CYL_OUT:
+ * particles outside such a cylinder.  Walls are rigid, static, of the
+ * particles' material; contact with them is Hertz with tangential history
+ * (the particle-wall law of section 3.1). */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double p[6];
+} dem_wall;
+
+/* Cell-centred fluid grid: n[0]*n[1]*n[2] cells of equal size covering
+ * [lo, hi]; cell (ix, iy, iz) has linear index (iz*n[1] + iy)*n[0] + ix. */
+typedef struct {
+  double lo[3], hi[3];
+  int32_t n[3];
+  int32_t reserved;
+} dem_grid;
+
+/* Parameters of one sample.  Material values are FINE-scale (the layout of
+ * Table 3); the library applies the coarse-graining of section 2.4 with the
+ * factor k: gamma_g = k gamma, everything else unchanged, drag rule k^3 f(d/k).
+ * Particle radii given to dem_init are the grains' own radii (SSW: fine
+ * diameters times k; SSP: one diameter, see dem_cg_diameters). */
+typedef struct {
+  double rho, E, nu, e, mu, mu_roll, gamma;  /* density, Young, Poisson, restitution,
+                                                friction, rolling friction, surface energy */
+  double k;                 /* coarse-grain factor (eq 14), >= 1; 1 = no scaling    */
+  int32_t cg_scheme;        /* DEM_CG_SSW or DEM_CG_SSP (bookkeeping only)          */
+  int32_t normal_model;     /* DEM_NORMAL_*; LINEAR (eq 3) is a test law            */
+  double k_lin;             /* spring constant of the LINEAR law, N/m               */
+  int32_t fluid_on;         /* 1: drag/porosity coupling active                     */
+  int32_t voidfrac;         /* DEM_VOID_CIC (trilinear) or DEM_VOID_CENTROID         */
+  int32_t u_superficial;    /* 1: fluid velocity passed to dem_map_fluid is n*u     */
+  int32_t couple_every;     /* DEM steps between coupling evaluations (>= 1)        */
+  double rho_f, mu_f;       /* fluid density and viscosity (Table 4)                */
+  double n_min;             /* lower clamp of the cell porosity                     */
+  dem_grid grid;            /* fluid grid of this sample                            */
+  double g[3];              /* gravity                                              */
+  double dt;                /* DEM time step (same for all samples)                 */
+  double skin;              /* neighbour-list skin; <= 0: 0.1 x smallest diameter   */
+  double dt_rayleigh_max_frac; /* > 0: reject dt above this fraction of eq 37       */
+  int32_t outlet_kind;      /* DEM_OUTLET_*                                         */
+  int32_t n_walls;          /* <= DEM_MAX_WALLS                                     */
+  double outlet[4];         /* CAVITY: axis x, axis y, radius; centres inside leave */
+  dem_wall walls[DEM_MAX_WALLS];
+  int32_t precision;        /* DEM_PREC_FP64 or DEM_PREC_MIXED (same for all samples) */
+  int32_t bond_at_init;     /* 1: every touching pair starts bonded (JKR_MOD only)  */
+  int64_t pair_capacity;    /* half-pair capacity; <= 0: automatic                  */
+  uint32_t flags;           /* DEM_FLAG_*                                           */
+  int32_t reserved;
+} dem_params;
+
+/* Particle state.  Owned by the caller; on input to dem_init every pointer
+ * may be host or device, on output of dem_read_state every pointer may be
+ * host or device or NULL (not wanted).  Order of particles is the caller's
+ * original order throughout. */
+typedef struct {
+  int64_t n;                /* number of particles (all samples)                    */
+  double* x;                /* 3n positions                                         */
+  double* v;                /* 3n velocities                                        */
+  double* omega;            /* 3n angular velocities                                */
+  double* force;            /* 3n total force of the last evaluation (NULL: zero)   */
+  double* torque;           /* 3n total torque of the last evaluation (NULL: zero)  */
+  double* radius;           /* n radii (input only)                                 */
+  uint8_t* alive;           /* n; 0 = removed through the outlet (NULL: all alive)  */
+  /* contact history; dem_init: optional input (n_pairs > 0 replaces
+   * bond_at_init); dem_read_state: see dem_read_pairs */
+  int64_t n_pairs;
+  int64_t* pair_idx;        /* 2 n_pairs particle indices (a, b), a < b             */
+  double* pair_dt;          /* 3 n_pairs tangential elongation, orientation a -> b  */
+  uint8_t* pair_bonded;     /* n_pairs                                              */
+  /* scalars filled by dem_read_state */
+  double produced_mass;     /* mass removed through the outlet (eq 40 integrand)    */
+  double time;              /* simulated time                                       */
+  double coordination;      /* 2 x active contacts / alive particles                */
+  double kinetic;           /* translational + rotational kinetic energy            */
+  int64_t step;             /* steps taken                                          */
+  int64_t broken_bonds;     /* bonds broken at point C since init                   */
+  int64_t n_alive;
+  int64_t n_contacts;       /* active particle-particle contacts                    */
+} dem_state;
+
+typedef struct dem_ctx dem_ctx;
+
+/* Create a context on `device` using HIP stream `hip_stream` (NULL: the
+ * default stream).  params: n_samples entries; sample_offsets: n_samples+1
+ * increasing particle offsets (NULL allowed when n_samples == 1).  The
+ * initial state is copied; the caller keeps ownership.  Validation failures
+ * (dt <= 0 or differing between samples, nu outside (-1, 0.5), e outside
+ * (0, 1], k < 1, a radius <= 0, a non-finite input, an empty fluid grid while
+ * fluid_on, dt above dt_rayleigh_max_frac of the Rayleigh step of eq 37-38
+ * for the smallest radius) return DEM_E_INVAL and leave *out NULL. */
+dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples,
+                    const int64_t* sample_offsets, const dem_state* init, int32_t device,
+                    void* hip_stream);
+
+/* Advance every sample by nsteps DEM steps (stream-ordered). */
+dem_status dem_step(dem_ctx* ctx, int64_t nsteps);
+
+/* Coupling exchange with the fluid solver (section 2.2, eq 6-7).
+ * u_cell, gradp_cell: 3*ncell fluid velocity (superficial n*u when
+ * u_superficial) and dynamic pressure gradient per cell, host or device,
+ * FP64; they replace the fields used by later coupling evaluations.
+ * eps_solid_out (ncell) and fdrag_out (3*ncell), host, device or NULL,
+ * receive the solid volume fraction and the eq 7 drag source (sum over the
+ * particles of the drag ON them, weighted into the cell, per cell volume;
+ * the fluid receives its negative) of the latest coupling evaluation, and
+ * zeros before the first one.  ncell is the total over all samples. */
+dem_status dem_map_fluid(dem_ctx* ctx, const double* u_cell, const double* gradp_cell,
+                         double* eps_solid_out, double* fdrag_out);
+
+/* Copy the state out in the caller's particle order (see dem_state).  The
+ * pair arrays are not written; use dem_read_pairs. */
+dem_status dem_read_state(dem_ctx* ctx, dem_state* out);
+
+/* Active contact history: pairs with a bond or touching at the last force
+ * evaluation, as particle indices a < b in the caller's order.  cap is the
+ * capacity of the output arrays (host or device); *n_out receives the count
+ * (which may exceed cap; then only cap entries are written).  touching_only:
+ * 0 active pairs, 1 only pairs with d < r_a + r_b, 2 every candidate pair of
+ * the neighbour list (d < r_a + r_b + cutoff margin). */
+dem_status dem_read_pairs(dem_ctx* ctx, int32_t which, int64_t cap, int64_t* pair_idx,
+                          double* pair_dt, uint8_t* pair_bonded, int64_t* n_out);
+
+/* Per-sample aggregates (section 3.3-3.4 observables): produced mass,
+ * coordination number, broken bonds, alive count.  Arrays of n_samples, host. */
+dem_status dem_read_aggregates(dem_ctx* ctx, double* produced_mass, double* coordination,
+                               int64_t* broken_bonds, int64_t* n_alive);
+
+/* Query: total fluid cells, pair-list size and capacity, rebuild count, and
+ * the candidate margin (skin plus the largest pull-off separation) used by
+ * the neighbour list of sample 0. */
+dem_status dem_info(dem_ctx* ctx, int64_t* ncell, int64_t* n_pairs, int64_t* pair_capacity,
+                    int64_t* rebuilds, double* cutoff_margin);
+
+/* Force a neighbour-list rebuild at the start of the next step. */
+dem_status dem_request_rebuild(dem_ctx* ctx);
+
+void dem_destroy(dem_ctx* ctx);
+const char* dem_status_str(dem_status s);
+
+/* ---- coarse-graining helpers (host only, no device needed) ----
+ * dem_cg_material: grain-scale surface energy and drag factor of section 2.4
+ * (Table 3: rho, E, nu, e, mu unchanged, gamma x k).
+ * dem_cg_diameters: SSW multiplies each fine diameter by k; SSP writes one
+ * diameter, k (sum d^3 / n)^(1/3), to every output.  n_fine inputs, n_out
+ * outputs (SSW: n_out <= n_fine, the first n_out are used). */
+dem_status dem_cg_material(const dem_params* fine, double* gamma_grain, double* drag_factor);
+dem_status dem_cg_diameters(int32_t scheme, double k, const double* d_fine, int64_t n_fine,
+                            double* d_out, int64_t n_out);
+/* eq 37-38 Rayleigh time step with G = E / (2 (1 + nu)). */
+double dem_rayleigh_dt(double radius, double rho, double E, double nu);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,108 @@
+/*
+ * dem_oracle.h -- plain, slow, FP64 CPU oracle of the CFD-DEM step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link
+ * or call this.  It shares no code, header, constant or helper with the HIP
+ * library under paper_2211_06142_amd/ and include/.
+ *
+ * Every function restates the paper (Kazidenov, Khamitov, Amanbek,
+ * "Coarse-graining of CFD-DEM for simulation of sand production in the
+ * modified cohesive contact model", arXiv:2211.06142) in the most direct
+ * form: brute force or a plain grid for contacts, bisection for the JKR
+ * contact radius, plain sums in particle-index order for every reduction.
+ *
+ * Conventions
+ *   - particles are stored in index order; index = identity
+ *   - pair (i, j) always has i < j; n points from i to j
+ *   - all arrays are plain C arrays of doubles, 3-vectors interleaved (x,y,z)
+ */
+#ifndef DEM_ORACLE_H
+#define DEM_ORACLE_H
+#include <stdint.h>
+
+#define OR_MAX_WALLS 8
+
+enum { OR_WALL_PLANE = 0, OR_WALL_CYL_IN = 1, OR_WALL_CYL_OUT = 2 };
+enum { OR_NORMAL_JKR_MOD = 0, OR_NORMAL_HERTZ = 1, OR_NORMAL_LINEAR = 2 };
+enum { OR_VOID_CIC = 0, OR_VOID_CENTROID = 1 };
+enum { OR_OUTLET_NONE = 0, OR_OUTLET_CAVITY = 1 };
+
+typedef struct {
+  int kind;
+  /* plane   : p[0..2] inward unit normal, p[3] offset  (signed distance = n.x - p[3])
+   * cyl_in  : particles inside a z-axis cylinder, p[0],p[1] axis (x,y), p[2] radius
+   * cyl_out : particles outside a z-axis cylinder, same layout                       */
+  double p[6];
+} or_wall;
+
+typedef struct {
+  double lo[3], hi[3];
+  int n[3];
+} or_grid;
+
+typedef struct {
+  /* grain-scale material (coarse-graining already applied to gamma) */
+  double rho, E, nu, e, mu, mu_roll, gamma;
+  double k_cg;          /* coarse-grain factor for the drag rule f = k^3 f(d/k) */
+  double k_lin;         /* spring constant of the linear test law (eq 3)        */
+  int normal_model;     /* OR_NORMAL_*                                           */
+  /* fluid */
+  int fluid_on;
+  double rho_f, mu_f, n_min;
+  int voidfrac;         /* OR_VOID_*                                             */
+  int u_superficial;    /* 1: cell velocity given is n*u                         */
+  int couple_every;
+  or_grid grid;
+  /* body, time */
+  double g[3];
+  double dt;
+  /* geometry */
+  int outlet_kind;      /* OR_OUTLET_*                                           */
+  double outlet[4];     /* cavity: axis x, axis y, radius                        */
+  int n_walls;
+  or_wall walls[OR_MAX_WALLS];
+  int use_grid_search;  /* 0 brute force O(N^2); 1 plain uniform grid            */
+} or_params;
+
+typedef struct or_sim or_sim;
+
+/* ---- single-contact laws (section 2.3, eq 12-13, Table 1) ---- */
+double or_jkr_delta_of_a(double a, double Rs, double Es, double gamma);   /* eq 13 */
+double or_jkr_force_of_a(double a, double Rs, double Es, double gamma);   /* eq 12 */
+double or_jkr_a_of_delta(double delta, double Rs, double Es, double gamma); /* eq 13 inverted */
+int    or_bond_holds(double d2, double c, double Rs, double Es, double gamma);
+double or_beta_of_e(double e);                                             /* eq 33 (squared) */
+
+/* ---- Di Felice drag on one particle (eq 8-11) ---- */
+void or_drag(const double s[3], double d, double k_cg, double n, double rho_f, double mu_f,
+             double c_drag, double out_f[3]);
+
+/* ---- contact sets (plain definitions) ---- */
+/* all pairs i<j (both alive) with d2 < (ri+rj+extra)^2; returns count, writes up to cap */
+int64_t or_pairs_brute(int64_t n, const double* x, const double* r, const uint8_t* alive,
+                       double extra, int64_t cap, int64_t* pi, int64_t* pj);
+int64_t or_pairs_grid(int64_t n, const double* x, const double* r, const uint8_t* alive,
+                      double extra, int64_t cap, int64_t* pi, int64_t* pj);
+
+/* ---- simulation ---- */
+or_sim* or_create(const or_params* p, int64_t n, const double* x, const double* v,
+                  const double* w, const double* F, const double* T, const double* r,
+                  const uint8_t* alive,
+                  int64_t npairs, const int64_t* pi, const int64_t* pj,
+                  const double* pdt, const uint8_t* pbond, int bond_at_init,
+                  const double* wall_dt);
+void    or_destroy(or_sim* s);
+int     or_set_fluid(or_sim* s, const double* u_cell, const double* gradp_cell);
+int     or_set_closure(or_sim* s, const double* c_drag, const double* c_coh);
+int     or_step(or_sim* s, int64_t nsteps);
+void    or_get_state(const or_sim* s, double* x, double* v, double* w, double* F, double* T,
+                     uint8_t* alive, double* fscale, double* tscale);
+void    or_get_scalars(const or_sim* s, double* produced_mass, int64_t* broken_bonds,
+                       int64_t* step, int64_t* n_contacts, double* kinetic);
+int64_t or_get_pairs(const or_sim* s, int64_t cap, int64_t* pi, int64_t* pj, double* pdt,
+                     uint8_t* pbond, uint8_t* ptouch);
+void    or_get_wall_dt(const or_sim* s, double* wall_dt);
+void    or_get_fluid(const or_sim* s, double* eps_s, double* fdrag_cell, double* f_part,
+                     double* fb_part);
+
+#endif

@@ -1,0 +1,873 @@
+// dem_api.hip -- host runtime behind the C ABI of include/dem.h.
+//
+// Owns the device memory of one context, derives the per-sample constants
+// (coarse-graining of section 2.4 applied here), drives the rebuild /
+// coupling / force / integration kernels of dem_kernels.hip on the caller's
+// stream, and converts between the caller's particle order and the sorted
+// device order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "dem_internal.h"
+
+using namespace dem;
+
+namespace {
+
+#define HIPCHK(x)                                    \
+  do {                                               \
+    hipError_t e_ = (x);                             \
+    if (e_ != hipSuccess) return DEM_E_DEVICE;       \
+  } while (0)
+
+struct PairSet {
+  int32_t *prow = nullptr, *pj = nullptr, *pown = nullptr;
+  void* hdt = nullptr;
+  uint8_t* pfl = nullptr;
+  int64_t cap = 0, n = 0;
+};
+
+struct WallSet {
+  int32_t *wrow = nullptr, *wid = nullptr;
+  void* wdt = nullptr;
+  uint8_t* wfl = nullptr;
+  int64_t cap = 0, n = 0;
+};
+
+}  // namespace
+
+struct dem_ctx {
+  DevState d;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int fp64 = 1;
+  size_t rsz = 8;  // sizeof(R)
+  std::vector<dem_params> params;
+  std::vector<SampleConst> sc;
+  std::vector<int64_t> offsets;
+  int64_t* d_offsets = nullptr;
+  std::vector<double> dead_mass0;
+  PairSet ps[2];
+  WallSet ws[2];
+  int cur = 0;          // ps[cur] / ws[cur] is the live list
+  int64_t rec_cap = 0;  // capacity of recF/recC/recT/ridx
+  int64_t step = 0;
+  int64_t rebuilds = 0;
+  int have_fluid = 0;
+  int any_fluid = 0;
+  int force_rebuild = 1;
+  int failed = 0;       // a latched device fault
+  int* h_flag = nullptr;  // pinned
+  std::vector<void*> allocs;
+  // staging for read-back
+  double* stage = nullptr;
+  uint8_t* stage_alive = nullptr;
+};
+
+namespace {
+
+template <typename T> hipError_t dalloc(dem_ctx* c, T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
+  if (e == hipSuccess) c->allocs.push_back((void*)*p);
+  return e;
+}
+
+hipError_t dalloc_bytes(dem_ctx* c, void** p, int64_t bytes) {
+  *p = nullptr;
+  if (bytes <= 0) bytes = 16;
+  hipError_t e = hipMalloc(p, (size_t)bytes);
+  if (e == hipSuccess) c->allocs.push_back(*p);
+  return e;
+}
+
+void dfree(dem_ctx* c, void* p) {
+  if (!p) return;
+  for (auto& a : c->allocs)
+    if (a == p) { (void)hipFree(p); a = nullptr; }
+}
+
+bool finite_all(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// copy from host or device memory into a host vector
+template <typename T> hipError_t fetch(std::vector<T>& out, const T* src, int64_t count) {
+  out.resize((size_t)std::max<int64_t>(count, 0));
+  if (count <= 0 || !src) return hipSuccess;
+  return hipMemcpy(out.data(), src, sizeof(T) * (size_t)count, hipMemcpyDefault);
+}
+
+const double kPi = 3.14159265358979323846;
+
+double beta_of_e(double e) {
+  double l = log(e);
+  return -l / sqrt(l * l + kPi * kPi);
+}
+
+dem_status validate(const dem_params& p) {
+  if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return DEM_E_INVAL;
+  if (!(p.nu > -1.0 && p.nu < 0.5)) return DEM_E_INVAL;
+  if (!(p.e > 0.0 && p.e <= 1.0)) return DEM_E_INVAL;
+  if (!(p.k >= 1.0)) return DEM_E_INVAL;
+  if (!(p.rho > 0.0) || !(p.E > 0.0) || !(p.mu >= 0.0) || !(p.mu_roll >= 0.0) || !(p.gamma >= 0.0))
+    return DEM_E_INVAL;
+  if (p.n_walls < 0 || p.n_walls > DEM_MAX_WALLS) return DEM_E_INVAL;
+  if (p.normal_model < 0 || p.normal_model > 2) return DEM_E_INVAL;
+  if (p.normal_model == DEM_NORMAL_LINEAR && !(p.k_lin > 0.0)) return DEM_E_INVAL;
+  if (p.precision != DEM_PREC_FP64 && p.precision != DEM_PREC_MIXED) return DEM_E_INVAL;
+  if (p.fluid_on) {
+    for (int c = 0; c < 3; ++c)
+      if (p.grid.n[c] < 1 || !(p.grid.hi[c] > p.grid.lo[c])) return DEM_E_INVAL;
+    if (!(p.rho_f > 0.0) || !(p.mu_f > 0.0) || !(p.n_min > 0.0 && p.n_min <= 1.0)) return DEM_E_INVAL;
+    if (p.couple_every < 1) return DEM_E_INVAL;
+    if (p.voidfrac != DEM_VOID_CIC && p.voidfrac != DEM_VOID_CENTROID) return DEM_E_INVAL;
+  }
+  for (int w = 0; w < p.n_walls; ++w)
+    if (p.walls[w].kind < 0 || p.walls[w].kind > 2) return DEM_E_INVAL;
+  return DEM_OK;
+}
+
+// per-sample constants (grain scale) and the binning grid
+void derive(const dem_params& p, const double* x, const double* r, const uint8_t* alive, int64_t lo,
+            int64_t hi, SampleConst& c) {
+  memset(&c, 0, sizeof(c));
+  c.Es = p.E / (2.0 * (1.0 - p.nu * p.nu));
+  c.Gs = p.E / (4.0 * (2.0 - p.nu) * (1.0 + p.nu));
+  c.beta = beta_of_e(p.e);
+  c.cdamp = 2.0 * sqrt(5.0 / 6.0) * c.beta;
+  c.gamma = p.k * p.gamma;                           // eq 24
+  if (p.normal_model != DEM_NORMAL_JKR_MOD) c.gamma = 0.0;
+  c.mu = p.mu;
+  c.mu_roll = p.mu_roll;
+  c.rho = p.rho;
+  c.k_lin = p.k_lin;
+  c.jkrK = (kPi * kPi) * (c.gamma * c.gamma) / (c.Es * c.Es);
+  c.breakA = ((3.0 / 16.0) * (kPi * kPi)) * (c.gamma * c.gamma);
+  c.kcg = p.k;
+  c.k3 = p.k * p.k * p.k;
+  c.normal_model = p.normal_model;
+  c.fluid_on = p.fluid_on;
+  c.voidfrac = p.voidfrac;
+  c.u_superficial = p.u_superficial;
+  c.rho_f = p.rho_f;
+  c.mu_f = p.mu_f;
+  c.n_min = p.n_min;
+  for (int k = 0; k < 3; ++k) {
+    c.g[k] = p.g[k];
+    if (p.fluid_on) {
+      c.glo[k] = p.grid.lo[k];
+      c.gh[k] = (p.grid.hi[k] - p.grid.lo[k]) / p.grid.n[k];
+      c.gn[k] = p.grid.n[k];
+      c.dn[k] = p.voidfrac == DEM_VOID_CENTROID ? p.grid.n[k] : std::max(p.grid.n[k] - 1, 1);
+    } else {
+      c.glo[k] = 0.0; c.gh[k] = 1.0; c.gn[k] = 1; c.dn[k] = 1;
+    }
+  }
+  c.vcell = c.gh[0] * c.gh[1] * c.gh[2];
+  c.outlet_kind = p.outlet_kind;
+  for (int k = 0; k < 4; ++k) c.outlet[k] = p.outlet[k];
+  c.n_walls = p.n_walls;
+  for (int w = 0; w < p.n_walls; ++w) {
+    c.walls[w].kind = p.walls[w].kind;
+    for (int k = 0; k < 6; ++k) c.walls[w].p[k] = p.walls[w].p[k];
+  }
+  // sizes
+  double rmin = 1e300, rmax = 0.0, bl[3] = {1e300, 1e300, 1e300}, bh[3] = {-1e300, -1e300, -1e300};
+  int64_t nal = 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    rmin = std::min(rmin, r[i]);
+    rmax = std::max(rmax, r[i]);
+    if (alive && !alive[i]) continue;
+    ++nal;
+    for (int k = 0; k < 3; ++k) { bl[k] = std::min(bl[k], x[3 * i + k]); bh[k] = std::max(bh[k], x[3 * i + k]); }
+  }
+  if (nal == 0) { for (int k = 0; k < 3; ++k) { bl[k] = 0.0; bh[k] = 0.0; } }
+  if (rmax == 0.0) { rmin = rmax = 1e-6; }
+  c.skin = p.skin > 0.0 ? p.skin : 0.2 * rmin;
+  // largest pull-off separation |delta_C| = (3/16)^(1/3) X (Table 1), with the
+  // surface energy bounded by twice its value (closure factors are <= 2)
+  double gmax = 2.0 * c.gamma;
+  double Rsmax = 0.5 * rmax;
+  double dC = cbrt(3.0 / 16.0) * cbrt((kPi * kPi) * gmax * gmax * Rsmax / (c.Es * c.Es));
+  c.margin = c.skin + 1.01 * dC;
+  double h = 2.0 * rmax + c.margin;
+  double ext[3];
+  for (int k = 0; k < 3; ++k) {
+    c.blo[k] = bl[k] - h;
+    ext[k] = (bh[k] - bl[k]) + 2.0 * h;
+  }
+  int64_t budget = 4 * std::max<int64_t>(hi - lo, 1) + 64;
+  for (;;) {
+    int64_t tot = 1;
+    for (int k = 0; k < 3; ++k) {
+      double q = floor(ext[k] / h);
+      c.bn[k] = (int)std::max(1.0, std::min(q, (double)(1 << 20)));
+      tot *= c.bn[k];
+    }
+    if (tot <= budget) break;
+    h *= 1.25;
+  }
+  for (int k = 0; k < 3; ++k) c.bh[k] = ext[k] / c.bn[k];
+}
+
+template <typename R> void run_kick_drift(dem_ctx* c) { launch_kick_drift<R>(c->d, c->stream); }
+
+// bind the live pair/wall sets into the device descriptor
+void bind_sets(dem_ctx* c) {
+  PairSet& a = c->ps[c->cur];
+  PairSet& b = c->ps[1 - c->cur];
+  c->d.prow = a.prow; c->d.pj = a.pj; c->d.pown = a.pown; c->d.hdt = a.hdt; c->d.pfl = a.pfl;
+  c->d.pair_cap = a.cap; c->d.npairs = a.n;
+  c->d.prow_old = b.prow; c->d.pj_old = b.pj; c->d.hdt2 = b.hdt; c->d.pfl2 = b.pfl;
+  WallSet& wa = c->ws[c->cur];
+  WallSet& wb = c->ws[1 - c->cur];
+  c->d.wrow = wa.wrow; c->d.wid = wa.wid; c->d.wdt = wa.wdt; c->d.wfl = wa.wfl;
+  c->d.wall_cap = wa.cap; c->d.nwall = wa.n;
+  c->d.wrow_old = wb.wrow; c->d.wid_old = wb.wid; c->d.wdt2 = wb.wdt; c->d.wfl2 = wb.wfl;
+}
+
+hipError_t grow_pairs(dem_ctx* c, PairSet& s, int64_t need) {
+  if (need <= s.cap) return hipSuccess;
+  int64_t cap = std::max<int64_t>(need + need / 4 + 1024, s.cap * 2);
+  dfree(c, s.pj); dfree(c, s.pown); dfree(c, s.hdt); dfree(c, s.pfl);
+  hipError_t e;
+  if ((e = dalloc(c, &s.pj, cap)) != hipSuccess) return e;
+  if ((e = dalloc(c, &s.pown, cap)) != hipSuccess) return e;
+  if ((e = dalloc_bytes(c, &s.hdt, cap * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
+  if ((e = dalloc(c, &s.pfl, cap)) != hipSuccess) return e;
+  s.cap = cap;
+  return hipSuccess;
+}
+
+hipError_t grow_walls(dem_ctx* c, WallSet& s, int64_t need) {
+  if (need <= s.cap) return hipSuccess;
+  int64_t cap = std::max<int64_t>(need + need / 4 + 256, s.cap * 2);
+  dfree(c, s.wid); dfree(c, s.wdt); dfree(c, s.wfl);
+  hipError_t e;
+  if ((e = dalloc(c, &s.wid, cap)) != hipSuccess) return e;
+  if ((e = dalloc_bytes(c, &s.wdt, cap * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
+  if ((e = dalloc(c, &s.wfl, cap)) != hipSuccess) return e;
+  s.cap = cap;
+  return hipSuccess;
+}
+
+hipError_t grow_records(dem_ctx* c, int64_t need) {
+  if (need <= c->rec_cap) return hipSuccess;
+  int64_t cap = need + need / 4 + 1024;
+  dfree(c, c->d.recF); dfree(c, c->d.recC); dfree(c, c->d.recT); dfree(c, c->d.ridx);
+  hipError_t e;
+  if ((e = dalloc_bytes(c, &c->d.recF, cap * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
+  if ((e = dalloc_bytes(c, &c->d.recC, cap * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
+  if ((e = dalloc_bytes(c, &c->d.recT, (c->d.rolling ? cap : 1) * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
+  if ((e = dalloc(c, &c->d.ridx, cap)) != hipSuccess) return e;
+  c->rec_cap = cap;
+  return hipSuccess;
+}
+
+template <typename T> void swp(T& a, T& b) { T t = a; a = b; b = t; }
+
+// full neighbour-list rebuild (sort, permute, search, merge, reverse index)
+template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) {
+  DevState& d = c->d;
+  hipStream_t s = c->stream;
+  // 1. sort by (sample, cell, id); dead particles to their sample's last bucket
+  launch_bin_keys(d, s);
+  launch_bucket_sort(d.key, d.n, d.nbins_total, d.orig, d.bucket_cnt, d.cell_start, d.bucket_fill, d.order,
+                     d.scan_tmp, s);
+  launch_permute<R>(d, s);
+  swp(d.xr, d.xr2); swp(d.vel, d.vel2); swp(d.omg, d.omg2); swp(d.frc, d.frc2); swp(d.trq, d.trq2);
+  swp(d.fdr, d.fdr2); swp(d.alive, d.alive2); swp(d.sample, d.sample2); swp(d.orig, d.orig2);
+  if (d.cdrag) { swp(d.cdrag, d.cdrag2); swp(d.ccoh, d.ccoh2); }
+  // 2. the live list becomes the old one
+  int64_t old_n = c->ps[c->cur].n;
+  if (!first) c->cur = 1 - c->cur;
+  bind_sets(c);
+  // 3. count and fill pairs
+  launch_pair_count(d, s);
+  HIPCHK(hipMemsetAsync(d.pcnt + d.n, 0, sizeof(int32_t), s));
+  scan_exclusive(d.pcnt, d.prow, d.n + 1, d.scan_tmp, s);
+  launch_wall_count(d, s);
+  HIPCHK(hipMemsetAsync(d.wcnt + d.n, 0, sizeof(int32_t), s));
+  scan_exclusive(d.wcnt, d.wrow, d.n + 1, d.scan_tmp, s);
+  int32_t tot[2];
+  HIPCHK(hipMemcpyAsync(&tot[0], d.prow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tot[1], d.wrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  PairSet& ps = c->ps[c->cur];
+  WallSet& ws = c->ws[c->cur];
+  if (grow_pairs(c, ps, tot[0]) != hipSuccess) return DEM_E_NOMEM;
+  if (grow_walls(c, ws, tot[1]) != hipSuccess) return DEM_E_NOMEM;
+  if (grow_records(c, tot[0]) != hipSuccess) return DEM_E_NOMEM;
+  ps.n = tot[0];
+  ws.n = tot[1];
+  bind_sets(c);
+  launch_pair_fill(d, s);
+  launch_wall_fill(d, s);
+  // 4. carry history
+  int check = first ? 0 : 1;
+  if (check) launch_count_old_bonds(d, old_n, s);
+  launch_hist_merge<R>(d, s, check);
+  if (check) launch_check_lost(d, s);
+  if (mark_bonds) launch_mark_bonds(d, s);
+  // 5. reverse index and reference positions
+  launch_reverse(d, s);
+  launch_set_xref(d, s);
+  c->rebuilds++;
+  return DEM_OK;
+}
+
+template <typename R> dem_status step_impl(dem_ctx* c, int64_t nsteps) {
+  DevState& d = c->d;
+  hipStream_t s = c->stream;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    launch_kick_drift<R>(d, s);
+    int need = c->force_rebuild;
+    if (!need) {
+      HIPCHK(hipMemcpyAsync(c->h_flag, d.rebuild_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      need = *c->h_flag;
+    }
+    if (need) {
+      dem_status st = rebuild<R>(c, 0, 0);
+      if (st != DEM_OK) return st;
+      HIPCHK(hipMemsetAsync(d.rebuild_flag, 0, sizeof(int), s));
+      c->force_rebuild = 0;
+    }
+    if (c->any_fluid && c->have_fluid && (c->step % d.couple_every) == 0) launch_fluid<R>(d, s);
+    launch_pair_force<R>(d, s);
+    launch_gather_kick<R>(d, s);
+    c->step++;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  int st = 0;
+  HIPCHK(hipMemcpy(&st, d.status, sizeof(int), hipMemcpyDeviceToHost));
+  if (st) {
+    c->failed = st;
+    if (st & kStNonFinite) return DEM_E_NONFINITE;
+    if (st & kStCapacity) return DEM_E_CAPACITY;
+    return DEM_E_STATE;
+  }
+  return DEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dem_status_str(dem_status s) {
+  switch (s) {
+    case DEM_OK: return "ok";
+    case DEM_E_INVAL: return "invalid argument";
+    case DEM_E_NOMEM: return "device allocation failed";
+    case DEM_E_CAPACITY: return "pair capacity exceeded";
+    case DEM_E_NONFINITE: return "non-finite force or torque";
+    case DEM_E_DEVICE: return "HIP runtime error";
+    case DEM_E_STATE:
+      return "invalid state (fault latched: a particle moved more than half the skin in one step, a bond "
+             "was lost by the neighbour list, or fluid fields are missing)";
+  }
+  return "unknown status";
+}
+
+double dem_rayleigh_dt(double radius, double rho, double E, double nu) {
+  double G = E / (2.0 * (1.0 + nu));
+  double beta = 0.8766 + 0.163 * nu;
+  return kPi * radius / beta * sqrt(rho / G);
+}
+
+dem_status dem_cg_material(const dem_params* fine, double* gamma_grain, double* drag_factor) {
+  if (!fine || !(fine->k >= 1.0)) return DEM_E_INVAL;
+  if (gamma_grain) *gamma_grain = fine->k * fine->gamma;
+  if (drag_factor) *drag_factor = fine->k * fine->k * fine->k;
+  return DEM_OK;
+}
+
+dem_status dem_cg_diameters(int32_t scheme, double k, const double* d_fine, int64_t n_fine, double* d_out,
+                            int64_t n_out) {
+  if (!(k >= 1.0) || !d_fine || !d_out || n_fine <= 0 || n_out < 0) return DEM_E_INVAL;
+  if (scheme == DEM_CG_SSW) {
+    if (n_out > n_fine) return DEM_E_INVAL;
+    for (int64_t i = 0; i < n_out; ++i) d_out[i] = k * d_fine[i];
+    return DEM_OK;
+  }
+  if (scheme == DEM_CG_SSP) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n_fine; ++i) s += d_fine[i] * d_fine[i] * d_fine[i];
+    double dbar = cbrt(s / (double)n_fine);
+    for (int64_t i = 0; i < n_out; ++i) d_out[i] = k * dbar;
+    return DEM_OK;
+  }
+  return DEM_E_INVAL;
+}
+
+dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, const int64_t* sample_offsets,
+                    const dem_state* init, int32_t device, void* hip_stream) {
+  if (!out) return DEM_E_INVAL;
+  *out = nullptr;
+  if (!params || n_samples < 1 || !init || init->n < 0 || !init->x || !init->radius) return DEM_E_INVAL;
+  if (n_samples > 1 && !sample_offsets) return DEM_E_INVAL;
+  const int64_t n = init->n;
+  if (n > (int64_t)1 << 30) return DEM_E_INVAL;
+  std::vector<int64_t> offs(n_samples + 1);
+  if (sample_offsets) {
+    for (int s = 0; s <= n_samples; ++s) offs[s] = sample_offsets[s];
+    if (offs[0] != 0 || offs[n_samples] != n) return DEM_E_INVAL;
+    for (int s = 0; s < n_samples; ++s)
+      if (offs[s + 1] < offs[s]) return DEM_E_INVAL;
+  } else {
+    offs[0] = 0;
+    offs[1] = n;
+  }
+  for (int s = 0; s < n_samples; ++s) {
+    dem_status v = validate(params[s]);
+    if (v != DEM_OK) return v;
+    if (params[s].dt != params[0].dt || params[s].precision != params[0].precision ||
+        params[s].couple_every != params[0].couple_every)
+      return DEM_E_INVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DEM_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return DEM_E_DEVICE;
+  // host copies of the inputs
+  std::vector<double> x, v, w, F, T, r;
+  std::vector<uint8_t> alive;
+  if (fetch(x, init->x, 3 * n) != hipSuccess || fetch(r, init->radius, n) != hipSuccess) return DEM_E_DEVICE;
+  if (init->v && fetch(v, init->v, 3 * n) != hipSuccess) return DEM_E_DEVICE;
+  if (init->omega && fetch(w, init->omega, 3 * n) != hipSuccess) return DEM_E_DEVICE;
+  if (init->force && fetch(F, init->force, 3 * n) != hipSuccess) return DEM_E_DEVICE;
+  if (init->torque && fetch(T, init->torque, 3 * n) != hipSuccess) return DEM_E_DEVICE;
+  if (init->alive && fetch(alive, init->alive, n) != hipSuccess) return DEM_E_DEVICE;
+  if (v.empty()) v.assign(3 * n, 0.0);
+  if (w.empty()) w.assign(3 * n, 0.0);
+  if (F.empty()) F.assign(3 * n, 0.0);
+  if (T.empty()) T.assign(3 * n, 0.0);
+  if (alive.empty()) alive.assign(n, 1);
+  if (!finite_all(x.data(), 3 * n) || !finite_all(v.data(), 3 * n) || !finite_all(w.data(), 3 * n) ||
+      !finite_all(F.data(), 3 * n) || !finite_all(T.data(), 3 * n) || !finite_all(r.data(), n))
+    return DEM_E_INVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(r[i] > 0.0)) return DEM_E_INVAL;
+  // Rayleigh guard (eq 37-38) for the smallest radius of each sample
+  for (int s = 0; s < n_samples; ++s) {
+    const dem_params& p = params[s];
+    if (p.dt_rayleigh_max_frac > 0.0 && offs[s + 1] > offs[s]) {
+      double rmin = 1e300;
+      for (int64_t i = offs[s]; i < offs[s + 1]; ++i) rmin = std::min(rmin, r[i]);
+      if (p.dt > p.dt_rayleigh_max_frac * dem_rayleigh_dt(rmin, p.rho, p.E, p.nu)) return DEM_E_INVAL;
+    }
+  }
+  // initial pair history (optional)
+  std::vector<int64_t> hp;
+  std::vector<double> hdt;
+  std::vector<uint8_t> hb;
+  int64_t np0 = init->n_pairs > 0 ? init->n_pairs : 0;
+  if (np0 > 0) {
+    if (!init->pair_idx) return DEM_E_INVAL;
+    if (fetch(hp, init->pair_idx, 2 * np0) != hipSuccess) return DEM_E_DEVICE;
+    if (init->pair_dt && fetch(hdt, init->pair_dt, 3 * np0) != hipSuccess) return DEM_E_DEVICE;
+    if (init->pair_bonded && fetch(hb, init->pair_bonded, np0) != hipSuccess) return DEM_E_DEVICE;
+    for (int64_t k = 0; k < np0; ++k) {
+      int64_t a = hp[2 * k], b = hp[2 * k + 1];
+      if (a < 0 || b < 0 || a >= n || b >= n || a == b) return DEM_E_INVAL;
+    }
+  }
+
+  dem_ctx* c = new dem_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->params.assign(params, params + n_samples);
+  c->offsets = offs;
+  c->fp64 = params[0].precision == DEM_PREC_FP64;
+  c->rsz = c->fp64 ? 8 : 4;
+  DevState& d = c->d;
+  memset(&d, 0, sizeof(d));
+  d.n = n;
+  d.nsamples = n_samples;
+  d.dt = params[0].dt;
+  d.couple_every = params[0].couple_every > 0 ? params[0].couple_every : 1;
+  c->sc.resize(n_samples);
+  int64_t bin_base = 0, cell_base = 0, dual_base = 0;
+  for (int s = 0; s < n_samples; ++s) {
+    SampleConst& k = c->sc[s];
+    derive(params[s], x.data(), r.data(), alive.data(), offs[s], offs[s + 1], k);
+    k.bin_base = bin_base;
+    bin_base += (int64_t)k.bn[0] * k.bn[1] * k.bn[2] + 1;
+    k.cell_base = cell_base;
+    k.dual_base = dual_base;
+    if (params[s].fluid_on) {
+      cell_base += (int64_t)k.gn[0] * k.gn[1] * k.gn[2];
+      c->any_fluid = 1;
+    }
+    dual_base += (int64_t)k.dn[0] * k.dn[1] * k.dn[2] + 1;
+    if (params[s].mu_roll > 0.0) d.rolling = 1;
+  }
+  d.nbins_total = bin_base;
+  d.ncell = cell_base;
+  d.ndual = dual_base;
+  if (bin_base > ((int64_t)1 << 31) - 2 || dual_base > ((int64_t)1 << 31) - 2) { delete c; return DEM_E_INVAL; }
+  c->dead_mass0.assign(n_samples, 0.0);
+  for (int s = 0; s < n_samples; ++s)
+    for (int64_t i = offs[s]; i < offs[s + 1]; ++i)
+      if (!alive[i]) c->dead_mass0[s] += params[s].rho * (4.0 / 3.0) * kPi * r[i] * r[i] * r[i];
+
+  auto fail = [&](dem_status st) { dem_destroy(c); return st; };
+  const int64_t R4B = 4 * (int64_t)c->rsz;
+  bool ok = true;
+  ok &= dalloc(c, &d.xr, n) == hipSuccess && dalloc(c, &d.vel, n) == hipSuccess;
+  ok &= dalloc(c, &d.xr2, n) == hipSuccess && dalloc(c, &d.vel2, n) == hipSuccess;
+  ok &= dalloc(c, &d.xref, n) == hipSuccess;
+  void** r4s[] = {&d.omg, &d.frc, &d.trq, &d.fdr, &d.omg2, &d.frc2, &d.trq2, &d.fdr2};
+  for (void** q : r4s) ok &= dalloc_bytes(c, q, n * R4B) == hipSuccess;
+  ok &= dalloc(c, &d.alive, n) == hipSuccess && dalloc(c, &d.alive2, n) == hipSuccess;
+  ok &= dalloc(c, &d.sample, n) == hipSuccess && dalloc(c, &d.sample2, n) == hipSuccess;
+  ok &= dalloc(c, &d.orig, n) == hipSuccess && dalloc(c, &d.orig2, n) == hipSuccess;
+  int64_t nbk = std::max<int64_t>(std::max<int64_t>(d.nbins_total, n), d.ndual) + 2;
+  ok &= dalloc(c, &d.key, n) == hipSuccess;
+  ok &= dalloc(c, &d.bucket_cnt, nbk) == hipSuccess && dalloc(c, &d.bucket_fill, nbk) == hipSuccess;
+  ok &= dalloc(c, &d.cell_start, nbk) == hipSuccess;
+  ok &= dalloc(c, &d.order, n) == hipSuccess && dalloc(c, &d.inv_order, n) == hipSuccess;
+  ok &= dalloc(c, &d.pcnt, n + 1) == hipSuccess && dalloc(c, &d.rcnt, n + 1) == hipSuccess;
+  ok &= dalloc(c, &d.rrow, n + 1) == hipSuccess && dalloc(c, &d.wcnt, n + 1) == hipSuccess;
+  for (int q = 0; q < 2; ++q) {
+    ok &= dalloc(c, &c->ps[q].prow, n + 1) == hipSuccess;
+    ok &= dalloc(c, &c->ws[q].wrow, n + 1) == hipSuccess;
+  }
+  if (!ok) return fail(DEM_E_NOMEM);
+  int64_t cap0 = params[0].pair_capacity > 0 ? params[0].pair_capacity : 4 * n + 1024;
+  for (int q = 0; q < 2; ++q) {
+    if (grow_pairs(c, c->ps[q], cap0) != hipSuccess) return fail(DEM_E_NOMEM);
+    if (grow_walls(c, c->ws[q], n / 4 + 256) != hipSuccess) return fail(DEM_E_NOMEM);
+  }
+  if (grow_records(c, cap0) != hipSuccess) return fail(DEM_E_NOMEM);
+  // fluid
+  int64_t nc = std::max<int64_t>(d.ncell, 1);
+  ok &= dalloc(c, &d.cell_sample, nc) == hipSuccess;
+  ok &= dalloc(c, &d.u_in, 3 * nc) == hipSuccess && dalloc(c, &d.gp_in, 3 * nc) == hipSuccess;
+  ok &= dalloc(c, &d.cell_n, nc) == hipSuccess && dalloc(c, &d.cell_u, 3 * nc) == hipSuccess;
+  ok &= dalloc(c, &d.eps, nc) == hipSuccess && dalloc(c, &d.fdc, 3 * nc) == hipSuccess;
+  ok &= dalloc(c, &d.dkey, n) == hipSuccess && dalloc(c, &d.dfr, n) == hipSuccess;
+  ok &= dalloc(c, &d.fpart, n) == hipSuccess && dalloc(c, &d.dmem, n) == hipSuccess;
+  ok &= dalloc(c, &d.dcnt, d.ndual + 2) == hipSuccess && dalloc(c, &d.doff, d.ndual + 2) == hipSuccess;
+  ok &= dalloc(c, &d.dfill, d.ndual + 2) == hipSuccess;
+  ok &= dalloc(c, &d.sc, n_samples) == hipSuccess;
+  ok &= dalloc(c, &d.broken, n_samples) == hipSuccess;
+  ok &= dalloc(c, &d.status, 1) == hipSuccess && dalloc(c, &d.rebuild_flag, 1) == hipSuccess;
+  ok &= dalloc(c, &d.scratch_i, 4) == hipSuccess;
+  int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nbk, n + 1), d.ndual + 2);
+  d.scan_tmp_n = scan_n / 256 + 4096;
+  ok &= dalloc(c, &d.scan_tmp, d.scan_tmp_n) == hipSuccess;
+  if (!ok) return fail(DEM_E_NOMEM);
+  if (hipHostMalloc((void**)&c->h_flag, sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(DEM_E_NOMEM);
+  if (dalloc(c, &c->d_offsets, n_samples + 1) != hipSuccess) return fail(DEM_E_NOMEM);
+
+  // upload in the caller's order
+  std::vector<double4> hx(n), hv(n);
+  std::vector<int32_t> hs(n), ho(n);
+  std::vector<char> hw(n * R4B), hF(n * R4B), hT(n * R4B);
+  for (int s = 0; s < n_samples; ++s) {
+    const dem_params& p = params[s];
+    for (int64_t i = offs[s]; i < offs[s + 1]; ++i) {
+      double m = p.rho * (4.0 / 3.0) * kPi * r[i] * r[i] * r[i];
+      double I = 0.4 * m * r[i] * r[i];
+      hx[i] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], r[i]);
+      hv[i] = make_double4(v[3 * i], v[3 * i + 1], v[3 * i + 2], 1.0 / m);
+      hs[i] = s;
+      ho[i] = (int32_t)i;
+      if (c->fp64) {
+        ((double4*)hw.data())[i] = make_double4(w[3 * i], w[3 * i + 1], w[3 * i + 2], 1.0 / I);
+        ((double4*)hF.data())[i] = make_double4(F[3 * i], F[3 * i + 1], F[3 * i + 2], 0.0);
+        ((double4*)hT.data())[i] = make_double4(T[3 * i], T[3 * i + 1], T[3 * i + 2], 0.0);
+      } else {
+        ((float4*)hw.data())[i] = make_float4((float)w[3 * i], (float)w[3 * i + 1], (float)w[3 * i + 2], (float)(1.0 / I));
+        ((float4*)hF.data())[i] = make_float4((float)F[3 * i], (float)F[3 * i + 1], (float)F[3 * i + 2], 0.f);
+        ((float4*)hT.data())[i] = make_float4((float)T[3 * i], (float)T[3 * i + 1], (float)T[3 * i + 2], 0.f);
+      }
+    }
+  }
+  std::vector<int32_t> cs(nc, 0);
+  for (int s = 0; s < n_samples; ++s)
+    if (params[s].fluid_on)
+      for (int64_t q = 0; q < (int64_t)c->sc[s].gn[0] * c->sc[s].gn[1] * c->sc[s].gn[2]; ++q)
+        cs[c->sc[s].cell_base + q] = s;
+  hipStream_t st = c->stream;
+  bool up = true;
+  up &= hipMemcpyAsync(d.xr, hx.data(), sizeof(double4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.vel, hv.data(), sizeof(double4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.omg, hw.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.frc, hF.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.trq, hT.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemsetAsync(d.fdr, 0, n * R4B, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.alive, alive.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.sample, hs.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.orig, ho.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.sc, c->sc.data(), sizeof(SampleConst) * n_samples, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.cell_sample, cs.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(c->d_offsets, offs.data(), sizeof(int64_t) * (n_samples + 1), hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemsetAsync(d.broken, 0, sizeof(unsigned long long) * n_samples, st) == hipSuccess;
+  up &= hipMemsetAsync(d.status, 0, sizeof(int), st) == hipSuccess;
+  up &= hipMemsetAsync(d.rebuild_flag, 0, sizeof(int), st) == hipSuccess;
+  up &= hipMemsetAsync(d.eps, 0, sizeof(double) * nc, st) == hipSuccess;
+  up &= hipMemsetAsync(d.fdc, 0, sizeof(double) * 3 * nc, st) == hipSuccess;
+  up &= hipMemsetAsync(d.u_in, 0, sizeof(double) * 3 * nc, st) == hipSuccess;
+  up &= hipMemsetAsync(d.gp_in, 0, sizeof(double) * 3 * nc, st) == hipSuccess;
+  // the "old" list of the first build: the given history, CSR over caller indices
+  PairSet& old = c->ps[1];
+  WallSet& wold = c->ws[1];
+  {
+    std::vector<int32_t> prow(n + 1, 0), pj;
+    std::vector<uint8_t> pfl;
+    std::vector<char> ph;
+    std::vector<std::pair<std::pair<int64_t, int64_t>, int64_t>> items;
+    for (int64_t k = 0; k < np0; ++k) {
+      int64_t a = hp[2 * k], b = hp[2 * k + 1];
+      items.push_back({{std::min(a, b), std::max(a, b)}, k});
+    }
+    std::sort(items.begin(), items.end());
+    if (grow_pairs(c, old, (int64_t)items.size()) != hipSuccess) return fail(DEM_E_NOMEM);
+    pj.resize(items.size());
+    pfl.resize(items.size());
+    ph.assign(items.size() * R4B, 0);
+    for (size_t q = 0; q < items.size(); ++q) {
+      int64_t a = items[q].first.first, b = items[q].first.second, k = items[q].second;
+      prow[a + 1]++;
+      pj[q] = (int32_t)b;
+      double sg = hp[2 * k] < hp[2 * k + 1] ? 1.0 : -1.0;
+      pfl[q] = hb.empty() ? 0 : (hb[k] ? 1 : 0);
+      if (params[0].normal_model != DEM_NORMAL_JKR_MOD) pfl[q] = 0;
+      double t[3] = {0, 0, 0};
+      if (!hdt.empty()) for (int e = 0; e < 3; ++e) t[e] = sg * hdt[3 * k + e];
+      if (c->fp64) ((double4*)ph.data())[q] = make_double4(t[0], t[1], t[2], 0.0);
+      else ((float4*)ph.data())[q] = make_float4((float)t[0], (float)t[1], (float)t[2], 0.f);
+    }
+    for (int64_t i = 0; i < n; ++i) prow[i + 1] += prow[i];
+    up &= hipMemcpyAsync(old.prow, prow.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st) == hipSuccess;
+    if (!items.empty()) {
+      up &= hipMemcpyAsync(old.pj, pj.data(), sizeof(int32_t) * pj.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(old.pfl, pfl.data(), pfl.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(old.hdt, ph.data(), ph.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    }
+    old.n = (int64_t)items.size();
+    up &= hipMemsetAsync(wold.wrow, 0, sizeof(int32_t) * (n + 1), st) == hipSuccess;
+    wold.n = 0;
+    up &= hipStreamSynchronize(st) == hipSuccess;
+  }
+  if (!up) return fail(DEM_E_DEVICE);
+  c->cur = 0;
+  bind_sets(c);
+  int mark = (np0 == 0 && params[0].bond_at_init) ? 1 : 0;
+  dem_status rs = c->fp64 ? rebuild<double>(c, 1, mark) : rebuild<float>(c, 1, mark);
+  if (rs != DEM_OK) return fail(rs);
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(DEM_E_DEVICE);
+  c->force_rebuild = 0;
+  *out = c;
+  return DEM_OK;
+}
+
+dem_status dem_step(dem_ctx* c, int64_t nsteps) {
+  if (!c || nsteps < 0) return DEM_E_INVAL;
+  if (c->failed) return DEM_E_STATE;
+  if (c->any_fluid && !c->have_fluid) return DEM_E_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  return c->fp64 ? step_impl<double>(c, nsteps) : step_impl<float>(c, nsteps);
+}
+
+dem_status dem_map_fluid(dem_ctx* c, const double* u_cell, const double* gradp_cell, double* eps_out,
+                         double* fdrag_out) {
+  if (!c) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  int64_t nc = c->d.ncell;
+  hipStream_t s = c->stream;
+  if (eps_out && nc > 0) HIPCHK(hipMemcpyAsync(eps_out, c->d.eps, sizeof(double) * nc, hipMemcpyDefault, s));
+  if (fdrag_out && nc > 0) HIPCHK(hipMemcpyAsync(fdrag_out, c->d.fdc, sizeof(double) * 3 * nc, hipMemcpyDefault, s));
+  if (u_cell && gradp_cell && nc > 0) {
+    HIPCHK(hipMemcpyAsync(c->d.u_in, u_cell, sizeof(double) * 3 * nc, hipMemcpyDefault, s));
+    HIPCHK(hipMemcpyAsync(c->d.gp_in, gradp_cell, sizeof(double) * 3 * nc, hipMemcpyDefault, s));
+    c->have_fluid = 1;
+  } else if (u_cell || gradp_cell) {
+    return DEM_E_INVAL;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return DEM_OK;
+}
+
+static dem_status aggregates(dem_ctx* c, std::vector<double>& pm, std::vector<double>& ke,
+                             std::vector<long long>& nc, std::vector<long long>& na, std::vector<unsigned long long>& br) {
+  int ns = c->d.nsamples;
+  double *dpm, *dke;
+  long long *dnc, *dna;
+  if (hipMalloc((void**)&dpm, sizeof(double) * ns * 2 + sizeof(long long) * ns * 2) != hipSuccess) return DEM_E_NOMEM;
+  dke = dpm + ns;
+  dnc = (long long*)(dke + ns);
+  dna = dnc + ns;
+  launch_aggregate_impl(c->d, c->d_offsets, dpm, dke, dnc, dna, c->fp64, c->stream);
+  pm.resize(ns); ke.resize(ns); nc.resize(ns); na.resize(ns); br.resize(ns);
+  bool ok = hipStreamSynchronize(c->stream) == hipSuccess;
+  ok &= hipMemcpy(pm.data(), dpm, sizeof(double) * ns, hipMemcpyDeviceToHost) == hipSuccess;
+  ok &= hipMemcpy(ke.data(), dke, sizeof(double) * ns, hipMemcpyDeviceToHost) == hipSuccess;
+  ok &= hipMemcpy(nc.data(), dnc, sizeof(long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
+  ok &= hipMemcpy(na.data(), dna, sizeof(long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
+  ok &= hipMemcpy(br.data(), c->d.broken, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
+  (void)hipFree(dpm);
+  for (int s = 0; s < ns; ++s) pm[s] -= c->dead_mass0[s];
+  return ok ? DEM_OK : DEM_E_DEVICE;
+}
+
+dem_status dem_read_state(dem_ctx* c, dem_state* out) {
+  if (!c || !out) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  const int64_t n = c->d.n;
+  if (!c->stage) {
+    if (hipMalloc((void**)&c->stage, sizeof(double) * 15 * std::max<int64_t>(n, 1)) != hipSuccess) return DEM_E_NOMEM;
+    if (hipMalloc((void**)&c->stage_alive, std::max<int64_t>(n, 1)) != hipSuccess) return DEM_E_NOMEM;
+  }
+  double* sx = c->stage;
+  double* sv = sx + 3 * n;
+  double* sw = sv + 3 * n;
+  double* sF = sw + 3 * n;
+  double* sT = sF + 3 * n;
+  if (c->fp64) launch_unpermute<double>(c->d, sx, sv, sw, sF, sT, c->stage_alive, c->stream);
+  else launch_unpermute<float>(c->d, sx, sv, sw, sF, sT, c->stage_alive, c->stream);
+  hipStream_t s = c->stream;
+  if (out->x) HIPCHK(hipMemcpyAsync(out->x, sx, sizeof(double) * 3 * n, hipMemcpyDefault, s));
+  if (out->v) HIPCHK(hipMemcpyAsync(out->v, sv, sizeof(double) * 3 * n, hipMemcpyDefault, s));
+  if (out->omega) HIPCHK(hipMemcpyAsync(out->omega, sw, sizeof(double) * 3 * n, hipMemcpyDefault, s));
+  if (out->force) HIPCHK(hipMemcpyAsync(out->force, sF, sizeof(double) * 3 * n, hipMemcpyDefault, s));
+  if (out->torque) HIPCHK(hipMemcpyAsync(out->torque, sT, sizeof(double) * 3 * n, hipMemcpyDefault, s));
+  if (out->alive) HIPCHK(hipMemcpyAsync(out->alive, c->stage_alive, n, hipMemcpyDefault, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> pm, ke;
+  std::vector<long long> nc, na;
+  std::vector<unsigned long long> br;
+  dem_status st = aggregates(c, pm, ke, nc, na, br);
+  if (st != DEM_OK) return st;
+  out->n = n;
+  out->produced_mass = 0; out->kinetic = 0; out->n_contacts = 0; out->n_alive = 0; out->broken_bonds = 0;
+  for (int q = 0; q < c->d.nsamples; ++q) {
+    out->produced_mass += pm[q];
+    out->kinetic += ke[q];
+    out->n_contacts += nc[q];
+    out->n_alive += na[q];
+    out->broken_bonds += (int64_t)br[q];
+  }
+  out->coordination = out->n_alive > 0 ? 2.0 * (double)out->n_contacts / (double)out->n_alive : 0.0;
+  out->step = c->step;
+  out->time = (double)c->step * c->d.dt;
+  if (c->failed) return (c->failed & kStNonFinite) ? DEM_E_NONFINITE : DEM_E_STATE;
+  return DEM_OK;
+}
+
+dem_status dem_read_aggregates(dem_ctx* c, double* produced_mass, double* coordination, int64_t* broken_bonds,
+                               int64_t* n_alive) {
+  if (!c) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  std::vector<double> pm, ke;
+  std::vector<long long> nc, na;
+  std::vector<unsigned long long> br;
+  dem_status st = aggregates(c, pm, ke, nc, na, br);
+  if (st != DEM_OK) return st;
+  for (int q = 0; q < c->d.nsamples; ++q) {
+    if (produced_mass) produced_mass[q] = pm[q];
+    if (coordination) coordination[q] = na[q] > 0 ? 2.0 * (double)nc[q] / (double)na[q] : 0.0;
+    if (broken_bonds) broken_bonds[q] = (int64_t)br[q];
+    if (n_alive) n_alive[q] = na[q];
+  }
+  return DEM_OK;
+}
+
+dem_status dem_read_pairs(dem_ctx* c, int32_t which, int64_t cap, int64_t* pair_idx, double* pair_dt,
+                          uint8_t* pair_bonded, int64_t* n_out) {
+  if (!c || which < 0 || which > 2 || cap < 0) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  DevState& d = c->d;
+  int64_t np = d.npairs;
+  std::vector<int32_t> own(np), pj(np), orig(d.n);
+  std::vector<uint8_t> fl(np);
+  std::vector<char> h(np * 4 * c->rsz);
+  std::vector<double4> xr(d.n);
+  if (np > 0) {
+    HIPCHK(hipMemcpy(own.data(), d.pown, sizeof(int32_t) * np, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(pj.data(), d.pj, sizeof(int32_t) * np, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(fl.data(), d.pfl, np, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(h.data(), d.hdt, h.size(), hipMemcpyDeviceToHost));
+  }
+  if (d.n > 0) {
+    HIPCHK(hipMemcpy(orig.data(), d.orig, sizeof(int32_t) * d.n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(xr.data(), d.xr, sizeof(double4) * d.n, hipMemcpyDeviceToHost));
+  }
+  std::vector<int64_t> oi;
+  std::vector<double> odt;
+  std::vector<uint8_t> ob;
+  for (int64_t p = 0; p < np; ++p) {
+    int32_t i = own[p], j = pj[p];
+    bool take;
+    if (which == 2) take = true;
+    else if (which == 0) take = (fl[p] & 3) != 0;
+    else {
+      double dx = xr[j].x - xr[i].x, dy = xr[j].y - xr[i].y, dz = xr[j].z - xr[i].z;
+      double d2 = (dx * dx + dy * dy) + dz * dz;
+      double cs = xr[i].w + xr[j].w;
+      take = d2 < cs * cs;
+    }
+    if (!take) continue;
+    int64_t a = orig[i], b = orig[j];
+    double sg = 1.0;
+    if (a > b) { std::swap(a, b); sg = -1.0; }
+    oi.push_back(a);
+    oi.push_back(b);
+    double t[3];
+    if (c->fp64) { double4 q = ((double4*)h.data())[p]; t[0] = q.x; t[1] = q.y; t[2] = q.z; }
+    else { float4 q = ((float4*)h.data())[p]; t[0] = q.x; t[1] = q.y; t[2] = q.z; }
+    for (int e = 0; e < 3; ++e) odt.push_back(sg * t[e]);
+    ob.push_back(fl[p] & 1);
+  }
+  int64_t cnt = (int64_t)ob.size();
+  if (n_out) *n_out = cnt;
+  int64_t w = std::min(cnt, cap);
+  if (w > 0) {
+    if (pair_idx) HIPCHK(hipMemcpy(pair_idx, oi.data(), sizeof(int64_t) * 2 * w, hipMemcpyDefault));
+    if (pair_dt) HIPCHK(hipMemcpy(pair_dt, odt.data(), sizeof(double) * 3 * w, hipMemcpyDefault));
+    if (pair_bonded) HIPCHK(hipMemcpy(pair_bonded, ob.data(), w, hipMemcpyDefault));
+  }
+  return DEM_OK;
+}
+
+dem_status dem_info(dem_ctx* c, int64_t* ncell, int64_t* n_pairs, int64_t* pair_capacity, int64_t* rebuilds,
+                    double* cutoff_margin) {
+  if (!c) return DEM_E_INVAL;
+  if (ncell) *ncell = c->d.ncell;
+  if (n_pairs) *n_pairs = c->d.npairs;
+  if (pair_capacity) *pair_capacity = c->d.pair_cap;
+  if (rebuilds) *rebuilds = c->rebuilds;
+  if (cutoff_margin) *cutoff_margin = c->sc[0].margin;
+  return DEM_OK;
+}
+
+dem_status dem_request_rebuild(dem_ctx* c) {
+  if (!c) return DEM_E_INVAL;
+  c->force_rebuild = 1;
+  return DEM_OK;
+}
+
+void dem_destroy(dem_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : c->allocs)
+    if (p) (void)hipFree(p);
+  if (c->stage) (void)hipFree(c->stage);
+  if (c->stage_alive) (void)hipFree(c->stage_alive);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+"""Seeded synthetic inputs for the DEM + coupling workloads.
+
+This module is shared by the oracle side and the GPU side and holds none of the
+method's arithmetic: particle size samples, geometric packings (pure placement,
+see packing.c), prescribed fluid fields, and the workload definitions.
+
+The paper's own workload (a laboratory sand sample from a Kazakhstan reservoir,
+its PSD in Table 2, Aspherix runs) is not available; these synthetic inputs stand
+in for it.  Sizes, PSD, materials and geometry follow the workload list:
+
+  c0  2 000 spheres, walled 3 mm box, 8^3 fluid grid, uniform upflow, FP64
+  c1  200 000 spheres, hollow cylinder R 12 mm / cavity 2 mm / H 6 mm,
+      48x48x24 grid, radial Darcy inflow to the cavity, mixed precision
+  c2  c1 coarse-grained at k = 2, 3 (SSW and SSP)
+  c3  256 boxes, N ~ U{500..20000}, surface energy swept 0.1-1.0 J/m^2
+  c4  2 000 000-particle fine-equivalent cylinder at k = 3 (74 074 parcels)
+"""
+import ctypes
+import hashlib
+import math
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsynth.so")
+CACHE = os.path.join(HERE, "_cache")
+SEED0 = 2211061420
+
+# lognormal PSD of the diameters: median 0.15 mm, sigma 0.3, truncated 0.05-0.5 mm
+PSD = dict(median=0.15e-3, sigma=0.3, dmin=0.05e-3, dmax=0.5e-3)
+
+MATERIAL = dict(rho=2650.0, E=70e6, nu=0.3, e=0.5, mu=0.5, mu_roll=0.0, gamma=0.5)
+WATER = dict(rho_f=998.2, mu_f=1.0e-3)          # Table 4
+DT = 1.0e-7
+COUPLE_EVERY = 10                                 # CFD step 1e-6 s (section 3.1) / DEM 1e-7 s
+N_MIN = 0.3
+GRAV = (0.0, 0.0, -9.81)
+
+WALL_PLANE, WALL_CYL_IN, WALL_CYL_OUT = 0, 1, 2
+
+
+def build(force=True):
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp,
+                           os.path.join(HERE, "packing.c"), "-lm"])
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.settle_packing.restype = ctypes.c_double
+        L.settle_packing.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# particle sizes
+# ---------------------------------------------------------------------------
+def sample_diameters(rng, n, psd=PSD):
+    """Lognormal diameters truncated to [dmin, dmax] by resampling."""
+    out = np.empty(0)
+    mu = math.log(psd["median"])
+    while out.size < n:
+        d = np.exp(rng.normal(mu, psd["sigma"], size=max(2 * (n - out.size), 16)))
+        d = d[(d >= psd["dmin"]) & (d <= psd["dmax"])]
+        out = np.concatenate([out, d])
+    return out[:n].copy()
+
+
+# ---------------------------------------------------------------------------
+# packings
+# ---------------------------------------------------------------------------
+def settle(r, region_kind, region, rng, phi_start=0.25, shrink=0.998, iters=2000,
+           settle_iters=600, relax=1.0):
+    """Random start in a dilute column, then geometric settling (packing.c).
+    region_kind 0: box (x0,y0,z0,x1,y1,z1); 1: annulus (cx,cy,r_in,r_out,z0,z1)."""
+    n = r.size
+    vs = float(np.sum(4.0 / 3.0 * math.pi * r ** 3))
+    if region_kind == 0:
+        x0, y0, z0, x1, y1, z1 = region
+        area = (x1 - x0) * (y1 - y0)
+    else:
+        cx, cy, rin, rout, z0, z1 = region
+        area = math.pi * (rout ** 2 - rin ** 2)
+    h_start = vs / (phi_start * area)
+    h_bed = vs / (0.6 * area)
+    x = np.empty((n, 3))
+    if region_kind == 0:
+        x[:, 0] = rng.uniform(x0 + r, x1 - r)
+        x[:, 1] = rng.uniform(y0 + r, y1 - r)
+    else:
+        # uniform in the annulus by area
+        u = rng.uniform(0.0, 1.0, n)
+        rho = np.sqrt(rin ** 2 + u * (rout ** 2 - rin ** 2))
+        th = rng.uniform(0.0, 2.0 * math.pi, n)
+        rho = np.clip(rho, rin + r, rout - r)
+        x[:, 0] = cx + rho * np.cos(th)
+        x[:, 1] = cy + rho * np.sin(th)
+    x[:, 2] = z0 + r + rng.uniform(0.0, 1.0, n) * h_start
+    drop = 2.0 * (h_start - h_bed) / settle_iters
+    prm = np.ascontiguousarray(region, dtype=np.float64)
+    x = np.ascontiguousarray(x)
+    rr = np.ascontiguousarray(r, dtype=np.float64)
+    worst = _L().settle_packing(n, x.ctypes.data_as(ctypes.c_void_p), rr.ctypes.data_as(ctypes.c_void_p),
+                                region_kind, prm.ctypes.data_as(ctypes.c_void_p), shrink, iters,
+                                settle_iters, drop, relax)
+    return x, worst
+
+
+def _cache_path(name):
+    os.makedirs(CACHE, exist_ok=True)
+    return os.path.join(CACHE, name + ".npz")
+
+
+def digest(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def cached(name, fn):
+    path = _cache_path(name)
+    if os.path.exists(path):
+        z = np.load(path)
+        d = {k: z[k] for k in z.files}
+        if "sha256" in d and digest(d["x"], d["r"]) == str(d["sha256"]):
+            return d
+    d = fn()
+    d["sha256"] = np.array(digest(d["x"], d["r"]))
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **d)
+    os.replace(tmp, path)
+    return d
+
+
+# ---------------------------------------------------------------------------
+# fluid fields (prescribed: the CFD solve lies outside the DEM step)
+# ---------------------------------------------------------------------------
+def grid_centres(grid):
+    lo, hi, nn = grid
+    axes = [lo[c] + (np.arange(nn[c]) + 0.5) * (hi[c] - lo[c]) / nn[c] for c in range(3)]
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)   # x fastest
+
+
+def uniform_field(grid, U):
+    nc = grid[2][0] * grid[2][1] * grid[2][2]
+    u = np.tile(np.asarray(U, dtype=np.float64), (nc, 1))
+    gp = np.zeros((nc, 3))
+    return u, gp
+
+
+def radial_darcy_field(grid, r_cav, r_out, U_cav, mu_f, kappa):
+    """Steady radial inflow to the cavity: superficial U(rho) = U_cav r_cav / rho
+    inward and p(rho) = p_cav + dp ln(rho/r_cav)/ln(R/r_cav) with
+    dp = U_cav mu_f r_cav ln(R/r_cav) / kappa (Darcy)."""
+    c = grid_centres(grid)
+    rho = np.hypot(c[:, 0], c[:, 1])
+    lnr = math.log(r_out / r_cav)
+    dp = U_cav * mu_f * r_cav * lnr / kappa
+    er = np.zeros((rho.size, 3))
+    nz = rho > 0
+    er[nz, 0] = c[nz, 0] / rho[nz]
+    er[nz, 1] = c[nz, 1] / rho[nz]
+    mag = np.where(rho >= r_cav, U_cav * r_cav / np.maximum(rho, 1e-30), U_cav * rho / r_cav)
+    u = -mag[:, None] * er
+    dpdr = np.where(rho >= r_cav, dp / (np.maximum(rho, 1e-30) * lnr), 0.0)
+    gp = dpdr[:, None] * er
+    return u, gp
+
+
+def kozeny_carman(d, n):
+    return d * d * n ** 3 / (180.0 * (1.0 - n) ** 2)
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+def box_walls(lo, hi):
+    return [(WALL_PLANE, (1.0, 0.0, 0.0, lo[0])), (WALL_PLANE, (-1.0, 0.0, 0.0, -hi[0])),
+            (WALL_PLANE, (0.0, 1.0, 0.0, lo[1])), (WALL_PLANE, (0.0, -1.0, 0.0, -hi[1])),
+            (WALL_PLANE, (0.0, 0.0, 1.0, lo[2])), (WALL_PLANE, (0.0, 0.0, -1.0, -hi[2]))]
+
+
+def box_workload(n, side, seed, gamma=0.5, grid_n=8, name=None, U=0.05):
+    """A walled cube of the given side with n settled spheres and a uniform
+    upward superficial flow."""
+    rng = np.random.default_rng(seed)
+    name = name or "box_n%d_s%d" % (n, seed)
+
+    def make():
+        d = sample_diameters(rng, n)
+        r = 0.5 * d
+        x, worst = settle(r, 0, (0.0, 0.0, 0.0, side, side, side), rng)
+        return {"x": x, "r": r, "worst": np.array(worst)}
+
+    pk = cached(name, make)
+    lo, hi = (0.0, 0.0, 0.0), (side, side, side)
+    grid = (lo, hi, (grid_n, grid_n, grid_n))
+    u, gp = uniform_field(grid, (0.0, 0.0, U))
+    mat = dict(MATERIAL)
+    mat["gamma"] = gamma
+    return dict(name=name, x=pk["x"], r=pk["r"], material=mat, k=1.0, scheme="ssw",
+                walls=box_walls(lo, hi), grid=grid, u_cell=u, gradp_cell=gp,
+                fluid=dict(WATER, n_min=N_MIN, voidfrac=0, u_superficial=1, couple_every=COUPLE_EVERY),
+                outlet=None, dt=DT, g=GRAV, sha256=str(pk["sha256"]))
+
+
+def c0():
+    """2 000 spheres in a walled 3x3x3 mm box, FP64, 1 000 steps."""
+    w = box_workload(2000, 3.0e-3, SEED0 + 0, name="c0")
+    w.update(precision="fp64", steps=1000, n_fine=2000)
+    return w
+
+
+def cylinder_workload(n, seed, name, k=1.0, scheme="ssw", R=12e-3, r_cav=2e-3, H=6e-3,
+                      grid_n=(48, 48, 24), U_cav=0.5, psd_sample_n=None):
+    """Hollow cylinder (axis z), outer Hertz wall, floor and a top plate on the
+    settled bed; the cavity r < r_cav is the outlet.  k > 1: grains, SSW (each
+    sampled fine diameter times k) or SSP (one diameter, k times the mass-mean
+    diameter of a fine sample)."""
+    rng = np.random.default_rng(seed)
+
+    def make():
+        if scheme == "ssp" and k > 1.0:
+            dref = sample_diameters(rng, psd_sample_n or 200000)
+            dbar = float(np.cbrt(np.mean(dref ** 3)))
+            d = np.full(n, k * dbar)
+        else:
+            d = k * sample_diameters(rng, n)
+        r = 0.5 * d
+        x, worst = settle(r, 1, (0.0, 0.0, r_cav, R, 0.0, H), rng)
+        return {"x": x, "r": r, "worst": np.array(worst)}
+
+    pk = cached(name, make)
+    x, r = pk["x"], pk["r"]
+    top = float(np.max(x[:, 2] + r))
+    walls = [(WALL_CYL_IN, (0.0, 0.0, R)), (WALL_PLANE, (0.0, 0.0, 1.0, 0.0)),
+             (WALL_PLANE, (0.0, 0.0, -1.0, -top))]
+    grid = ((-R, -R, 0.0), (R, R, H), grid_n)
+    kappa = kozeny_carman(PSD["median"] * math.exp(0.5 * PSD["sigma"] ** 2), 0.41)
+    u, gp = radial_darcy_field(grid, r_cav, R, U_cav, WATER["mu_f"], kappa)
+    return dict(name=name, x=x, r=r, material=dict(MATERIAL), k=k, scheme=scheme, walls=walls,
+                grid=grid, u_cell=u, gradp_cell=gp,
+                fluid=dict(WATER, n_min=N_MIN, voidfrac=0, u_superficial=1, couple_every=COUPLE_EVERY),
+                outlet=(0.0, 0.0, r_cav), dt=DT, g=GRAV, sha256=str(pk["sha256"]), bed_top=top)
+
+
+def c1(n=200000):
+    w = cylinder_workload(n, SEED0 + 1, "c1" if n == 200000 else "c1_n%d" % n)
+    w.update(precision="mixed", steps=5000, n_fine=n)
+    return w
+
+
+def c2(k=2, scheme="ssw", n_fine=200000):
+    n = int(round(n_fine / k ** 3))
+    w = cylinder_workload(n, SEED0 + 2 + 10 * int(k) + (1 if scheme == "ssp" else 0),
+                          "c2_k%d_%s_n%d" % (k, scheme, n_fine), k=float(k), scheme=scheme)
+    w.update(precision="mixed", steps=5000, n_fine=n_fine)
+    return w
+
+
+def c3_sizes(n_samples=256, seed=SEED0 + 3):
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(500, 20001, size=n_samples)
+    gam = 0.1 + 0.9 * np.arange(n_samples) / max(n_samples - 1, 1)
+    return ns, gam
+
+
+def c3_sample(s, n_s, gamma):
+    side = 3.0e-3 * (n_s / 2000.0) ** (1.0 / 3.0)
+    gn = int(min(16, max(8, round(8 * (n_s / 2000.0) ** (1.0 / 3.0)))))
+    w = box_workload(int(n_s), side, SEED0 + 1000 + s, gamma=gamma, grid_n=gn,
+                     name="c3_s%d_n%d" % (s, n_s))
+    w.update(precision="mixed", steps=2000, n_fine=int(n_s))
+    return w

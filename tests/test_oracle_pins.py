@@ -1,0 +1,547 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it pins.  None of these re-calls the oracle's own
+formula to check itself: they use closed forms of Table 1, textbook limits,
+conservation laws, exact self-similarity, brute force, or numbers the paper
+prints (tests/golden/).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize
+
+import oracle
+from oracle import cg
+from synth import scenes
+from tests.conftest import read_golden
+
+E, NU, GAM, RHO = 70e6, 0.3, 0.5, 2650.0
+ES, GS = oracle.effective_moduli(E, NU)
+RS = 3.75e-5
+
+
+def X_of(Rs=RS, Es=ES, g=GAM):
+    return (math.pi ** 2 * g * g * Rs / Es ** 2) ** (1.0 / 3.0)
+
+
+# ---------------------------------------------------------------------------
+# section 2.3, Table 1: characteristic points of the JKR curve
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("Rs,g", [(RS, GAM), (1e-4, 0.1), (2.5e-5, 2.0)])
+def test_table1_closed_forms(Rs, g):
+    X = X_of(Rs, ES, g)
+    pts = {
+        # overlap, contact radius, force (Table 1 closed forms with exact constants)
+        "C": (-(3.0 / 16.0) ** (1 / 3) * X, (9 * math.pi * g * Rs ** 2 / (4 * ES)) ** (1 / 3), -3.0),
+        "A": (0.0, (4 * math.pi * g * Rs ** 2 / ES) ** (1 / 3), -8.0 / 3.0),
+        "B": (3.0 ** (1 / 3) * X, (9 * math.pi * g * Rs ** 2 / ES) ** (1 / 3), 0.0),
+    }
+    unit = math.pi * g * Rs
+    for name, (d, a_ref, f_ref) in pts.items():
+        a = oracle.jkr_a_of_delta(d, Rs, ES, g)
+        assert a == pytest.approx(a_ref, rel=1e-13), name
+        F = oracle.jkr_force_of_a(a, Rs, ES, g)
+        assert abs(F / unit - f_ref) < 1e-12, name
+
+
+def test_table1_printed_coefficients():
+    """Round the oracle's curve at C, A, B to the digits Table 1 prints."""
+    X = X_of()
+    unit = math.pi * GAM * RS
+    for name, fc, oc, rc, digits in read_golden("table1_jkr_points.txt"):
+        fc, oc, rc, digits = float(fc), float(oc), float(rc), int(digits)
+        a = (rc * math.pi * GAM * RS ** 2 / ES) ** (1 / 3)
+        assert round(oracle.jkr_force_of_a(a, RS, ES, GAM) / unit, digits) == pytest.approx(fc)
+        assert round(oracle.jkr_delta_of_a(a, RS, ES, GAM) / X, digits) == pytest.approx(oc)
+
+
+def test_jkr_reduces_to_hertz():
+    """gamma = 0: eq 12-13 become Hertz, F = 4/3 E* sqrt(R*) delta^(3/2)."""
+    for d in [1e-9, 3e-7, 2e-6]:
+        a = oracle.jkr_a_of_delta(d, RS, ES, 0.0)
+        F = oracle.jkr_force_of_a(a, RS, ES, 0.0)
+        assert F == pytest.approx(4.0 / 3.0 * ES * math.sqrt(RS) * d ** 1.5, rel=1e-13)
+
+
+def test_peeling_work_eq26():
+    """eq 25-26: W_CA = 11.12 (gamma^5 R*^4 / E*^2)^(1/3), integrating the
+    oracle's force-overlap curve from A down to C."""
+    X = X_of()
+    dC = -(3.0 / 16.0) ** (1 / 3) * X
+
+    def F(d):
+        return oracle.jkr_force_of_a(oracle.jkr_a_of_delta(d, RS, ES, GAM), RS, ES, GAM)
+
+    W, _ = integrate.quad(F, 0.0, dC, epsabs=0, epsrel=1e-12, limit=200)
+    unit = (GAM ** 5 * RS ** 4 / ES ** 2) ** (1 / 3)
+    coef = float(read_golden("eq26_peeling.txt")[0][1])
+    assert W / unit == pytest.approx(coef, rel=5e-4)
+    # The paper's second form "0.965 F_C delta_C" is not consistent with its
+    # first: the exact ratio is 0.961 (recorded as a reading of eq 26).
+    ratio = W / (3 * math.pi * GAM * RS * abs(dC))
+    assert ratio == pytest.approx(0.9610, abs=2e-4)
+    # eq 27: W scales k^3 under gamma -> k gamma, R* -> k R*, same E*
+    k = 3.0
+    W3, _ = integrate.quad(lambda d: oracle.jkr_force_of_a(oracle.jkr_a_of_delta(d, k * RS, ES, k * GAM),
+                                                           k * RS, ES, k * GAM),
+                           0.0, k * dC, epsabs=0, epsrel=1e-12, limit=200)
+    assert W3 == pytest.approx(k ** 3 * W, rel=1e-9)
+
+
+def test_bond_break_threshold_point_C():
+    """Fig. 2: a bond holds down to the pull-off overlap of point C and breaks below it."""
+    X = X_of()
+    dC = -(3.0 / 16.0) ** (1 / 3) * X
+    r1 = r2 = 2 * RS
+    c = r1 + r2
+    for frac, holds in [(0.999999, True), (1.000001, False), (0.0, True), (-1.0, True), (3.0, False)]:
+        dist = c - frac * dC
+        assert oracle.bond_holds(dist * dist, c, RS, ES, GAM) == holds, frac
+
+
+def test_beta_eq33():
+    """eq 33 with the square restored: beta(0.5) = 0.2155; beta(1) = 0."""
+    assert oracle.beta_of_e(0.5) == pytest.approx(0.2155, abs=1e-4)
+    assert oracle.beta_of_e(1.0) == 0.0
+    for e in [0.1, 0.5, 0.9]:
+        b = oracle.beta_of_e(e)
+        # damped-oscillator identity: exp(-pi beta / sqrt(1 - beta^2)) = e
+        assert math.exp(-math.pi * b / math.sqrt(1 - b * b)) == pytest.approx(e, rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# section 2.2: Di Felice drag
+# ---------------------------------------------------------------------------
+def test_drag_limits():
+    rho_f, mu_f = 998.2, 1e-3
+    d = 1.5e-4
+    # chi at Re = 10^1.5 is 3.7 - 0.65 = 3.05 (eq 10)
+    s_mag = 10 ** 1.5 * mu_f / (rho_f * d)
+    n = 0.5
+    f = oracle.drag([s_mag, 0, 0], d, 1.0, n, rho_f, mu_f)
+    Cd = (0.63 + 4.8 / 10 ** 0.75) ** 2
+    base = 0.125 * Cd * rho_f * math.pi * d * d * s_mag * s_mag
+    assert f[0] / base == pytest.approx(n ** -3.05, rel=1e-12)
+    # Re -> 0: f -> 2.88 pi mu_f d s n^-3.7 (0.96 x Stokes)
+    s = 1e-9
+    f = oracle.drag([0, 0, s], d, 1.0, n, rho_f, mu_f)
+    assert f[2] == pytest.approx(2.88 * math.pi * mu_f * d * s * n ** -3.7, rel=2e-3)
+    # Re -> infinity: Cd -> 0.63^2, chi -> 3.7
+    s = 1e9
+    f = oracle.drag([0, s, 0], d, 1.0, n, rho_f, mu_f)
+    assert f[1] / (0.125 * rho_f * math.pi * d * d * s * s * n ** -3.7) == pytest.approx(0.3969, rel=1e-3)
+    # zero slip: zero force (no log of zero)
+    assert np.all(oracle.drag([0, 0, 0], d, 1.0, n, rho_f, mu_f) == 0.0)
+    # coarse-grained rule: k^3 times the drag on diameter d/k
+    k = 3.0
+    f1 = oracle.drag([0.01, 0.02, -0.03], d / k, 1.0, n, rho_f, mu_f)
+    fk = oracle.drag([0.01, 0.02, -0.03], d, k, n, rho_f, mu_f)
+    np.testing.assert_allclose(fk, k ** 3 * f1, rtol=1e-14)
+
+
+def _params(mat, dt, **kw):
+    return oracle.make_params(mat, dt, **kw)
+
+
+def test_terminal_velocity_single_sphere():
+    """A sphere settling in still water reaches the velocity at which drag balances
+    its submerged weight (eq 1 with eq 8-11, n ~ 1)."""
+    r = 1e-4
+    mat = scenes.material(gamma=0.0)
+    grid = ((-0.05, -0.05, -0.05), (0.05, 0.05, 0.05), (1, 1, 1))
+    fluid = dict(rho_f=998.2, mu_f=1e-3, n_min=0.3, voidfrac=0, u_superficial=0, couple_every=1)
+    p = _params(mat, 2e-6, grid=grid, fluid=fluid, normal_model=oracle.NORMAL_HERTZ)
+    sim = oracle.OracleSim(p, np.zeros((1, 3)), np.array([r]), bond_at_init=False)
+    sim.set_fluid(np.zeros(3), np.zeros(3))
+    sim.step(60000)
+    vz = sim.state()["v"][0, 2]
+    V = 4 / 3 * math.pi * r ** 3
+    n = 1.0 - V / 0.1 ** 3
+    W = (RHO - 998.2) * V * 9.81
+
+    def bal(v):
+        Re = 998.2 * 2 * r * v / 1e-3
+        Cd = (0.63 + 4.8 / math.sqrt(Re)) ** 2
+        chi = 3.7 - 0.65 * math.exp(-(1.5 - math.log10(Re)) ** 2 / 2)
+        return 0.125 * Cd * 998.2 * math.pi * (2 * r) ** 2 * v * v * n ** -chi - W
+
+    vt = optimize.brentq(bal, 1e-6, 10.0, xtol=1e-15)
+    assert -vz == pytest.approx(vt, rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# contact sets: brute force is the definition
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_grid_equals_brute(seed):
+    rng = np.random.default_rng(seed)
+    n = 700
+    x = rng.uniform(0, 2e-3, (n, 3))
+    r = rng.uniform(2e-5, 1.2e-4, n)
+    alive = (rng.uniform(size=n) > 0.05).astype(np.uint8)
+    for extra in [0.0, 3e-6, 5e-5]:
+        a = oracle.pairs(x, r, alive, extra, method="brute")
+        b = oracle.pairs(x, r, alive, extra, method="grid")
+        assert len(a) > 0
+        np.testing.assert_array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# damping and restitution (eq 3, eq 31-34)
+# ---------------------------------------------------------------------------
+def collide(mat, model, speed, dt, r1=7.5e-5, r2=7.5e-5, k_lin=0.0, axis=(1, 0, 0), max_steps=200000):
+    x, r, v = scenes.two_spheres(r1, r2, 1e-9, speed, axis=axis)
+    p = _params(mat, dt, g=(0, 0, 0), normal_model=model, k_lin=k_lin)
+    sim = oracle.OracleSim(p, x, r, v=v, bond_at_init=False)
+    touched = False
+    for _ in range(max_steps // 100):
+        sim.step(100)
+        st = sim.state()
+        d = np.linalg.norm(st["x"][1] - st["x"][0])
+        if d < r1 + r2:
+            touched = True
+        elif touched:
+            break
+    ax = np.asarray(axis, float) / np.linalg.norm(axis)
+    rel = (st["v"][0] - st["v"][1]) @ ax
+    return -rel / speed, sim
+
+
+def test_cor_linear_law_equals_e():
+    """eq 3 with eta = 2 beta sqrt(k m*): the restitution coefficient equals e."""
+    for e in [0.3, 0.5, 0.8]:
+        cor, _ = collide(scenes.material(e=e, mu=0.0), oracle.NORMAL_LINEAR, 0.1, 2e-9, k_lin=500.0)
+        assert cor == pytest.approx(e, abs=2e-3)
+
+
+def test_cor_hertz_velocity_independent():
+    """Hertz with the eq 32 damping: the COR does not depend on impact speed."""
+    cors = [collide(scenes.material(e=0.5, mu=0.0), oracle.NORMAL_HERTZ, s, 2e-9)[0] for s in (0.02, 0.2, 2.0)]
+    assert max(cors) - min(cors) < 2e-5
+    assert 0.4 < cors[0] < 0.7
+
+
+def test_cor_elastic_is_one():
+    cor, _ = collide(scenes.material(e=1.0, mu=0.0), oracle.NORMAL_HERTZ, 0.2, 2e-9)
+    assert cor == pytest.approx(1.0, abs=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# integrator and invariants
+# ---------------------------------------------------------------------------
+def test_free_fall_exact():
+    """Velocity Verlet integrates a constant force exactly."""
+    g = (0.3, -1.0, -9.81)
+    r = np.array([1e-4])
+    m = RHO * 4 / 3 * math.pi * r[0] ** 3
+    x0 = np.array([[0.1, 0.2, 0.3]])
+    v0 = np.array([[0.01, 0.02, 0.5]])
+    p = _params(scenes.material(), 1e-5, g=g)
+    sim = oracle.OracleSim(p, x0, r, v=v0, F=m * np.array([g]), bond_at_init=False)
+    sim.step(1000)
+    t = 1000 * 1e-5
+    st = sim.state()
+    np.testing.assert_allclose(st["x"][0], x0[0] + v0[0] * t + 0.5 * np.array(g) * t * t, rtol=1e-12)
+    np.testing.assert_allclose(st["v"][0], v0[0] + np.array(g) * t, rtol=1e-12)
+
+
+def _gas(seed=3, n=150):
+    rng = np.random.default_rng(seed)
+    x, r, v = scenes.random_gas(rng, n, 1.2e-3, 4e-5, 8e-5, 0.5)
+    return x, r, v
+
+
+def test_momentum_conserved():
+    """Pair forces are equal and opposite (eq 1): total momentum of a colliding
+    gas with friction and damping is conserved to round-off."""
+    x, r, v = _gas()
+    m = RHO * 4 / 3 * math.pi * r ** 3
+    mat = scenes.material(e=0.5, mu=0.3, gamma=0.0)
+    p = _params(mat, 2e-8, g=(0, 0, 0), normal_model=oracle.NORMAL_HERTZ)
+    sim = oracle.OracleSim(p, x, r, v=v, bond_at_init=False)
+    P0 = (m[:, None] * v).sum(0)
+    sim.step(20000)
+    st = sim.state()
+    assert not np.allclose(st["v"], v)
+    P = (m[:, None] * st["v"]).sum(0)
+    np.testing.assert_allclose(P, P0, rtol=0, atol=1e-13 * np.abs(m[:, None] * v).sum())
+
+
+def _jkr_potential(delta, Rs, g):
+    """W(delta) = integral of eq 12 over eq 13 from point B, in closed form of
+    the contact radius (F dDelta = F(a) (2a/R* - sqrt(pi gamma/(E* a))) da)."""
+    aB = (9 * math.pi * g * Rs ** 2 / ES) ** (1 / 3)
+
+    def lo_a(d):
+        return optimize.brentq(lambda a: a * a / Rs - math.sqrt(4 * math.pi * g * a / ES) - d,
+                               (math.pi * g * Rs ** 2 / (4 * ES)) ** (1 / 3), 10 * aB, xtol=1e-22, rtol=1e-15)
+
+    def integrand(a):
+        F = 4 * ES * a ** 3 / (3 * Rs) - math.sqrt(16 * math.pi * g * ES * a ** 3)
+        return F * (2 * a / Rs - math.sqrt(math.pi * g / (ES * a)))
+
+    val, _ = integrate.quad(integrand, aB, lo_a(delta), epsabs=0, epsrel=1e-13)
+    return val
+
+
+def test_energy_second_order_bonded_oscillator():
+    """Velocity Verlet: for a smooth conservative force (an undamped bonded
+    JKR pair oscillating about point B) the energy error is O(dt^2)."""
+    r = 7.5e-5
+    Rs = r / 2
+    X = X_of(Rs, ES, GAM)
+    mat = scenes.material(e=1.0, mu=0.0)
+    m = RHO * 4 / 3 * math.pi * r ** 3
+    errs = []
+    for dt in (4e-8, 2e-8):
+        x, rr, v = scenes.two_spheres(r, r, -3.0 * X, 0.0)
+        p = _params(mat, dt, g=(0, 0, 0))
+        sim = oracle.OracleSim(p, x, rr, v=v, pairs=np.array([[0, 1]]), pair_bonded=np.array([1]),
+                               bond_at_init=False)
+        E0 = _jkr_potential(3.0 * X, Rs, GAM)
+        worst = 0.0
+        nsteps = int(round(2e-5 / dt))
+        for _ in range(40):
+            sim.step(nsteps // 40)
+            st = sim.state()
+            d = 2 * r - np.linalg.norm(st["x"][1] - st["x"][0])
+            ke = 0.5 * m * np.sum(st["v"] ** 2)
+            worst = max(worst, abs(ke + _jkr_potential(d, Rs, GAM) - E0))
+        assert sim.scalars()["broken_bonds"] == 0
+        errs.append(worst / E0)
+    assert errs[0] < 1e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+@pytest.mark.parametrize("theta,rolls", [(math.radians(20), True), (math.radians(70), False)])
+def test_sphere_on_incline(theta, rolls):
+    """Tangential spring, Coulomb cap and eq 5 torque: a sphere on a slope rolls
+    without slip (a = 5/7 g sin) when tan(theta) <= 3.5 mu, else slides
+    (a = g (sin - mu cos))."""
+    r = 1e-4
+    mu = 0.5
+    mat = scenes.material(mu=mu, gamma=0.0)
+    g = scenes.incline_gravity(theta)
+    m = RHO * 4 / 3 * math.pi * r ** 3
+    d0 = (m * 9.81 * math.cos(theta) / (4 / 3 * (2 * ES) * math.sqrt(r))) ** (2 / 3)
+    p = _params(mat, 1e-7, g=g, walls=[scenes.plane((0, 0, 1), 0.0)], normal_model=oracle.NORMAL_HERTZ)
+    sim = oracle.OracleSim(p, np.array([[0, 0, r - d0]]), np.array([r]), bond_at_init=False)
+    sim.step(5000)
+    t, vx = [], []
+    for k in range(20):
+        sim.step(1000)
+        t.append(k * 1000 * 1e-7)
+        vx.append(sim.state()["v"][0, 0])
+    a = np.polyfit(t, vx, 1)[0]
+    expect = 5 / 7 * 9.81 * math.sin(theta) if rolls else 9.81 * (math.sin(theta) - mu * math.cos(theta))
+    assert a == pytest.approx(expect, rel=3e-3)
+
+
+def test_rolling_resistance_deceleration():
+    """Constant directional rolling torque: a rolling sphere slows at 5/7 mu_r g."""
+    r = 1e-4
+    mur = 0.05
+    mat = scenes.material(mu=0.5, gamma=0.0, mu_roll=mur)
+    m = RHO * 4 / 3 * math.pi * r ** 3
+    d0 = (m * 9.81 / (4 / 3 * (2 * ES) * math.sqrt(r))) ** (2 / 3)
+    p = _params(mat, 1e-7, g=(0, 0, -9.81), walls=[scenes.plane((0, 0, 1), 0.0)], normal_model=oracle.NORMAL_HERTZ)
+    v0 = 0.02
+    sim = oracle.OracleSim(p, np.array([[0, 0, r - d0]]), np.array([r]), v=np.array([[v0, 0, 0]]),
+                           w=np.array([[0, v0 / r, 0]]), bond_at_init=False)
+    sim.step(3000)
+    t, vx = [], []
+    for k in range(20):
+        sim.step(1000)
+        t.append(k * 1e-4)
+        vx.append(sim.state()["v"][0, 0])
+    a = np.polyfit(t, vx, 1)[0]
+    assert -a == pytest.approx(5 / 7 * mur * 9.81, rel=2e-2)
+
+
+# ---------------------------------------------------------------------------
+# bonded contact state machine (Fig. 2)
+# ---------------------------------------------------------------------------
+def test_pull_off_break_and_no_rebond():
+    r = 7.5e-5
+    Rs = r / 2
+    X = X_of(Rs, ES, GAM)
+    dC = -(3.0 / 16.0) ** (1 / 3) * X
+    mat = scenes.material(e=1.0, mu=0.0, rho=1e9)
+    dt = 1e-7
+    vpull = 2e-3
+    x, rr, v = scenes.two_spheres(r, r, -0.5 * X, -vpull)        # overlapping, separating
+    p = _params(mat, dt, g=(0, 0, 0))
+    sim = oracle.OracleSim(p, x, rr, v=v, pairs=np.array([[0, 1]]), pair_bonded=np.array([1]),
+                           bond_at_init=False)
+    fmin = 0.0
+    broke_at = None
+    prev_delta = None
+    for k in range(3000):
+        sim.step(1)
+        st = sim.state()
+        d = np.linalg.norm(st["x"][1] - st["x"][0])
+        delta = 2 * r - d
+        Fel = st["F"][0, 0] * -1.0           # force on 0 is -F_el n, n = +x
+        if sim.scalars()["broken_bonds"] == 1 and broke_at is None:
+            broke_at = (prev_delta, delta)
+            assert Fel == 0.0
+        if broke_at is None:
+            fmin = min(fmin, Fel)
+        prev_delta = delta
+    assert broke_at is not None
+    assert broke_at[1] < dC <= broke_at[0]
+    # pull-off force 3 pi gamma R* (Table 1, point C), resolved to the step size
+    assert fmin == pytest.approx(-3 * math.pi * GAM * Rs, rel=1e-6)
+    # re-approach: no cohesion while apart, Hertz (never JKR) on contact
+    st = sim.state()
+    sim2 = oracle.OracleSim(p, st["x"], rr, v=-st["v"], bond_at_init=False)
+    saw_contact = False
+    for k in range(3000):
+        sim2.step(1)
+        s2 = sim2.state()
+        d = np.linalg.norm(s2["x"][1] - s2["x"][0])
+        Fel = -s2["F"][0, 0]
+        if d >= 2 * r:
+            assert Fel == 0.0
+        else:
+            saw_contact = True
+            hertz = 4 / 3 * ES * math.sqrt(Rs) * (2 * r - d) ** 1.5
+            assert Fel == pytest.approx(hertz, rel=1e-9)
+            break
+    assert saw_contact
+    assert sim2.scalars()["broken_bonds"] == 0
+
+
+# ---------------------------------------------------------------------------
+# coarse-graining (section 2.4, Table 3)
+# ---------------------------------------------------------------------------
+def test_cg_identities():
+    fine = scenes.material()
+    for k in (2.0, 3.0):
+        g = cg.scale_material(fine, k)
+        for key in ("rho", "E", "nu", "e", "mu"):
+            assert g[key] == fine[key]
+        assert g["gamma"] == k * fine["gamma"]
+        Rp, Rg = RS, k * RS
+        # pull-off force scales k^2 (eq 23), pull-off overlap and contact radius k (eq 29-30)
+        assert 3 * math.pi * g["gamma"] * Rg == pytest.approx(k * k * 3 * math.pi * fine["gamma"] * Rp, rel=1e-15)
+        for d in (-0.3 * X_of(), 0.0, 1.0 * X_of(), 5 * X_of()):
+            ap = oracle.jkr_a_of_delta(d, Rp, ES, fine["gamma"])
+            ag = oracle.jkr_a_of_delta(k * d, Rg, ES, g["gamma"])
+            assert ag == pytest.approx(k * ap, rel=1e-14)
+            assert oracle.jkr_force_of_a(ag, Rg, ES, g["gamma"]) == pytest.approx(
+                k * k * oracle.jkr_force_of_a(ap, Rp, ES, fine["gamma"]), rel=1e-12, abs=1e-20)
+    rows = {r[0]: r[1:] for r in read_golden("table3_material.txt")}
+    assert cg.grain_count(float(rows["number"][0]), 2.0) == float(rows["number"][1])
+    assert cg.scale_material(dict(fine, gamma=float(rows["surface_energy"][0])), 2.0)["gamma"] == \
+        float(rows["surface_energy"][1])
+    for n, k, ng in [(200000, 2, 25000), (200000, 3, 7407), (2000000, 3, 74074)]:
+        assert cg.grain_count(n, k) == pytest.approx(ng, abs=0.5)
+
+
+@pytest.mark.parametrize("bonded", [True, False])
+def test_cg_dynamics_self_similar(bonded):
+    """Gravity-free two-grain impact: with lengths, times x k, masses x k^3,
+    gamma x k and E, nu, e, mu kept (Table 3), velocities are unchanged and
+    forces scale k^2 at every step (eq 21-35)."""
+    k = 3.0
+    r1, r2 = 6e-5, 9e-5
+    X = X_of(r1 * r2 / (r1 + r2), ES, GAM)
+    fine = scenes.material(mu=0.3)
+    runs = []
+    for kk, mat in ((1.0, fine), (k, cg.scale_material(fine, k))):
+        x, r, v = scenes.two_spheres(kk * r1, kk * r2, -kk * 0.3 * X, 0.05, axis=(1.0, 0.4, 0.2))
+        v[0] += np.array([0.0, 0.01, -0.02])
+        w = np.array([[0.0, 300.0, -100.0], [50.0, 0.0, 20.0]]) / kk
+        p = _params(mat, kk * 5e-8, g=(0, 0, 0))
+        kw = dict(pairs=np.array([[0, 1]]), pair_bonded=np.array([1])) if bonded else {}
+        sim = oracle.OracleSim(p, x, r, v=v, w=w, bond_at_init=False, **kw)
+        hist = []
+        for _ in range(60):
+            sim.step(10)
+            st = sim.state()
+            hist.append((st["x"], st["v"], st["w"], st["F"], st["T"]))
+        runs.append(hist)
+    for (xp, vp, wp, Fp, Tp), (xg, vg, wg, Fg, Tg) in zip(*runs):
+        np.testing.assert_allclose(vg, vp, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(wg * k, wp, rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(xg[1] - xg[0], k * (xp[1] - xp[0]), rtol=1e-11)
+        fs = np.abs(Fp).max() + 1e-30
+        np.testing.assert_allclose(Fg, k * k * Fp, rtol=0, atol=1e-9 * k * k * fs)
+        ts = np.abs(Tp).max() + 1e-30
+        np.testing.assert_allclose(Tg, k ** 3 * Tp, rtol=0, atol=1e-9 * k ** 3 * ts)
+
+
+# ---------------------------------------------------------------------------
+# coupling conservation (eq 7)
+# ---------------------------------------------------------------------------
+def test_deposition_and_drag_conserved():
+    rng = np.random.default_rng(7)
+    n = 400
+    x = rng.uniform(-0.2e-3, 2.2e-3, (n, 3))            # some outside the grid: folded in
+    r = rng.uniform(3e-5, 8e-5, n)
+    v = rng.normal(0, 0.01, (n, 3))
+    grid = ((0.0, 0.0, 0.0), (2e-3, 2e-3, 2e-3), (5, 4, 3))
+    fluid = dict(rho_f=998.2, mu_f=1e-3, n_min=0.3, voidfrac=0, u_superficial=1, couple_every=1)
+    nc = 5 * 4 * 3
+    u = rng.normal(0, 0.05, (nc, 3))
+    gp = rng.normal(0, 1e3, (nc, 3))
+    for vf in (oracle.VOID_CIC, oracle.VOID_CENTROID):
+        fl = dict(fluid, voidfrac=vf)
+        p = _params(scenes.material(gamma=0.0), 1e-9, grid=grid, fluid=fl, normal_model=oracle.NORMAL_HERTZ)
+        sim = oracle.OracleSim(p, x, r, v=v, bond_at_init=False)
+        sim.set_fluid(u, gp)
+        sim.step(1)
+        fl_out = sim.fluid()
+        vcell = (2e-3 / 5) * (2e-3 / 4) * (2e-3 / 3)
+        assert fl_out["eps_s"].sum() * vcell == pytest.approx(np.sum(4 / 3 * math.pi * r ** 3), rel=1e-13)
+        np.testing.assert_allclose(fl_out["fdrag_cell"].sum(0) * vcell, fl_out["f_part"].sum(0), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# numbers printed in section 3.1 (Tables 2-3, eq 36-38)
+# ---------------------------------------------------------------------------
+def test_paper_internal_consistency():
+    rows = read_golden("table2_psd.txt")
+    psd = [tuple(float(q) for q in row) for row in rows if row[0] != "ssp_k2_mm"]
+    ssp = float([r for r in rows if r[0] == "ssp_k2_mm"][0][1])
+    w = np.array([p[0] for p in psd])
+    d = np.array([p[1] for p in psd])
+    dssw = np.array([p[2] for p in psd])
+    np.testing.assert_allclose(cg.ssw_diameters(d, 2.0), dssw, rtol=1e-12)
+    dbar = cg.mean_diameter_mass_fractions(d, w)
+    assert dbar == pytest.approx(0.22948, abs=2e-5)
+    assert round(2 * dbar, 2) == ssp
+    setup = {r[0]: float(r[1]) for r in read_golden("section31_setup.txt")}
+    assert setup["cfd_cell_mm"] / dbar == pytest.approx(setup["cells_ratio_original"], rel=5e-3)
+    assert setup["cfd_cell_mm"] / ssp == pytest.approx(setup["cells_ratio_k2"], rel=5e-3)
+    assert cg.unresolved_ok(setup["cfd_cell_mm"], 2 * dbar)
+    mat = {r[0]: float(r[1]) for r in read_golden("table3_material.txt")}
+    tc = cg.rayleigh_dt(0.5 * dbar * 1e-3, mat["density"], mat["young"], mat["poisson"])
+    assert setup["dem_dt"] / tc == pytest.approx(setup["rayleigh_fraction"], abs=1e-3)
+    vs = mat["number"] * math.pi / 6 * (dbar * 1e-3) ** 3
+    box = (setup["box_side_mm"] * 1e-3) ** 2 * setup["height_mm"] * 1e-3
+    assert 1 - vs / box == pytest.approx(setup["porosity"], abs=0.01)
+
+
+def test_rmsre_and_dimensionless_production():
+    t = np.linspace(0, 1, 11)
+    M = np.exp(-3 * t)
+    td, Md = cg.dimensionless_production(t, M)
+    assert td[-1] == 1.0 and Md[-1] == pytest.approx(1.0) and Md[0] == 0.0
+    assert np.all(np.diff(Md) > 0)
+    assert cg.rmsre([1.0, 2.0], [1.0, 2.0]) == 0.0
+    assert cg.rmsre([1.0, 1.0], [0.9, 1.1]) == pytest.approx(10.0)
+
+
+def test_outlet_removes_and_counts_mass():
+    r = np.array([5e-5, 5e-5])
+    x = np.array([[2.0e-3 + 1e-7, 0, 1e-3], [5e-3, 0, 1e-3]])
+    v = np.array([[-1.0, 0, 0], [0, 0, 0]])
+    p = _params(scenes.material(), 1e-6, g=(0, 0, 0), outlet=(0.0, 0.0, 2.0e-3))
+    sim = oracle.OracleSim(p, x, r, v=v, bond_at_init=False)
+    sim.step(1)
+    st = sim.state()
+    assert list(st["alive"]) == [0, 1]
+    assert sim.scalars()["produced_mass"] == pytest.approx(RHO * 4 / 3 * math.pi * r[0] ** 3, rel=1e-15)
