@@ -1,0 +1,191 @@
+"""Benchmark: DEM + fluid-coupling steps on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1] [--no-cpu]
+
+Workload c1: 200 000 polydisperse spheres in the hollow cylinder with the radial
+Darcy inflow (mixed precision: FP64 positions/velocities, FP32 forces), inputs
+resident in HBM before the timed region.  A step is one pass of the whole hot
+path: kick/drift with outlet removal, neighbour-list rebuild when the skin is
+exceeded, coupling (porosity, drag, cell drag source) every couple_every steps,
+pair forces, fixed-order gather, walls, second kick.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2211_06142_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2211_06142_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def alg_bytes(cls, n_alive, n_pairs, n_cells, rsz):
+    """Unique footprint of each kernel class per launch (every element the
+    class must read or write once), from the data layout of the state."""
+    R3 = 3 * rsz
+    part_kin = 24 + 24 + R3 + 8          # x, v, omega, radius
+    if cls == "kick_drift":
+        # read x, v, omega, F, T, mass terms, alive; write x, v, omega
+        return n_alive * (24 + 24 + R3 + R3 + R3 + 8 + 1 + 24 + 24 + R3)
+    if cls == "pair_force":
+        # per pair: indices, history r/w, flags r/w, force record write (F, n x Ft);
+        # per particle: the kinematic state gathered once
+        return n_pairs * (8 + 2 * R3 + 2 + 2 * R3) + n_alive * part_kin
+    if cls == "gather_kick":
+        # records read once per side; per particle: v, omega, radius, fluid force in,
+        # v, omega, F, T out
+        return n_pairs * 2 * (2 * R3) + n_alive * (24 + R3 + 8 + R3 + 24 + R3 + R3 + R3)
+    if cls == "fluid":
+        # per particle: position, radius, velocity in, drag out; per cell: u, grad p in,
+        # porosity and drag source out
+        return n_alive * (24 + 8 + 24 + R3) + n_cells * (48 + 8 + 24)
+    if cls == "rebuild":
+        return n_alive * 2 * (24 + 24 + 4 * R3 + 8) + n_pairs * (8 + R3 + 1)
+    return 0
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle on the same workload, single thread, bounded sample."""
+    import oracle
+    from oracle import cg
+    mat = cg.scale_material(w["material"], w.get("k", 1.0))
+    op = oracle.make_params(mat, w["dt"], g=w["g"], walls=w["walls"], grid=w["grid"], fluid=w["fluid"],
+                            outlet=w["outlet"])
+    t0 = time.perf_counter()
+    sim = oracle.OracleSim(op, w["x"], w["r"], bond_at_init=True)
+    sim.set_fluid(w["u_cell"], w["gradp_cell"])
+    t_init = time.perf_counter() - t0
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        sim.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= 200:
+            break
+    nal = int(sim.state()["alive"].sum())
+    return {"value": nal * steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%s: %d particles, first %d steps from the initial packing (incl. one coupling "
+                      "evaluation per %d steps), %.1f s; setup %.1f s excluded"
+                      % (w["name"], len(w["r"]), steps, w["fluid"]["couple_every"], el, t_init)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; the multi-GPU sharding of the DEM step is a "
+              "design (see DESIGN.md), not an implemented path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2211_06142_amd import dem
+
+    if args.workload == "c1":
+        w = synth.c1()
+    elif args.workload == "c0":
+        w = synth.c0()
+    else:
+        raise SystemExit("unknown workload")
+    p = dem.params_from_workload(w)
+    sim = dem.Simulation(p, w["x"], w["r"])
+    sim.map_fluid(w["u_cell"], w["gradp_cell"])
+    sim.step(args.warmup)
+    n0 = sim.state()["n_alive"]
+    stream = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    sim.profile(1)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    prof = sim.read_profile()
+    sim.profile(0)
+    st = sim.state()
+    inf = sim.info()
+    n1 = st["n_alive"]
+    n_alive = 0.5 * (n0 + n1)
+    value = n_alive * args.steps / (ms * 1e-3)
+    rsz = 8 if w["precision"] == "fp64" else 4
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    avg_s = dom_ms * 1e-3 / max(dom_n, 1)
+    ab = alg_bytes(dom, n_alive, inf["n_pairs"], inf["ncell"], rsz)
+    achieved = ab / avg_s / 1e9
+    kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
+                   "avg_us": round(1e3 * v[0] / max(v[1], 1), 3),
+                   "alg_GBs": round(alg_bytes(k, n_alive, inf["n_pairs"], inf["ncell"], rsz) /
+                                    (v[0] * 1e-3 / max(v[1], 1)) / 1e9, 1) if v[1] else None}
+               for k, v in prof.items()}
+    out = {
+        "metric": "particle-steps/s at 200k particles, 1 GPU",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64-positions/f32-forces" if rsz == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d polydisperse spheres (lognormal d, median 0.15 mm), hollow cylinder "
+                               "R 12 mm / cavity 2 mm, 48x48x24 fluid grid, radial Darcy inflow, dt 1e-7 s, "
+                               "coupling every %d steps" % (w["name"], len(w["r"]), w["fluid"]["couple_every"]),
+                   "n_particles": len(w["r"]), "n_alive_mean": n_alive, "n_pairs": inf["n_pairs"],
+                   "rebuilds": inf["rebuilds"], "packing_sha256": w["sha256"][:16],
+                   "produced_mass_kg": st["produced_mass"], "coordination": st["coordination"],
+                   "broken_bonds": st["broken_bonds"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(dom, args.workload),
+                     "alg_bytes_per_launch": ab, "avg_launch_us": avg_s * 1e6},
+        "kernels": kernels,
+        "wall_s": wall,
+    }
+    sim.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

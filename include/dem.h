@@ -205,6 +205,16 @@ dem_status dem_info(dem_ctx* ctx, int64_t* ncell, int64_t* n_pairs, int64_t* pai
 /* Force a neighbour-list rebuild at the start of the next step. */
 dem_status dem_request_rebuild(dem_ctx* ctx);
 
+/* Kernel-class timing with HIP events recorded on the context's stream
+ * around every launch of each class (for roofline reporting).  enable = 1
+ * starts (and zeroes) the accumulators, 0 stops.  dem_read_profile fills
+ * DEM_PROF_N entries: total milliseconds and number of launches of each
+ * class since the last enable (host arrays). */
+enum { DEM_PROF_KICK = 0, DEM_PROF_REBUILD = 1, DEM_PROF_FLUID = 2, DEM_PROF_PAIR = 3,
+       DEM_PROF_GATHER = 4, DEM_PROF_N = 5 };
+dem_status dem_profile(dem_ctx* ctx, int32_t enable);
+dem_status dem_read_profile(dem_ctx* ctx, double* total_ms, int64_t* launches);
+
 void dem_destroy(dem_ctx* ctx);
 const char* dem_status_str(dem_status s);
 

@@ -63,6 +63,13 @@ struct dem_ctx {
   int failed = 0;       // a latched device fault
   int* h_flag = nullptr;  // pinned
   std::vector<void*> allocs;
+  // kernel-class timing
+  int prof = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<int, int>>> ev_pending;  // class, (start, stop) pool slots
+  size_t ev_used = 0;
+  double prof_ms[DEM_PROF_N] = {0, 0, 0, 0, 0};
+  int64_t prof_cnt[DEM_PROF_N] = {0, 0, 0, 0, 0};
   // staging for read-back
   double* stage = nullptr;
   uint8_t* stage_alive = nullptr;
@@ -324,11 +331,49 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   return DEM_OK;
 }
 
+// event pair around one launch of a kernel class (profiling mode only)
+int prof_begin(dem_ctx* c) {
+  if (!c->prof) return -1;
+  if (c->ev_used + 2 > c->ev_pool.size()) {
+    size_t grow = std::max<size_t>(256, c->ev_pool.size());
+    for (size_t k = 0; k < grow; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      c->ev_pool.push_back(e);
+    }
+  }
+  int slot = (int)c->ev_used;
+  c->ev_used += 2;
+  (void)hipEventRecord(c->ev_pool[slot], c->stream);
+  return slot;
+}
+
+void prof_end(dem_ctx* c, int cls, int slot) {
+  if (slot < 0) return;
+  (void)hipEventRecord(c->ev_pool[slot + 1], c->stream);
+  c->ev_pending.push_back({cls, {slot, slot + 1}});
+}
+
+// accumulate completed event pairs (the stream has been synchronised)
+void prof_collect(dem_ctx* c) {
+  for (auto& q : c->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[q.second.first], c->ev_pool[q.second.second]) == hipSuccess) {
+      c->prof_ms[q.first] += ms;
+      c->prof_cnt[q.first] += 1;
+    }
+  }
+  c->ev_pending.clear();
+  c->ev_used = 0;
+}
+
 template <typename R> dem_status step_impl(dem_ctx* c, int64_t nsteps) {
   DevState& d = c->d;
   hipStream_t s = c->stream;
   for (int64_t k = 0; k < nsteps; ++k) {
+    int ps = prof_begin(c);
     launch_kick_drift<R>(d, s);
+    prof_end(c, DEM_PROF_KICK, ps);
     int need = c->force_rebuild;
     if (!need) {
       HIPCHK(hipMemcpyAsync(c->h_flag, d.rebuild_flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -336,17 +381,32 @@ template <typename R> dem_status step_impl(dem_ctx* c, int64_t nsteps) {
       need = *c->h_flag;
     }
     if (need) {
+      ps = prof_begin(c);
       dem_status st = rebuild<R>(c, 0, 0);
       if (st != DEM_OK) return st;
+      prof_end(c, DEM_PROF_REBUILD, ps);
       HIPCHK(hipMemsetAsync(d.rebuild_flag, 0, sizeof(int), s));
       c->force_rebuild = 0;
     }
-    if (c->any_fluid && c->have_fluid && (c->step % d.couple_every) == 0) launch_fluid<R>(d, s);
+    if (c->any_fluid && c->have_fluid && (c->step % d.couple_every) == 0) {
+      ps = prof_begin(c);
+      launch_fluid<R>(d, s);
+      prof_end(c, DEM_PROF_FLUID, ps);
+    }
+    ps = prof_begin(c);
     launch_pair_force<R>(d, s);
+    prof_end(c, DEM_PROF_PAIR, ps);
+    ps = prof_begin(c);
     launch_gather_kick<R>(d, s);
+    prof_end(c, DEM_PROF_GATHER, ps);
     c->step++;
+    if (c->ev_used > 4096) {
+      HIPCHK(hipStreamSynchronize(s));
+      prof_collect(c);
+    }
   }
   HIPCHK(hipStreamSynchronize(s));
+  prof_collect(c);
   int st = 0;
   HIPCHK(hipMemcpy(&st, d.status, sizeof(int), hipMemcpyDeviceToHost));
   if (st) {
@@ -851,6 +911,26 @@ dem_status dem_info(dem_ctx* c, int64_t* ncell, int64_t* n_pairs, int64_t* pair_
   return DEM_OK;
 }
 
+dem_status dem_profile(dem_ctx* c, int32_t enable) {
+  if (!c) return DEM_E_INVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  if (enable) {
+    for (int k = 0; k < DEM_PROF_N; ++k) { c->prof_ms[k] = 0.0; c->prof_cnt[k] = 0; }
+  }
+  c->prof = enable ? 1 : 0;
+  return DEM_OK;
+}
+
+dem_status dem_read_profile(dem_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c) return DEM_E_INVAL;
+  for (int k = 0; k < DEM_PROF_N; ++k) {
+    if (total_ms) total_ms[k] = c->prof_ms[k];
+    if (launches) launches[k] = c->prof_cnt[k];
+  }
+  return DEM_OK;
+}
+
 dem_status dem_request_rebuild(dem_ctx* c) {
   if (!c) return DEM_E_INVAL;
   c->force_rebuild = 1;
@@ -867,6 +947,7 @@ void dem_destroy(dem_ctx* c) {
   if (c->stage) (void)hipFree(c->stage);
   if (c->stage_alive) (void)hipFree(c->stage_alive);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 

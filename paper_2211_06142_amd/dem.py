@@ -23,9 +23,12 @@ DEM_PREC_FP64, DEM_PREC_MIXED = 0, 1
 DEM_CG_SSW, DEM_CG_SSP = 0, 1
 DEM_FLAG_AUTO_REGROW = 1
 
-EXPORTS = ["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "dem_read_pairs",
-           "dem_read_aggregates", "dem_info", "dem_request_rebuild", "dem_destroy", "dem_status_str",
-           "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt"]
+DEM_PROF_KICK, DEM_PROF_REBUILD, DEM_PROF_FLUID, DEM_PROF_PAIR, DEM_PROF_GATHER, DEM_PROF_N = 0, 1, 2, 3, 4, 5
+PROF_NAMES = ["kick_drift", "rebuild", "fluid", "pair_force", "gather_kick"]
+
+EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "dem_read_pairs",
+                  "dem_read_aggregates", "dem_info", "dem_request_rebuild", "dem_destroy", "dem_status_str",
+                  "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile"])
 
 
 class dem_wall(ctypes.Structure):
@@ -103,6 +106,10 @@ def lib():
         L.dem_info.argtypes = [vp, vp, vp, vp, vp, vp]
         L.dem_request_rebuild.restype = i32
         L.dem_request_rebuild.argtypes = [vp]
+        L.dem_profile.restype = i32
+        L.dem_profile.argtypes = [vp, i32]
+        L.dem_read_profile.restype = i32
+        L.dem_read_profile.argtypes = [vp, vp, vp]
         L.dem_destroy.restype = None
         L.dem_destroy.argtypes = [vp]
         L.dem_status_str.restype = ctypes.c_char_p
@@ -190,6 +197,17 @@ def dem_request_rebuild(ctx):
 
 def dem_destroy(ctx):
     lib().dem_destroy(ctx)
+
+
+def dem_profile(ctx, enable):
+    return lib().dem_profile(ctx, int(enable))
+
+
+def dem_read_profile(ctx):
+    ms = np.zeros(DEM_PROF_N)
+    cnt = np.zeros(DEM_PROF_N, np.int64)
+    rc = lib().dem_read_profile(ctx, ms.ctypes.data, cnt.ctypes.data)
+    return rc, ms, cnt
 
 
 def dem_cg_material(params):
@@ -390,6 +408,14 @@ class Simulation:
         rc, inf = dem_info(self.ctx)
         _check(rc, "dem_info")
         return inf
+
+    def profile(self, enable):
+        _check(dem_profile(self.ctx, enable), "dem_profile")
+
+    def read_profile(self):
+        rc, ms, cnt = dem_read_profile(self.ctx)
+        _check(rc, "dem_read_profile")
+        return {name: (float(ms[k]), int(cnt[k])) for k, name in enumerate(PROF_NAMES)}
 
     def request_rebuild(self):
         _check(dem_request_rebuild(self.ctx), "dem_request_rebuild")
