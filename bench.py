@@ -33,27 +33,29 @@ def source_hash():
 
 
 def alg_bytes(cls, n_alive, n_pairs, n_cells, rsz):
-    """Unique footprint of each kernel class per launch (every element the
-    class must read or write once), from the data layout of the state."""
-    R3 = 3 * rsz
-    part_kin = 24 + 24 + R3 + 8          # x, v, omega, radius
-    if cls == "kick_drift":
-        # read x, v, omega, F, T, mass terms, alive; write x, v, omega
-        return n_alive * (24 + 24 + R3 + R3 + R3 + 8 + 1 + 24 + 24 + R3)
-    if cls == "pair_force":
-        # per pair: indices, history r/w, flags r/w, force record write (F, n x Ft);
-        # per particle: the kinematic state gathered once
-        return n_pairs * (8 + 2 * R3 + 2 + 2 * R3) + n_alive * part_kin
-    if cls == "gather_kick":
-        # records read once per side; per particle: v, omega, radius, fluid force in,
-        # v, omega, F, T out
-        return n_pairs * 2 * (2 * R3) + n_alive * (24 + R3 + 8 + R3 + 24 + R3 + R3 + R3)
+    """Algorithmic bytes per launch of each kernel class: the per-unit figures
+    of the method's state (mixed: FP64 x, v and FP32 omega, F, history; FP64
+    mode: all FP64) times the units one launch processes.
+      particle update: read x, v, omega, radius, flags; write x, v, omega
+                       mixed 24+24+12+4+4 + 60 = 128 B, FP64 156 B
+      half pair:       pair key 8 + history read and write + flags
+                       mixed 8 + 24 + 4 = 36 B, FP64 60 B
+      fluid cell:      u, grad p in, porosity and drag source out = 40 B
+    The fused step kernel is one particle update plus one pass over the
+    pairs; the coupling launch reads position, radius and velocity and writes
+    the held force of every particle (24+4+24+12 = 64 B) and does one cell
+    pass; the prologue is one particle update."""
+    per_p = 128 if rsz == 4 else 156
+    per_pair = 36 if rsz == 4 else 60
+    if cls == "step":
+        return n_alive * per_p + n_pairs * per_pair
+    if cls == "prologue":
+        return n_alive * per_p
     if cls == "fluid":
-        # per particle: position, radius, velocity in, drag out; per cell: u, grad p in,
-        # porosity and drag source out
-        return n_alive * (24 + 8 + 24 + R3) + n_cells * (48 + 8 + 24)
+        return n_alive * 64 + n_cells * 40
     if cls == "rebuild":
-        return n_alive * 2 * (24 + 24 + 4 * R3 + 8) + n_pairs * (8 + R3 + 1)
+        # one sort and permutation of the particle update state, one pass over the new pairs
+        return n_alive * 2 * per_p + n_pairs * per_pair
     return 0
 
 

@@ -210,10 +210,15 @@ dem_status dem_request_rebuild(dem_ctx* ctx);
  * starts (and zeroes) the accumulators, 0 stops.  dem_read_profile fills
  * DEM_PROF_N entries: total milliseconds and number of launches of each
  * class since the last enable (host arrays). */
-enum { DEM_PROF_KICK = 0, DEM_PROF_REBUILD = 1, DEM_PROF_FLUID = 2, DEM_PROF_PAIR = 3,
-       DEM_PROF_GATHER = 4, DEM_PROF_N = 5 };
+enum { DEM_PROF_PROLOGUE = 0, DEM_PROF_REBUILD = 1, DEM_PROF_FLUID = 2, DEM_PROF_STEP = 3,
+       DEM_PROF_N = 4 };
 dem_status dem_profile(dem_ctx* ctx, int32_t enable);
 dem_status dem_read_profile(dem_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Latched device fault bits (0: none): 1 pair capacity, 2 non-finite force,
+ * 4 a particle moved half the skin or more in one step, 8 a bonded pair was
+ * missing from a rebuilt neighbour list, 16 inconsistent rebuild request. */
+dem_status dem_read_fault(dem_ctx* ctx, int32_t* bits);
 
 void dem_destroy(dem_ctx* ctx);
 const char* dem_status_str(dem_status s);

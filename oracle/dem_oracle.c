@@ -377,7 +377,7 @@ int or_set_closure(or_sim* s, const double* c_drag, const double* c_coh) {
  * body, relative angular velocity wrel, and the tangential history dt.
  * Outputs: force on i, c = n x F_t (torque on body b is r_b * c), rolling
  * torque on i, scale = sum of the magnitudes of every force term. */
-typedef struct { double F[3], c[3], Tr[3], scale, tscale_roll; } law_out;
+typedef struct { double F[3], c[3], Tr[3], scale, tscale_t, tscale_roll; } law_out;
 
 static void contact_law(const or_sim* s, int bonded, double delta, double Rs, double ms, double gam,
                         const double* n, const double* vrel, const double* wrel, double* dt,
@@ -429,6 +429,10 @@ static void contact_law(const or_sim* s, int bonded, double delta, double Rs, do
   double tpl = norm3(tp);
   if (tpl > 0.0) { for (int c = 0; c < 3; ++c) dt[c] = tp[c] * (old / tpl); }
   else { dt[0] = dt[1] = dt[2] = 0.0; }
+  /* magnitudes of the terms entering F_t: spring on the carried elongation,
+   * spring and dashpot on this step's slip (which itself is v_rel minus its
+   * normal part) */
+  double tsc = kt * norm3(dt) + (kt * p->dt + etat) * norm3(vrel);
   for (int c = 0; c < 3; ++c) dt[c] += vt[c] * p->dt;
   double Ft[3];
   for (int c = 0; c < 3; ++c) Ft[c] = -kt * dt[c] - etat * vt[c];
@@ -441,7 +445,8 @@ static void contact_law(const or_sim* s, int bonded, double delta, double Rs, do
     else { dt[0] = dt[1] = dt[2] = 0.0; }
   }
   for (int c = 0; c < 3; ++c) o->F[c] += Ft[c];
-  scale += norm3(Ft);
+  scale += tsc;
+  o->tscale_t = tsc;
   cross3(n, Ft, o->c);                                              /* eq 5 */
 
   /* optional rolling resistance (constant directional torque) */
@@ -722,9 +727,8 @@ static void one_step(or_sim* s) {
       s->T[3 * i + c] += ri * o.c[c] + o.Tr[c];
       s->T[3 * j + c] += rj * o.c[c] - o.Tr[c];
     }
-    double cm = norm3(o.c);
     s->fscale[i] += o.scale; s->fscale[j] += o.scale;
-    s->tscale[i] += ri * cm + o.tscale_roll; s->tscale[j] += rj * cm + o.tscale_roll;
+    s->tscale[i] += ri * o.tscale_t + o.tscale_roll; s->tscale[j] += rj * o.tscale_t + o.tscale_roll;
     nh[nnh++] = rec;
   }
   free(uni);
@@ -755,7 +759,7 @@ static void one_step(or_sim* s) {
         s->T[3 * i + c] += ri * o.c[c] + o.Tr[c];
       }
       s->fscale[i] += o.scale;
-      s->tscale[i] += ri * norm3(o.c) + o.tscale_roll;
+      s->tscale[i] += ri * o.tscale_t + o.tscale_roll;
     }
   }
 

@@ -24,11 +24,11 @@ namespace {
     if (e_ != hipSuccess) return DEM_E_DEVICE;       \
   } while (0)
 
-struct PairSet {
-  int32_t *prow = nullptr, *pj = nullptr, *pown = nullptr;
-  void* hdt = nullptr;
-  uint8_t* pfl = nullptr;
-  int64_t cap = 0, n = 0;
+struct NbrSet {
+  int32_t *nrow = nullptr, *nbr = nullptr, *nslot = nullptr, *hrow = nullptr, *sown = nullptr, *spart = nullptr;
+  void* hdt[2] = {nullptr, nullptr};
+  uint8_t* pfl[2] = {nullptr, nullptr};
+  int64_t ent_cap = 0, slot_cap = 0, nent = 0, nslots = 0;
 };
 
 struct WallSet {
@@ -36,6 +36,12 @@ struct WallSet {
   void* wdt = nullptr;
   uint8_t* wfl = nullptr;
   int64_t cap = 0, n = 0;
+};
+
+struct ProfRec {
+  int cls;
+  int64_t step;   // step a launch belongs to (-1: always counted)
+  int slot;
 };
 
 }  // namespace
@@ -51,25 +57,26 @@ struct dem_ctx {
   std::vector<int64_t> offsets;
   int64_t* d_offsets = nullptr;
   std::vector<double> dead_mass0;
-  PairSet ps[2];
+  NbrSet ns[2];
   WallSet ws[2];
-  int cur = 0;          // ps[cur] / ws[cur] is the live list
-  int64_t rec_cap = 0;  // capacity of recF/recC/recT/ridx
+  int live = 0;          // ns[live] / ws[live] is the current list
+  int hist_old = 0;      // history buffer of the previous list at the next rebuild
   int64_t step = 0;
   int64_t rebuilds = 0;
   int have_fluid = 0;
   int any_fluid = 0;
-  int force_rebuild = 1;
-  int failed = 0;       // a latched device fault
-  int* h_flag = nullptr;  // pinned
+  int force_rebuild = 0;
+  int failed = 0;        // a latched device fault
+  int window = 32;       // steps enqueued between host checks
+  int* h_flags = nullptr;  // pinned: abort, abort_step, status
   std::vector<void*> allocs;
   // kernel-class timing
   int prof = 0;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, std::pair<int, int>>> ev_pending;  // class, (start, stop) pool slots
+  std::vector<ProfRec> ev_pending;
   size_t ev_used = 0;
-  double prof_ms[DEM_PROF_N] = {0, 0, 0, 0, 0};
-  int64_t prof_cnt[DEM_PROF_N] = {0, 0, 0, 0, 0};
+  double prof_ms[DEM_PROF_N] = {0, 0, 0, 0};
+  int64_t prof_cnt[DEM_PROF_N] = {0, 0, 0, 0};
   // staging for read-back
   double* stage = nullptr;
   uint8_t* stage_alive = nullptr;
@@ -156,8 +163,6 @@ void derive(const dem_params& p, const double* x, const double* r, const uint8_t
   c.mu_roll = p.mu_roll;
   c.rho = p.rho;
   c.k_lin = p.k_lin;
-  c.jkrK = (kPi * kPi) * (c.gamma * c.gamma) / (c.Es * c.Es);
-  c.breakA = ((3.0 / 16.0) * (kPi * kPi)) * (c.gamma * c.gamma);
   c.kcg = p.k;
   c.k3 = p.k * p.k * p.k;
   c.normal_model = p.normal_model;
@@ -186,7 +191,6 @@ void derive(const dem_params& p, const double* x, const double* r, const uint8_t
     c.walls[w].kind = p.walls[w].kind;
     for (int k = 0; k < 6; ++k) c.walls[w].p[k] = p.walls[w].p[k];
   }
-  // sizes
   double rmin = 1e300, rmax = 0.0, bl[3] = {1e300, 1e300, 1e300}, bh[3] = {-1e300, -1e300, -1e300};
   int64_t nal = 0;
   for (int64_t i = lo; i < hi; ++i) {
@@ -225,32 +229,42 @@ void derive(const dem_params& p, const double* x, const double* r, const uint8_t
   for (int k = 0; k < 3; ++k) c.bh[k] = ext[k] / c.bn[k];
 }
 
-template <typename R> void run_kick_drift(dem_ctx* c) { launch_kick_drift<R>(c->d, c->stream); }
-
-// bind the live pair/wall sets into the device descriptor
 void bind_sets(dem_ctx* c) {
-  PairSet& a = c->ps[c->cur];
-  PairSet& b = c->ps[1 - c->cur];
-  c->d.prow = a.prow; c->d.pj = a.pj; c->d.pown = a.pown; c->d.hdt = a.hdt; c->d.pfl = a.pfl;
-  c->d.pair_cap = a.cap; c->d.npairs = a.n;
-  c->d.prow_old = b.prow; c->d.pj_old = b.pj; c->d.hdt2 = b.hdt; c->d.pfl2 = b.pfl;
-  WallSet& wa = c->ws[c->cur];
-  WallSet& wb = c->ws[1 - c->cur];
-  c->d.wrow = wa.wrow; c->d.wid = wa.wid; c->d.wdt = wa.wdt; c->d.wfl = wa.wfl;
-  c->d.wall_cap = wa.cap; c->d.nwall = wa.n;
-  c->d.wrow_old = wb.wrow; c->d.wid_old = wb.wid; c->d.wdt2 = wb.wdt; c->d.wfl2 = wb.wfl;
+  NbrSet& a = c->ns[c->live];
+  NbrSet& b = c->ns[1 - c->live];
+  DevState& d = c->d;
+  d.nrow = a.nrow; d.nbr = a.nbr; d.nslot = a.nslot; d.hrow = a.hrow; d.sown = a.sown; d.spart = a.spart;
+  d.hdt[0] = a.hdt[0]; d.hdt[1] = a.hdt[1]; d.pfl[0] = a.pfl[0]; d.pfl[1] = a.pfl[1];
+  d.ent_cap = a.ent_cap; d.slot_cap = a.slot_cap; d.nent = a.nent; d.nslots = a.nslots;
+  d.nrow_o = b.nrow; d.nbr_o = b.nbr; d.nslot_o = b.nslot; d.sown_o = b.sown; d.spart_o = b.spart;
+  d.hdt_o = b.hdt[c->hist_old]; d.pfl_o = b.pfl[c->hist_old]; d.nslots_o = b.nslots;
+  WallSet& wa = c->ws[c->live];
+  WallSet& wb = c->ws[1 - c->live];
+  d.wrow = wa.wrow; d.wid = wa.wid; d.wdt = wa.wdt; d.wfl = wa.wfl; d.wall_cap = wa.cap; d.nwall = wa.n;
+  d.wrow_o = wb.wrow; d.wid_o = wb.wid; d.wdt_o = wb.wdt; d.wfl_o = wb.wfl;
 }
 
-hipError_t grow_pairs(dem_ctx* c, PairSet& s, int64_t need) {
-  if (need <= s.cap) return hipSuccess;
-  int64_t cap = std::max<int64_t>(need + need / 4 + 1024, s.cap * 2);
-  dfree(c, s.pj); dfree(c, s.pown); dfree(c, s.hdt); dfree(c, s.pfl);
+hipError_t grow_nbr(dem_ctx* c, NbrSet& s, int64_t nent, int64_t nslots) {
   hipError_t e;
-  if ((e = dalloc(c, &s.pj, cap)) != hipSuccess) return e;
-  if ((e = dalloc(c, &s.pown, cap)) != hipSuccess) return e;
-  if ((e = dalloc_bytes(c, &s.hdt, cap * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
-  if ((e = dalloc(c, &s.pfl, cap)) != hipSuccess) return e;
-  s.cap = cap;
+  if (nent > s.ent_cap) {
+    int64_t cap = std::max<int64_t>(nent + nent / 4 + 1024, s.ent_cap * 2);
+    dfree(c, s.nbr); dfree(c, s.nslot);
+    if ((e = dalloc(c, &s.nbr, cap)) != hipSuccess) return e;
+    if ((e = dalloc(c, &s.nslot, cap)) != hipSuccess) return e;
+    s.ent_cap = cap;
+  }
+  if (nslots > s.slot_cap) {
+    int64_t cap = std::max<int64_t>(nslots + nslots / 4 + 1024, s.slot_cap * 2);
+    dfree(c, s.sown); dfree(c, s.spart);
+    for (int b = 0; b < 2; ++b) { dfree(c, s.hdt[b]); dfree(c, s.pfl[b]); }
+    if ((e = dalloc(c, &s.sown, cap)) != hipSuccess) return e;
+    if ((e = dalloc(c, &s.spart, cap)) != hipSuccess) return e;
+    for (int b = 0; b < 2; ++b) {
+      if ((e = dalloc_bytes(c, &s.hdt[b], cap * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
+      if ((e = dalloc(c, &s.pfl[b], cap)) != hipSuccess) return e;
+    }
+    s.slot_cap = cap;
+  }
   return hipSuccess;
 }
 
@@ -266,70 +280,7 @@ hipError_t grow_walls(dem_ctx* c, WallSet& s, int64_t need) {
   return hipSuccess;
 }
 
-hipError_t grow_records(dem_ctx* c, int64_t need) {
-  if (need <= c->rec_cap) return hipSuccess;
-  int64_t cap = need + need / 4 + 1024;
-  dfree(c, c->d.recF); dfree(c, c->d.recC); dfree(c, c->d.recT); dfree(c, c->d.ridx);
-  hipError_t e;
-  if ((e = dalloc_bytes(c, &c->d.recF, cap * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
-  if ((e = dalloc_bytes(c, &c->d.recC, cap * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
-  if ((e = dalloc_bytes(c, &c->d.recT, (c->d.rolling ? cap : 1) * 4 * (int64_t)c->rsz)) != hipSuccess) return e;
-  if ((e = dalloc(c, &c->d.ridx, cap)) != hipSuccess) return e;
-  c->rec_cap = cap;
-  return hipSuccess;
-}
-
 template <typename T> void swp(T& a, T& b) { T t = a; a = b; b = t; }
-
-// full neighbour-list rebuild (sort, permute, search, merge, reverse index)
-template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) {
-  DevState& d = c->d;
-  hipStream_t s = c->stream;
-  // 1. sort by (sample, cell, id); dead particles to their sample's last bucket
-  launch_bin_keys(d, s);
-  launch_bucket_sort(d.key, d.n, d.nbins_total, d.orig, d.bucket_cnt, d.cell_start, d.bucket_fill, d.order,
-                     d.scan_tmp, s);
-  launch_permute<R>(d, s);
-  swp(d.xr, d.xr2); swp(d.vel, d.vel2); swp(d.omg, d.omg2); swp(d.frc, d.frc2); swp(d.trq, d.trq2);
-  swp(d.fdr, d.fdr2); swp(d.alive, d.alive2); swp(d.sample, d.sample2); swp(d.orig, d.orig2);
-  if (d.cdrag) { swp(d.cdrag, d.cdrag2); swp(d.ccoh, d.ccoh2); }
-  // 2. the live list becomes the old one
-  int64_t old_n = c->ps[c->cur].n;
-  if (!first) c->cur = 1 - c->cur;
-  bind_sets(c);
-  // 3. count and fill pairs
-  launch_pair_count(d, s);
-  HIPCHK(hipMemsetAsync(d.pcnt + d.n, 0, sizeof(int32_t), s));
-  scan_exclusive(d.pcnt, d.prow, d.n + 1, d.scan_tmp, s);
-  launch_wall_count(d, s);
-  HIPCHK(hipMemsetAsync(d.wcnt + d.n, 0, sizeof(int32_t), s));
-  scan_exclusive(d.wcnt, d.wrow, d.n + 1, d.scan_tmp, s);
-  int32_t tot[2];
-  HIPCHK(hipMemcpyAsync(&tot[0], d.prow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&tot[1], d.wrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  PairSet& ps = c->ps[c->cur];
-  WallSet& ws = c->ws[c->cur];
-  if (grow_pairs(c, ps, tot[0]) != hipSuccess) return DEM_E_NOMEM;
-  if (grow_walls(c, ws, tot[1]) != hipSuccess) return DEM_E_NOMEM;
-  if (grow_records(c, tot[0]) != hipSuccess) return DEM_E_NOMEM;
-  ps.n = tot[0];
-  ws.n = tot[1];
-  bind_sets(c);
-  launch_pair_fill(d, s);
-  launch_wall_fill(d, s);
-  // 4. carry history
-  int check = first ? 0 : 1;
-  if (check) launch_count_old_bonds(d, old_n, s);
-  launch_hist_merge<R>(d, s, check);
-  if (check) launch_check_lost(d, s);
-  if (mark_bonds) launch_mark_bonds(d, s);
-  // 5. reverse index and reference positions
-  launch_reverse(d, s);
-  launch_set_xref(d, s);
-  c->rebuilds++;
-  return DEM_OK;
-}
 
 // event pair around one launch of a kernel class (profiling mode only)
 int prof_begin(dem_ctx* c) {
@@ -348,73 +299,172 @@ int prof_begin(dem_ctx* c) {
   return slot;
 }
 
-void prof_end(dem_ctx* c, int cls, int slot) {
+void prof_end(dem_ctx* c, int cls, int slot, int64_t step = -1) {
   if (slot < 0) return;
   (void)hipEventRecord(c->ev_pool[slot + 1], c->stream);
-  c->ev_pending.push_back({cls, {slot, slot + 1}});
+  c->ev_pending.push_back({cls, step, slot});
 }
 
-// accumulate completed event pairs (the stream has been synchronised)
-void prof_collect(dem_ctx* c) {
+// accumulate completed event pairs (the stream has been synchronised);
+// launches of steps >= drop_from did no work (aborted) and are not counted
+void prof_collect(dem_ctx* c, int64_t drop_from = INT64_MAX) {
   for (auto& q : c->ev_pending) {
+    if (q.step >= 0 && q.step >= drop_from) continue;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->ev_pool[q.second.first], c->ev_pool[q.second.second]) == hipSuccess) {
-      c->prof_ms[q.first] += ms;
-      c->prof_cnt[q.first] += 1;
+    if (hipEventElapsedTime(&ms, c->ev_pool[q.slot], c->ev_pool[q.slot + 1]) == hipSuccess) {
+      c->prof_ms[q.cls] += ms;
+      c->prof_cnt[q.cls] += 1;
     }
   }
   c->ev_pending.clear();
   c->ev_used = 0;
 }
 
+// full neighbour-list rebuild from the state in buffer d.cur
+template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) {
+  DevState& d = c->d;
+  hipStream_t s = c->stream;
+  // 1. sort by (sample, cell, id); dead particles to their sample's last bucket
+  launch_bin_keys(d, s);
+  launch_bucket_sort(d.key, d.n, d.nbins_total, d.orig, d.bucket_cnt, d.cell_start, d.bucket_fill, d.order_tmp,
+                     d.order, d.scan_tmp, s);
+  // 2. permute into the other buffer
+  launch_permute<R>(d, s);
+  c->hist_old = d.cur;
+  d.cur = 1 - d.cur;
+  swp(d.frc, d.t_r4[0]); swp(d.trq, d.t_r4[1]); swp(d.fdr, d.t_r4[2]);
+  swp(d.sample, d.t_i[0]); swp(d.orig, d.t_i[1]);
+  if (d.cdrag) { swp(d.cdrag, d.t_d[0]); swp(d.ccoh, d.t_d[1]); }
+  // 3. the live list becomes the previous one
+  if (!first) c->live = 1 - c->live;
+  bind_sets(c);
+  // 4. count and fill (dead particles own no entries: their counts stay zero)
+  HIPCHK(hipMemsetAsync(d.ncnt, 0, sizeof(int32_t) * (d.n + 1), s));
+  HIPCHK(hipMemsetAsync(d.ocnt, 0, sizeof(int32_t) * (d.n + 1), s));
+  launch_nbr_count(d, s);
+  scan_exclusive(d.ncnt, d.nrow, d.n + 1, d.scan_tmp, s);
+  scan_exclusive(d.ocnt, d.hrow, d.n + 1, d.scan_tmp, s);
+  launch_wall_count(d, s);
+  HIPCHK(hipMemsetAsync(d.wcnt + d.n, 0, sizeof(int32_t), s));
+  scan_exclusive(d.wcnt, d.wrow, d.n + 1, d.scan_tmp, s);
+  int32_t tot[3];
+  HIPCHK(hipMemcpyAsync(&tot[0], d.nrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tot[1], d.hrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tot[2], d.wrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  NbrSet& ns = c->ns[c->live];
+  WallSet& ws = c->ws[c->live];
+  if (grow_nbr(c, ns, tot[0], tot[1]) != hipSuccess) return DEM_E_NOMEM;
+  if (grow_walls(c, ws, tot[2]) != hipSuccess) return DEM_E_NOMEM;
+  ns.nent = tot[0];
+  ns.nslots = tot[1];
+  ws.n = tot[2];
+  bind_sets(c);
+  launch_nbr_fill(d, s);
+  launch_nbr_mirror(d, s);
+  launch_wall_fill(d, s);
+  // 5. carry history
+  int check = first ? 0 : 1;
+  if (check) launch_count_old_bonds(d, s);
+  launch_hist_merge<R>(d, s, check);
+  if (check) launch_check_lost(d, s);
+  if (mark_bonds) launch_mark_bonds(d, s);
+  launch_set_xref(d, s);
+  c->rebuilds++;
+  return DEM_OK;
+}
+
+dem_status read_flags(dem_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->h_flags, c->d.abort, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(c->h_flags + 1, c->d.abort_step, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(c->h_flags + 2, c->d.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return DEM_OK;
+}
+
+dem_status fault(dem_ctx* c, int st) {
+  c->failed = st;
+  if (st & kStNonFinite) return DEM_E_NONFINITE;
+  if (st & kStCapacity) return DEM_E_CAPACITY;
+  return DEM_E_STATE;
+}
+
+// Steps are enqueued in windows without waiting for the device.  A step that
+// finds a particle beyond half the skin raises `abort` and records the next
+// step; every later launch of the window exits at entry.  At the end of the
+// window the host reads the flags, rebuilds the list from the state the last
+// completed step left, and resumes at the recorded step.
 template <typename R> dem_status step_impl(dem_ctx* c, int64_t nsteps) {
   DevState& d = c->d;
   hipStream_t s = c->stream;
-  for (int64_t k = 0; k < nsteps; ++k) {
-    int ps = prof_begin(c);
-    launch_kick_drift<R>(d, s);
-    prof_end(c, DEM_PROF_KICK, ps);
-    int need = c->force_rebuild;
-    if (!need) {
-      HIPCHK(hipMemcpyAsync(c->h_flag, d.rebuild_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      need = *c->h_flag;
-    }
-    if (need) {
-      ps = prof_begin(c);
-      dem_status st = rebuild<R>(c, 0, 0);
-      if (st != DEM_OK) return st;
-      prof_end(c, DEM_PROF_REBUILD, ps);
-      HIPCHK(hipMemsetAsync(d.rebuild_flag, 0, sizeof(int), s));
-      c->force_rebuild = 0;
-    }
-    if (c->any_fluid && c->have_fluid && (c->step % d.couple_every) == 0) {
-      ps = prof_begin(c);
-      launch_fluid<R>(d, s);
-      prof_end(c, DEM_PROF_FLUID, ps);
-    }
-    ps = prof_begin(c);
-    launch_pair_force<R>(d, s);
-    prof_end(c, DEM_PROF_PAIR, ps);
-    ps = prof_begin(c);
-    launch_gather_kick<R>(d, s);
-    prof_end(c, DEM_PROF_GATHER, ps);
-    c->step++;
-    if (c->ev_used > 4096) {
-      HIPCHK(hipStreamSynchronize(s));
-      prof_collect(c);
-    }
+  if (nsteps <= 0) return DEM_OK;
+  const int64_t s_end = c->step + nsteps;
+  HIPCHK(hipMemsetAsync(d.abort, 0, sizeof(int), s));
+  HIPCHK(hipMemsetAsync(d.abort_step, 0xff, sizeof(int), s));
+  // first half kick and drift of the first step
+  // (in place: the pair history stays in the buffer of the particle state)
+  int ps = prof_begin(c);
+  StepArgs pa{c->step, d.cur, d.cur, 0};
+  launch_prologue<R>(d, pa, s);
+  prof_end(c, DEM_PROF_PROLOGUE, ps);
+  int buf = d.cur;           // buffer holding the drifted state of step c->step
+  if (c->force_rebuild) {
+    HIPCHK(hipStreamSynchronize(s));
+    c->h_flags[3] = (int)c->step;
+    HIPCHK(hipMemsetAsync(d.abort, 0xff, sizeof(int), s));
+    HIPCHK(hipMemcpyAsync(d.abort_step, c->h_flags + 3, sizeof(int), hipMemcpyHostToDevice, s));
+    c->force_rebuild = 0;
   }
+  int64_t t = c->step;
+  while (t < s_end) {
+    std::vector<int> bufs;
+    bufs.push_back(buf);
+    int64_t t1 = std::min<int64_t>(s_end, t + c->window);
+    for (int64_t q = t; q < t1; ++q) {
+      int b = bufs.back();
+      if (c->any_fluid && c->have_fluid && (q % d.couple_every) == 0) {
+        int pf = prof_begin(c);
+        launch_fluid<R>(d, b, s);
+        prof_end(c, DEM_PROF_FLUID, pf, q);
+      }
+      StepArgs a{q, b, 1 - b, q == s_end - 1 ? 1 : 0};
+      int pk = prof_begin(c);
+      launch_step<R>(d, a, s);
+      prof_end(c, DEM_PROF_STEP, pk, q);
+      bufs.push_back(1 - b);
+    }
+    dem_status rs = read_flags(c);
+    if (rs != DEM_OK) return rs;
+    int abort = c->h_flags[0], astep = c->h_flags[1], status = c->h_flags[2];
+    if (status) {
+      prof_collect(c);
+      return fault(c, status);
+    }
+    if (!abort) {
+      prof_collect(c);
+      buf = bufs.back();
+      t = t1;
+      continue;
+    }
+    // resume at the recorded step after a rebuild from the state before it
+    int64_t ta = astep;
+    if (ta < t || ta > t1) return fault(c, kStBadAbort);
+    prof_collect(c, ta);
+    buf = bufs[ta - t];
+    d.cur = buf;
+    HIPCHK(hipMemsetAsync(d.abort, 0, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(d.abort_step, 0xff, sizeof(int), s));
+    int pr = prof_begin(c);
+    dem_status st = rebuild<R>(c, 0, 0);
+    if (st != DEM_OK) return st;
+    prof_end(c, DEM_PROF_REBUILD, pr);
+    buf = d.cur;
+    t = ta;
+  }
+  d.cur = buf;
   HIPCHK(hipStreamSynchronize(s));
   prof_collect(c);
-  int st = 0;
-  HIPCHK(hipMemcpy(&st, d.status, sizeof(int), hipMemcpyDeviceToHost));
-  if (st) {
-    c->failed = st;
-    if (st & kStNonFinite) return DEM_E_NONFINITE;
-    if (st & kStCapacity) return DEM_E_CAPACITY;
-    return DEM_E_STATE;
-  }
+  c->step = s_end;
   return DEM_OK;
 }
 
@@ -581,54 +631,60 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   auto fail = [&](dem_status st) { dem_destroy(c); return st; };
   const int64_t R4B = 4 * (int64_t)c->rsz;
   bool ok = true;
-  ok &= dalloc(c, &d.xr, n) == hipSuccess && dalloc(c, &d.vel, n) == hipSuccess;
-  ok &= dalloc(c, &d.xr2, n) == hipSuccess && dalloc(c, &d.vel2, n) == hipSuccess;
+  for (int b = 0; b < 2; ++b) {
+    ok &= dalloc(c, &d.xr[b], n) == hipSuccess && dalloc(c, &d.vel[b], n) == hipSuccess;
+    ok &= dalloc_bytes(c, &d.omg[b], n * R4B) == hipSuccess;
+    ok &= dalloc(c, &d.alive[b], n) == hipSuccess;
+  }
   ok &= dalloc(c, &d.xref, n) == hipSuccess;
-  void** r4s[] = {&d.omg, &d.frc, &d.trq, &d.fdr, &d.omg2, &d.frc2, &d.trq2, &d.fdr2};
+  void** r4s[] = {&d.frc, &d.trq, &d.fdr, &d.t_r4[0], &d.t_r4[1], &d.t_r4[2]};
   for (void** q : r4s) ok &= dalloc_bytes(c, q, n * R4B) == hipSuccess;
-  ok &= dalloc(c, &d.alive, n) == hipSuccess && dalloc(c, &d.alive2, n) == hipSuccess;
-  ok &= dalloc(c, &d.sample, n) == hipSuccess && dalloc(c, &d.sample2, n) == hipSuccess;
-  ok &= dalloc(c, &d.orig, n) == hipSuccess && dalloc(c, &d.orig2, n) == hipSuccess;
+  ok &= dalloc(c, &d.sample, n) == hipSuccess && dalloc(c, &d.orig, n) == hipSuccess;
+  ok &= dalloc(c, &d.t_i[0], n) == hipSuccess && dalloc(c, &d.t_i[1], n) == hipSuccess;
   int64_t nbk = std::max<int64_t>(std::max<int64_t>(d.nbins_total, n), d.ndual) + 2;
   ok &= dalloc(c, &d.key, n) == hipSuccess;
   ok &= dalloc(c, &d.bucket_cnt, nbk) == hipSuccess && dalloc(c, &d.bucket_fill, nbk) == hipSuccess;
-  ok &= dalloc(c, &d.cell_start, nbk) == hipSuccess;
-  ok &= dalloc(c, &d.order, n) == hipSuccess && dalloc(c, &d.inv_order, n) == hipSuccess;
-  ok &= dalloc(c, &d.pcnt, n + 1) == hipSuccess && dalloc(c, &d.rcnt, n + 1) == hipSuccess;
-  ok &= dalloc(c, &d.rrow, n + 1) == hipSuccess && dalloc(c, &d.wcnt, n + 1) == hipSuccess;
+  ok &= dalloc(c, &d.cell_start, nbk) == hipSuccess && dalloc(c, &d.bin_sample, nbk) == hipSuccess;
+  ok &= dalloc(c, &d.order, n) == hipSuccess && dalloc(c, &d.order_tmp, n) == hipSuccess;
+  ok &= dalloc(c, &d.inv_order, n) == hipSuccess;
+  ok &= dalloc(c, &d.ncnt, n + 1) == hipSuccess && dalloc(c, &d.ocnt, n + 1) == hipSuccess;
+  ok &= dalloc(c, &d.wcnt, n + 1) == hipSuccess;
   for (int q = 0; q < 2; ++q) {
-    ok &= dalloc(c, &c->ps[q].prow, n + 1) == hipSuccess;
+    ok &= dalloc(c, &c->ns[q].nrow, n + 1) == hipSuccess;
+    ok &= dalloc(c, &c->ns[q].hrow, n + 1) == hipSuccess;
     ok &= dalloc(c, &c->ws[q].wrow, n + 1) == hipSuccess;
   }
   if (!ok) return fail(DEM_E_NOMEM);
   int64_t cap0 = params[0].pair_capacity > 0 ? params[0].pair_capacity : 4 * n + 1024;
   for (int q = 0; q < 2; ++q) {
-    if (grow_pairs(c, c->ps[q], cap0) != hipSuccess) return fail(DEM_E_NOMEM);
+    if (grow_nbr(c, c->ns[q], 2 * cap0, cap0) != hipSuccess) return fail(DEM_E_NOMEM);
     if (grow_walls(c, c->ws[q], n / 4 + 256) != hipSuccess) return fail(DEM_E_NOMEM);
   }
-  if (grow_records(c, cap0) != hipSuccess) return fail(DEM_E_NOMEM);
   // fluid
   int64_t nc = std::max<int64_t>(d.ncell, 1);
   ok &= dalloc(c, &d.cell_sample, nc) == hipSuccess;
   ok &= dalloc(c, &d.u_in, 3 * nc) == hipSuccess && dalloc(c, &d.gp_in, 3 * nc) == hipSuccess;
   ok &= dalloc(c, &d.cell_n, nc) == hipSuccess && dalloc(c, &d.cell_u, 3 * nc) == hipSuccess;
   ok &= dalloc(c, &d.eps, nc) == hipSuccess && dalloc(c, &d.fdc, 3 * nc) == hipSuccess;
+  ok &= dalloc(c, &d.dpart, 24 * (d.ndual + 1)) == hipSuccess;
   ok &= dalloc(c, &d.dkey, n) == hipSuccess && dalloc(c, &d.dfr, n) == hipSuccess;
   ok &= dalloc(c, &d.fpart, n) == hipSuccess && dalloc(c, &d.dmem, n) == hipSuccess;
+  ok &= dalloc(c, &d.dmem_tmp, n) == hipSuccess;
   ok &= dalloc(c, &d.dcnt, d.ndual + 2) == hipSuccess && dalloc(c, &d.doff, d.ndual + 2) == hipSuccess;
   ok &= dalloc(c, &d.dfill, d.ndual + 2) == hipSuccess;
   ok &= dalloc(c, &d.sc, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.broken, n_samples) == hipSuccess;
-  ok &= dalloc(c, &d.status, 1) == hipSuccess && dalloc(c, &d.rebuild_flag, 1) == hipSuccess;
+  ok &= dalloc(c, &d.status, 1) == hipSuccess && dalloc(c, &d.abort, 1) == hipSuccess;
+  ok &= dalloc(c, &d.abort_step, 1) == hipSuccess;
   ok &= dalloc(c, &d.scratch_i, 4) == hipSuccess;
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nbk, n + 1), d.ndual + 2);
   d.scan_tmp_n = scan_n / 256 + 4096;
   ok &= dalloc(c, &d.scan_tmp, d.scan_tmp_n) == hipSuccess;
   if (!ok) return fail(DEM_E_NOMEM);
-  if (hipHostMalloc((void**)&c->h_flag, sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(DEM_E_NOMEM);
+  if (hipHostMalloc((void**)&c->h_flags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(DEM_E_NOMEM);
   if (dalloc(c, &c->d_offsets, n_samples + 1) != hipSuccess) return fail(DEM_E_NOMEM);
 
-  // upload in the caller's order
+  // upload in the caller's order into buffer 0
   std::vector<double4> hx(n), hv(n);
   std::vector<int32_t> hs(n), ho(n);
   std::vector<char> hw(n * R4B), hF(n * R4B), hT(n * R4B);
@@ -652,81 +708,97 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
       }
     }
   }
-  std::vector<int32_t> cs(nc, 0);
-  for (int s = 0; s < n_samples; ++s)
+  std::vector<int32_t> cs(nc, 0), bs(nbk, 0);
+  for (int s = 0; s < n_samples; ++s) {
     if (params[s].fluid_on)
       for (int64_t q = 0; q < (int64_t)c->sc[s].gn[0] * c->sc[s].gn[1] * c->sc[s].gn[2]; ++q)
         cs[c->sc[s].cell_base + q] = s;
+    int64_t nbs = (int64_t)c->sc[s].bn[0] * c->sc[s].bn[1] * c->sc[s].bn[2] + 1;
+    for (int64_t q = 0; q < nbs; ++q) bs[c->sc[s].bin_base + q] = s;
+  }
   hipStream_t st = c->stream;
   bool up = true;
-  up &= hipMemcpyAsync(d.xr, hx.data(), sizeof(double4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-  up &= hipMemcpyAsync(d.vel, hv.data(), sizeof(double4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-  up &= hipMemcpyAsync(d.omg, hw.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
+  d.cur = 0;
+  up &= hipMemcpyAsync(d.xr[0], hx.data(), sizeof(double4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.vel[0], hv.data(), sizeof(double4) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.omg[0], hw.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.alive[0], alive.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.frc, hF.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.trq, hT.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemsetAsync(d.fdr, 0, n * R4B, st) == hipSuccess;
-  up &= hipMemcpyAsync(d.alive, alive.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.sample, hs.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.orig, ho.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.sc, c->sc.data(), sizeof(SampleConst) * n_samples, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.cell_sample, cs.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.bin_sample, bs.data(), sizeof(int32_t) * nbk, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(c->d_offsets, offs.data(), sizeof(int64_t) * (n_samples + 1), hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemsetAsync(d.broken, 0, sizeof(unsigned long long) * n_samples, st) == hipSuccess;
   up &= hipMemsetAsync(d.status, 0, sizeof(int), st) == hipSuccess;
-  up &= hipMemsetAsync(d.rebuild_flag, 0, sizeof(int), st) == hipSuccess;
+  up &= hipMemsetAsync(d.abort, 0, sizeof(int), st) == hipSuccess;
   up &= hipMemsetAsync(d.eps, 0, sizeof(double) * nc, st) == hipSuccess;
   up &= hipMemsetAsync(d.fdc, 0, sizeof(double) * 3 * nc, st) == hipSuccess;
   up &= hipMemsetAsync(d.u_in, 0, sizeof(double) * 3 * nc, st) == hipSuccess;
   up &= hipMemsetAsync(d.gp_in, 0, sizeof(double) * 3 * nc, st) == hipSuccess;
-  // the "old" list of the first build: the given history, CSR over caller indices
-  PairSet& old = c->ps[1];
+  // the "previous list" of the first build is the given history: full CSR rows
+  // over caller indices (both directions), one slot per pair
+  NbrSet& old = c->ns[1];
   WallSet& wold = c->ws[1];
+  c->hist_old = 0;
   {
-    std::vector<int32_t> prow(n + 1, 0), pj;
-    std::vector<uint8_t> pfl;
-    std::vector<char> ph;
     std::vector<std::pair<std::pair<int64_t, int64_t>, int64_t>> items;
     for (int64_t k = 0; k < np0; ++k) {
       int64_t a = hp[2 * k], b = hp[2 * k + 1];
       items.push_back({{std::min(a, b), std::max(a, b)}, k});
     }
     std::sort(items.begin(), items.end());
-    if (grow_pairs(c, old, (int64_t)items.size()) != hipSuccess) return fail(DEM_E_NOMEM);
-    pj.resize(items.size());
-    pfl.resize(items.size());
-    ph.assign(items.size() * R4B, 0);
-    for (size_t q = 0; q < items.size(); ++q) {
+    int64_t npair = (int64_t)items.size();
+    if (grow_nbr(c, old, 2 * npair, npair) != hipSuccess) return fail(DEM_E_NOMEM);
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> rows(n);   // (partner, slot)
+    std::vector<int32_t> sown(npair), spart(npair);
+    std::vector<uint8_t> pfl(npair);
+    std::vector<char> ph(npair * R4B, 0);
+    for (int64_t q = 0; q < npair; ++q) {
       int64_t a = items[q].first.first, b = items[q].first.second, k = items[q].second;
-      prow[a + 1]++;
-      pj[q] = (int32_t)b;
+      rows[a].push_back({(int32_t)b, (int32_t)q});
+      rows[b].push_back({(int32_t)a, (int32_t)q});
+      sown[q] = (int32_t)a;
+      spart[q] = (int32_t)b;
       double sg = hp[2 * k] < hp[2 * k + 1] ? 1.0 : -1.0;
       pfl[q] = hb.empty() ? 0 : (hb[k] ? 1 : 0);
       if (params[0].normal_model != DEM_NORMAL_JKR_MOD) pfl[q] = 0;
-      double t[3] = {0, 0, 0};
-      if (!hdt.empty()) for (int e = 0; e < 3; ++e) t[e] = sg * hdt[3 * k + e];
-      if (c->fp64) ((double4*)ph.data())[q] = make_double4(t[0], t[1], t[2], 0.0);
-      else ((float4*)ph.data())[q] = make_float4((float)t[0], (float)t[1], (float)t[2], 0.f);
+      double t3[3] = {0, 0, 0};
+      if (!hdt.empty()) for (int e = 0; e < 3; ++e) t3[e] = sg * hdt[3 * k + e];
+      if (c->fp64) ((double4*)ph.data())[q] = make_double4(t3[0], t3[1], t3[2], 0.0);
+      else ((float4*)ph.data())[q] = make_float4((float)t3[0], (float)t3[1], (float)t3[2], 0.f);
     }
-    for (int64_t i = 0; i < n; ++i) prow[i + 1] += prow[i];
-    up &= hipMemcpyAsync(old.prow, prow.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st) == hipSuccess;
-    if (!items.empty()) {
-      up &= hipMemcpyAsync(old.pj, pj.data(), sizeof(int32_t) * pj.size(), hipMemcpyHostToDevice, st) == hipSuccess;
-      up &= hipMemcpyAsync(old.pfl, pfl.data(), pfl.size(), hipMemcpyHostToDevice, st) == hipSuccess;
-      up &= hipMemcpyAsync(old.hdt, ph.data(), ph.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    std::vector<int32_t> nrow(n + 1, 0), nbr, nslot;
+    for (int64_t i = 0; i < n; ++i) {
+      std::sort(rows[i].begin(), rows[i].end());
+      nrow[i + 1] = nrow[i] + (int32_t)rows[i].size();
+      for (auto& e : rows[i]) { nbr.push_back(e.first); nslot.push_back(e.second); }
     }
-    old.n = (int64_t)items.size();
+    up &= hipMemcpyAsync(old.nrow, nrow.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st) == hipSuccess;
+    if (npair > 0) {
+      up &= hipMemcpyAsync(old.nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(old.nslot, nslot.data(), sizeof(int32_t) * nslot.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(old.sown, sown.data(), sizeof(int32_t) * npair, hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(old.spart, spart.data(), sizeof(int32_t) * npair, hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(old.pfl[0], pfl.data(), npair, hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(old.hdt[0], ph.data(), ph.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    }
+    old.nent = (int64_t)nbr.size();
+    old.nslots = npair;
     up &= hipMemsetAsync(wold.wrow, 0, sizeof(int32_t) * (n + 1), st) == hipSuccess;
     wold.n = 0;
     up &= hipStreamSynchronize(st) == hipSuccess;
   }
   if (!up) return fail(DEM_E_DEVICE);
-  c->cur = 0;
+  c->live = 0;
   bind_sets(c);
   int mark = (np0 == 0 && params[0].bond_at_init) ? 1 : 0;
   dem_status rs = c->fp64 ? rebuild<double>(c, 1, mark) : rebuild<float>(c, 1, mark);
   if (rs != DEM_OK) return fail(rs);
   if (hipStreamSynchronize(st) != hipSuccess) return fail(DEM_E_DEVICE);
-  c->force_rebuild = 0;
   *out = c;
   return DEM_OK;
 }
@@ -767,7 +839,7 @@ static dem_status aggregates(dem_ctx* c, std::vector<double>& pm, std::vector<do
   dke = dpm + ns;
   dnc = (long long*)(dke + ns);
   dna = dnc + ns;
-  launch_aggregate_impl(c->d, c->d_offsets, dpm, dke, dnc, dna, c->fp64, c->stream);
+  launch_aggregate_impl(c->d, c->d_offsets, dpm, dke, dnc, dna, nullptr, c->fp64, c->stream);
   pm.resize(ns); ke.resize(ns); nc.resize(ns); na.resize(ns); br.resize(ns);
   bool ok = hipStreamSynchronize(c->stream) == hipSuccess;
   ok &= hipMemcpy(pm.data(), dpm, sizeof(double) * ns, hipMemcpyDeviceToHost) == hipSuccess;
@@ -848,20 +920,21 @@ dem_status dem_read_pairs(dem_ctx* c, int32_t which, int64_t cap, int64_t* pair_
   if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
   HIPCHK(hipStreamSynchronize(c->stream));
   DevState& d = c->d;
-  int64_t np = d.npairs;
+  int64_t np = d.nslots;
   std::vector<int32_t> own(np), pj(np), orig(d.n);
-  std::vector<uint8_t> fl(np);
+  std::vector<uint8_t> fl(np), al(d.n);
   std::vector<char> h(np * 4 * c->rsz);
   std::vector<double4> xr(d.n);
   if (np > 0) {
-    HIPCHK(hipMemcpy(own.data(), d.pown, sizeof(int32_t) * np, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(pj.data(), d.pj, sizeof(int32_t) * np, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(fl.data(), d.pfl, np, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(h.data(), d.hdt, h.size(), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(own.data(), d.sown, sizeof(int32_t) * np, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(pj.data(), d.spart, sizeof(int32_t) * np, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(fl.data(), d.pfl[d.cur], np, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(h.data(), d.hdt[d.cur], h.size(), hipMemcpyDeviceToHost));
   }
   if (d.n > 0) {
     HIPCHK(hipMemcpy(orig.data(), d.orig, sizeof(int32_t) * d.n, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(xr.data(), d.xr, sizeof(double4) * d.n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(xr.data(), d.xr[d.cur], sizeof(double4) * d.n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(al.data(), d.alive[d.cur], d.n, hipMemcpyDeviceToHost));
   }
   std::vector<int64_t> oi;
   std::vector<double> odt;
@@ -869,7 +942,8 @@ dem_status dem_read_pairs(dem_ctx* c, int32_t which, int64_t cap, int64_t* pair_
   for (int64_t p = 0; p < np; ++p) {
     int32_t i = own[p], j = pj[p];
     bool take;
-    if (which == 2) take = true;
+    if (!al[i] || !al[j]) take = false;
+    else if (which == 2) take = true;
     else if (which == 0) take = (fl[p] & 3) != 0;
     else {
       double dx = xr[j].x - xr[i].x, dy = xr[j].y - xr[i].y, dz = xr[j].z - xr[i].z;
@@ -883,19 +957,19 @@ dem_status dem_read_pairs(dem_ctx* c, int32_t which, int64_t cap, int64_t* pair_
     if (a > b) { std::swap(a, b); sg = -1.0; }
     oi.push_back(a);
     oi.push_back(b);
-    double t[3];
-    if (c->fp64) { double4 q = ((double4*)h.data())[p]; t[0] = q.x; t[1] = q.y; t[2] = q.z; }
-    else { float4 q = ((float4*)h.data())[p]; t[0] = q.x; t[1] = q.y; t[2] = q.z; }
-    for (int e = 0; e < 3; ++e) odt.push_back(sg * t[e]);
+    double t3[3];
+    if (c->fp64) { double4 q = ((double4*)h.data())[p]; t3[0] = q.x; t3[1] = q.y; t3[2] = q.z; }
+    else { float4 q = ((float4*)h.data())[p]; t3[0] = q.x; t3[1] = q.y; t3[2] = q.z; }
+    for (int e = 0; e < 3; ++e) odt.push_back(sg * t3[e]);
     ob.push_back(fl[p] & 1);
   }
   int64_t cnt = (int64_t)ob.size();
   if (n_out) *n_out = cnt;
-  int64_t w = std::min(cnt, cap);
-  if (w > 0) {
-    if (pair_idx) HIPCHK(hipMemcpy(pair_idx, oi.data(), sizeof(int64_t) * 2 * w, hipMemcpyDefault));
-    if (pair_dt) HIPCHK(hipMemcpy(pair_dt, odt.data(), sizeof(double) * 3 * w, hipMemcpyDefault));
-    if (pair_bonded) HIPCHK(hipMemcpy(pair_bonded, ob.data(), w, hipMemcpyDefault));
+  int64_t wr = std::min(cnt, cap);
+  if (wr > 0) {
+    if (pair_idx) HIPCHK(hipMemcpy(pair_idx, oi.data(), sizeof(int64_t) * 2 * wr, hipMemcpyDefault));
+    if (pair_dt) HIPCHK(hipMemcpy(pair_dt, odt.data(), sizeof(double) * 3 * wr, hipMemcpyDefault));
+    if (pair_bonded) HIPCHK(hipMemcpy(pair_bonded, ob.data(), wr, hipMemcpyDefault));
   }
   return DEM_OK;
 }
@@ -904,8 +978,8 @@ dem_status dem_info(dem_ctx* c, int64_t* ncell, int64_t* n_pairs, int64_t* pair_
                     double* cutoff_margin) {
   if (!c) return DEM_E_INVAL;
   if (ncell) *ncell = c->d.ncell;
-  if (n_pairs) *n_pairs = c->d.npairs;
-  if (pair_capacity) *pair_capacity = c->d.pair_cap;
+  if (n_pairs) *n_pairs = c->d.nslots;
+  if (pair_capacity) *pair_capacity = c->d.slot_cap;
   if (rebuilds) *rebuilds = c->rebuilds;
   if (cutoff_margin) *cutoff_margin = c->sc[0].margin;
   return DEM_OK;
@@ -931,6 +1005,12 @@ dem_status dem_read_profile(dem_ctx* c, double* total_ms, int64_t* launches) {
   return DEM_OK;
 }
 
+dem_status dem_read_fault(dem_ctx* c, int32_t* bits) {
+  if (!c || !bits) return DEM_E_INVAL;
+  *bits = c->failed;
+  return DEM_OK;
+}
+
 dem_status dem_request_rebuild(dem_ctx* c) {
   if (!c) return DEM_E_INVAL;
   c->force_rebuild = 1;
@@ -946,7 +1026,7 @@ void dem_destroy(dem_ctx* c) {
     if (p) (void)hipFree(p);
   if (c->stage) (void)hipFree(c->stage);
   if (c->stage_alive) (void)hipFree(c->stage_alive);
-  if (c->h_flag) (void)hipHostFree(c->h_flag);
+  if (c->h_flags) (void)hipHostFree(c->h_flags);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }

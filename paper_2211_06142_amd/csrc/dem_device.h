@@ -1,0 +1,234 @@
+// dem_device.h -- device functions shared by the kernels: binning, wall
+// geometry, and the contact law of one pair (arXiv:2211.06142 sections
+// 2.1, 2.3, 2.4).
+#pragma once
+#include <math.h>
+
+#include "dem_internal.h"
+
+namespace dem {
+
+constexpr int kBlock = 256;
+static inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+template <typename R> __device__ inline R4<R> mk4(R a, R b, R c, R d) {
+  R4<R> v;
+  v.x = a; v.y = b; v.z = c; v.w = d;
+  return v;
+}
+
+template <typename R> __device__ inline R rcbrt_(R x);
+template <> __device__ inline double rcbrt_<double>(double x) { return cbrt(x); }
+template <> __device__ inline float rcbrt_<float>(float x) { return cbrtf(x); }
+template <typename R> __device__ inline R rsqrt_(R x);
+template <> __device__ inline double rsqrt_<double>(double x) { return sqrt(x); }
+template <> __device__ inline float rsqrt_<float>(float x) { return sqrtf(x); }
+
+__device__ inline int bin_coord(double x, double lo, double h, int n) {
+  double q = floor((x - lo) / h);
+  if (q < 0.0) return 0;
+  if (q > (double)(n - 1)) return n - 1;
+  return (int)q;
+}
+
+// signed distance from the wall surface (positive on the particle side) and
+// the unit normal pointing into the particle side
+__device__ inline bool wall_geom(const Wall& w, double x, double y, double z, double& sd, double nw[3]) {
+  if (w.kind == DEM_WALL_PLANE) {
+    nw[0] = w.p[0]; nw[1] = w.p[1]; nw[2] = w.p[2];
+    sd = ((nw[0] * x + nw[1] * y) + nw[2] * z) - w.p[3];
+    return true;
+  }
+  double ex = x - w.p[0], ey = y - w.p[1];
+  double rho = sqrt(ex * ex + ey * ey);
+  if (rho == 0.0) return false;
+  if (w.kind == DEM_WALL_CYL_IN) {
+    sd = w.p[2] - rho;
+    nw[0] = -ex / rho; nw[1] = -ey / rho; nw[2] = 0.0;
+  } else {
+    sd = rho - w.p[2];
+    nw[0] = ex / rho; nw[1] = ey / rho; nw[2] = 0.0;
+  }
+  return true;
+}
+
+// Contact radius and elastic force of a bonded JKR contact (eq 12-13).  With
+// X^3 = pi^2 gamma^2 R* / E*^2, a0 = sqrt(X R*), delta = X D and a = a0 b^2,
+// eq 13 becomes b^4 - 2 b = D and eq 12 F = pi gamma R* (4/3 b^6 - 4 b^3).
+// The branch through point C (b_C^3 = 3/2) is taken: two fixed-point steps of
+// b = (D + 2b)^(1/4) from b_C, then Newton on the convex increasing quartic.
+template <typename R>
+__device__ inline void jkr_bonded(R delta, R Rs, R gam, R jkrK, R& a, R& Fel) {
+  constexpr R kPi = (R)3.14159265358979323846;
+  constexpr R kbC = (R)1.1447142425533319;   // (3/2)^(1/3)
+  constexpr int kNewton = sizeof(R) == 8 ? 3 : 2;
+  R X = rcbrt_<R>(jkrK * Rs);
+  R D = delta / X;
+  R b = rsqrt_<R>(rsqrt_<R>(D + (R)2 * kbC));
+  b = rsqrt_<R>(rsqrt_<R>(D + (R)2 * b));
+#pragma unroll
+  for (int it = 0; it < kNewton; ++it) {
+    R b3 = b * b * b;
+    R f = b3 * b - (R)2 * b - D;
+    R fp = (R)4 * b3 - (R)2;
+    b -= f / fp;
+  }
+  R b3 = b * b * b;
+  R u = kPi * gam * Rs;
+  Fel = u * ((R)4 / (R)3) * b3 * b3 - u * (R)4 * b3;
+  a = rsqrt_<R>(X * Rs) * b * b;
+}
+
+template <typename R> struct LawOut {
+  R F[3], c[3], Tr[3];
+};
+
+// One contact (section 2.1 eq 3-5, section 2.3 eq 12-13, section 2.4 eq 32-35).
+// n: unit normal from the body to its partner; vrel: contact-point velocity of
+// the body relative to the partner; wrel: relative angular velocity; hdt:
+// tangential elongation (in/out).  Output: force on the body, n x F_t (the
+// torque on each body is its radius times this), rolling torque on the body.
+template <typename R>
+__device__ inline void contact_law(const SampleConst& c, int bonded, R delta, R Rs, R ms, R gam, R jkrK,
+                                   const R n[3], const R vrel[3], const R wrel[3], R hdt[3], R dt,
+                                   bool rolling, LawOut<R>& o) {
+  R a, Fel, kn, kt, etan, etat, L;
+  if (c.normal_model == DEM_NORMAL_LINEAR) {
+    kn = (R)c.k_lin;
+    Fel = kn * delta;
+    kt = ((R)2 / (R)7) * kn;
+    etan = (R)2 * (R)c.beta * rsqrt_<R>(kn * ms);
+    etat = (R)2 * (R)c.beta * rsqrt_<R>(kt * ms);
+    L = (R)c.mu * Fel;
+  } else {
+    if (bonded && gam > (R)0) {
+      jkr_bonded<R>(delta, Rs, gam, jkrK, a, Fel);
+      L = (R)c.mu * (Fel + (R)2 * ((R)3 * (R)3.14159265358979323846 * gam * Rs));
+    } else {
+      a = rsqrt_<R>(Rs * (delta > (R)0 ? delta : (R)0));
+      Fel = (R)4 * (R)c.Es * a * a * a / ((R)3 * Rs);
+      L = (R)c.mu * Fel;
+    }
+    kn = (R)2 * (R)c.Es * a;
+    kt = (R)8 * (R)c.Gs * a;
+    etan = (R)c.cdamp * rsqrt_<R>(kn * ms);
+    etat = (R)c.cdamp * rsqrt_<R>(kt * ms);
+  }
+  R vn = (vrel[0] * n[0] + vrel[1] * n[1]) + vrel[2] * n[2];
+  R vt[3] = {vrel[0] - vn * n[0], vrel[1] - vn * n[1], vrel[2] - vn * n[2]};
+  R Fn = Fel + etan * vn;
+  // rotate the stored elongation into the tangent plane, keep its length
+  R old = rsqrt_<R>((hdt[0] * hdt[0] + hdt[1] * hdt[1]) + hdt[2] * hdt[2]);
+  R dn = (hdt[0] * n[0] + hdt[1] * n[1]) + hdt[2] * n[2];
+  R tp[3] = {hdt[0] - dn * n[0], hdt[1] - dn * n[1], hdt[2] - dn * n[2]};
+  R tpl = rsqrt_<R>((tp[0] * tp[0] + tp[1] * tp[1]) + tp[2] * tp[2]);
+  if (tpl > (R)0) {
+    R f = old / tpl;
+    hdt[0] = tp[0] * f; hdt[1] = tp[1] * f; hdt[2] = tp[2] * f;
+  } else {
+    hdt[0] = hdt[1] = hdt[2] = (R)0;
+  }
+  hdt[0] += vt[0] * dt; hdt[1] += vt[1] * dt; hdt[2] += vt[2] * dt;
+  R Ft[3] = {-kt * hdt[0] - etat * vt[0], -kt * hdt[1] - etat * vt[1], -kt * hdt[2] - etat * vt[2]};
+  R ftm = rsqrt_<R>((Ft[0] * Ft[0] + Ft[1] * Ft[1]) + Ft[2] * Ft[2]);
+  if (ftm > L) {
+    R s = L / ftm;
+    Ft[0] *= s; Ft[1] *= s; Ft[2] *= s;
+    if (kt > (R)0) {
+      hdt[0] = -(Ft[0] + etat * vt[0]) / kt;
+      hdt[1] = -(Ft[1] + etat * vt[1]) / kt;
+      hdt[2] = -(Ft[2] + etat * vt[2]) / kt;
+    } else {
+      hdt[0] = hdt[1] = hdt[2] = (R)0;
+    }
+  }
+  o.F[0] = -Fn * n[0] + Ft[0];
+  o.F[1] = -Fn * n[1] + Ft[1];
+  o.F[2] = -Fn * n[2] + Ft[2];
+  o.c[0] = n[1] * Ft[2] - n[2] * Ft[1];
+  o.c[1] = n[2] * Ft[0] - n[0] * Ft[2];
+  o.c[2] = n[0] * Ft[1] - n[1] * Ft[0];
+  o.Tr[0] = o.Tr[1] = o.Tr[2] = (R)0;
+  if (rolling && c.mu_roll > 0.0) {
+    R wn = (wrel[0] * n[0] + wrel[1] * n[1]) + wrel[2] * n[2];
+    R wr[3] = {wrel[0] - wn * n[0], wrel[1] - wn * n[1], wrel[2] - wn * n[2]};
+    R wm = rsqrt_<R>((wr[0] * wr[0] + wr[1] * wr[1]) + wr[2] * wr[2]);
+    if (wm > (R)0) {
+      R tm = (R)c.mu_roll * Rs * (Fel < (R)0 ? -Fel : Fel) / wm;
+      o.Tr[0] = -tm * wr[0]; o.Tr[1] = -tm * wr[1]; o.Tr[2] = -tm * wr[2];
+    }
+  }
+}
+
+// Bond persistence down to the pull-off overlap of point C (Table 1, Fig. 2),
+// written with cubes so that no cube root enters the decision:
+// (-delta)^3 <= (3/16) pi^2 gamma^2 R* / E*^2.  Same operation order as the
+// FP64 reference definition; called only for bonded pairs that do not touch.
+__device__ inline bool bond_holds_apart(double d2, double cs, double Rsd, double gam, double Es) {
+  double sep = sqrt(d2) - cs;
+  double lhs = (sep * sep) * sep;
+  double rhs = ((3.0 / 16.0) * (M_PI * M_PI)) * (gam * gam) * Rsd / (Es * Es);
+  return lhs <= rhs;
+}
+
+// Result of one half pair in its canonical orientation (a = lower sorted
+// index, n from a to b): force on a, n x F_t, rolling torque on a.
+template <typename R> struct PairOut {
+  LawOut<R> o;
+  R4<R> h;
+  uint8_t fl;
+  bool active;   // contributes a force
+  bool broke;    // the bond broke this step
+};
+
+template <typename R>
+__device__ inline void pair_eval(const SampleConst& c, double dt, bool rolling, const double4& A, const double4& B,
+                                 const double4& VA, const double4& VB, const R4<R>& WA, const R4<R>& WB,
+                                 double gam, R4<R> h4, uint8_t fl, PairOut<R>& out) {
+  out.active = false;
+  out.broke = false;
+  const double dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
+  const double d2 = (dx * dx + dy * dy) + dz * dz;
+  const double cs = A.w + B.w;
+  const double Rsd = A.w * B.w / (A.w + B.w);
+  const bool touching = d2 < cs * cs;
+  const int bonded = fl & 1;
+  if (bonded && !touching && !bond_holds_apart(d2, cs, Rsd, gam, c.Es)) {
+    out.broke = true;
+    out.h = mk4<R>(0, 0, 0, 0);
+    out.fl = 0;
+    return;
+  }
+  if (!bonded && !touching) {
+    out.h = mk4<R>(0, 0, 0, 0);
+    out.fl = 0;
+    return;
+  }
+  R delta, n[3];
+  if (sizeof(R) == 8) {
+    const double dist = sqrt(d2);
+    delta = (R)(cs - dist);
+    n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
+  } else {
+    // overlap from the FP64 difference of squares, normal in FP32
+    const R dist = rsqrt_<R>((R)d2);
+    delta = (R)(cs * cs - d2) / ((R)cs + dist);
+    const R inv = (R)1 / dist;
+    n[0] = (R)dx * inv; n[1] = (R)dy * inv; n[2] = (R)dz * inv;
+  }
+  const R ra = (R)A.w, rb = (R)B.w;
+  const R ws[3] = {ra * WA.x + rb * WB.x, ra * WA.y + rb * WB.y, ra * WA.z + rb * WB.z};
+  const R vrel[3] = {(R)(VA.x - VB.x) + (ws[1] * n[2] - ws[2] * n[1]),
+                     (R)(VA.y - VB.y) + (ws[2] * n[0] - ws[0] * n[2]),
+                     (R)(VA.z - VB.z) + (ws[0] * n[1] - ws[1] * n[0])};
+  const R wrel[3] = {WA.x - WB.x, WA.y - WB.y, WA.z - WB.z};
+  const R ms = (R)(1.0 / (VA.w + VB.w));
+  R h[3] = {h4.x, h4.y, h4.z};
+  const R jkrK = (R)((M_PI * M_PI) * (gam * gam) / (c.Es * c.Es));
+  contact_law<R>(c, bonded, delta, (R)Rsd, ms, (R)gam, jkrK, n, vrel, wrel, h, (R)dt, rolling, out.o);
+  out.h = mk4<R>(h[0], h[1], h[2], (R)0);
+  out.fl = (uint8_t)(bonded | (touching ? 2 : 0));
+  out.active = true;
+}
+
+}  // namespace dem

@@ -1,0 +1,133 @@
+// dem_sort.hip -- exclusive scan and the stable bucket sort used by the
+// neighbour-list rebuild (bucket = binning cell) and by the coupling (bucket =
+// cell of the grid of fluid-cell centres).  The order produced is a function
+// of the keys and tie-break values only, never of scheduling.
+#include "dem_device.h"
+
+namespace dem {
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32, three phases; in and out may alias
+// ---------------------------------------------------------------------------
+__global__ void k_scan_block(const int32_t* in, int32_t* out, int64_t n, int32_t* bsum) {
+  __shared__ int32_t sh[256];
+  const int64_t base = (int64_t)blockIdx.x * 1024;
+  const int t = threadIdx.x;
+  int32_t v[4];
+  int32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int64_t idx = base + t * 4 + k;
+    v[k] = idx < n ? in[idx] : 0;
+    s += v[k];
+  }
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int32_t a = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  int32_t run = sh[t] - s;
+  if (t == 255) bsum[blockIdx.x] = sh[255];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int64_t idx = base + t * 4 + k;
+    if (idx < n) out[idx] = run;
+    run += v[k];
+  }
+}
+
+__global__ void k_scan_add(int32_t* out, int64_t n, const int32_t* bpre) {
+  int64_t idx = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  int32_t add = bpre[blockIdx.x];
+  for (int k = 0; k < 4; ++k, idx += 256)
+    if (idx < n) out[idx] += add;
+}
+
+void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t nb = (n + 1023) / 1024;
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(256), 0, s, in, out, n, tmp);
+  if (nb > 1) {
+    scan_exclusive(tmp, tmp + nb, nb, tmp + 2 * nb, s);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(256), 0, s, out, n, tmp + nb);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stable bucket sort: count, scan, scatter to arbitrary slots, then rank every
+// bucket's members by (tiebreak, index) -- one wavefront per bucket, members
+// staged in LDS when the bucket holds at most 64 of them
+// ---------------------------------------------------------------------------
+__global__ void k_bucket_count(const uint32_t* key, int64_t n, int32_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[key[i]], 1);
+}
+
+__global__ void k_bucket_scatter(const uint32_t* key, int64_t n, const int32_t* off, int32_t* fill,
+                                 int32_t* order) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t k = key[i];
+  int32_t slot = atomicAdd(&fill[k], 1);
+  order[off[k] + slot] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t nb, const int32_t* src,
+                                                     const int32_t* tiebreak, int32_t* dst) {
+  __shared__ int32_t sm[4][64];
+  __shared__ int32_t sk[4][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + w;
+  int32_t lo = 0, k = 0;
+  if (b < nb) {
+    lo = off[b];
+    k = off[b + 1] - lo;
+  }
+  const bool small = k <= 64;
+  if (small && lane < k) {
+    int32_t v = src[lo + lane];
+    sm[w][lane] = v;
+    sk[w][lane] = tiebreak ? tiebreak[v] : v;
+  }
+  __syncthreads();
+  if (b >= nb || k == 0) return;
+  if (small) {
+    if (lane < k) {
+      int32_t v = sm[w][lane], kv = sk[w][lane], rank = 0;
+      for (int u = 0; u < k; ++u) {
+        int32_t ku = sk[w][u];
+        rank += (ku < kv || (ku == kv && sm[w][u] < v)) ? 1 : 0;
+      }
+      dst[lo + rank] = v;
+    }
+  } else {
+    for (int32_t t = lane; t < k; t += 64) {
+      int32_t v = src[lo + t];
+      int32_t kv = tiebreak ? tiebreak[v] : v;
+      int32_t rank = 0;
+      for (int32_t u = 0; u < k; ++u) {
+        int32_t x = src[lo + u];
+        int32_t ku = tiebreak ? tiebreak[x] : x;
+        rank += (ku < kv || (ku == kv && x < v)) ? 1 : 0;
+      }
+      dst[lo + rank] = v;
+    }
+  }
+}
+
+void launch_bucket_sort(const uint32_t* key, int64_t n, int64_t nb, const int32_t* tiebreak, int32_t* cnt,
+                        int32_t* off, int32_t* fill, int32_t* order_tmp, int32_t* out_order,
+                        int32_t* scan_tmp, hipStream_t s) {
+  (void)hipMemsetAsync(cnt, 0, sizeof(int32_t) * (nb + 1), s);
+  (void)hipMemsetAsync(fill, 0, sizeof(int32_t) * (nb + 1), s);
+  if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt);
+  scan_exclusive(cnt, off, nb + 1, scan_tmp, s);
+  if (n > 0)
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, off, fill, order_tmp);
+  hipLaunchKernelGGL(k_bucket_rank, dim3(nblk(nb, 4)), dim3(256), 0, s, off, nb, order_tmp, tiebreak, out_order);
+}
+
+}  // namespace dem

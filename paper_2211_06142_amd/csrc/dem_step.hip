@@ -1,0 +1,222 @@
+// dem_step.hip -- the fused DEM step.
+//
+// k_prologue: first half kick and drift of the first step of a call (eq 1-2,
+// velocity Verlet), outlet removal, rebuild trigger.
+// k_step: one thread per particle.  The particle walks its full neighbour row
+// and evaluates every contact in the pair's canonical orientation (owner =
+// lower sorted index, n from owner to partner), so both partners compute the
+// bit-identical pair force and Newton's third law holds exactly without
+// atomics or force records; only the owner writes the pair's new history.
+// Then walls, gravity, the held fluid force, the second half kick, and -
+// unless the step ends the call - the next step's first half kick, drift,
+// outlet removal and rebuild trigger.  State and pair history are read from
+// buffer `in` and written to buffer `out`.
+#include "dem_device.h"
+
+namespace dem {
+
+template <typename R>
+__device__ inline void finish_drift(DevState& d, const SampleConst& c, int64_t i, int out, int64_t next_step,
+                                    double4 p, double4 v, R4<R> w) {
+  const double dt = d.dt;
+  double sx = dt * v.x, sy = dt * v.y, sz = dt * v.z;
+  p.x += sx; p.y += sy; p.z += sz;
+  const double hs = 0.5 * c.skin;
+  if ((sx * sx + sy * sy) + sz * sz >= hs * hs) {
+    atomicOr(d.status, (int)kStTooFast);
+    atomicOr(d.abort, 1);
+  }
+  d.xr[out][i] = p;
+  d.vel[out][i] = v;
+  ((R4<R>*)d.omg[out])[i] = w;
+  uint8_t alive = 1;
+  if (c.outlet_kind == DEM_OUTLET_CAVITY) {
+    double ex = p.x - c.outlet[0], ey = p.y - c.outlet[1];
+    double rc = c.outlet[2];
+    if (ex * ex + ey * ey < rc * rc) {
+      alive = 0;
+      ((R4<R>*)d.frc)[i] = mk4<R>(0, 0, 0, 0);
+      ((R4<R>*)d.trq)[i] = mk4<R>(0, 0, 0, 0);
+    }
+  }
+  d.alive[out][i] = alive;
+  if (alive) {
+    double4 q = d.xref[i];
+    double ux = p.x - q.x, uy = p.y - q.y, uz = p.z - q.z;
+    if ((ux * ux + uy * uy) + uz * uz > hs * hs) {
+      atomicOr(d.abort, 1);
+      atomicMax(d.abort_step, (int)next_step);
+    }
+  }
+}
+
+template <typename R>
+__global__ void k_prologue(DevState d, StepArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const int in = a.in, out = a.out;
+  double4 p = d.xr[in][i];
+  double4 v = d.vel[in][i];
+  R4<R> w = ((const R4<R>*)d.omg[in])[i];
+  if (!d.alive[in][i]) {
+    d.xr[out][i] = p;
+    d.vel[out][i] = v;
+    ((R4<R>*)d.omg[out])[i] = w;
+    d.alive[out][i] = 0;
+    return;
+  }
+  const SampleConst& c = d.sc[d.sample[i]];
+  const R4<R> F = ((const R4<R>*)d.frc)[i];
+  const R4<R> T = ((const R4<R>*)d.trq)[i];
+  const double hdt = 0.5 * d.dt;
+  v.x += hdt * (double)F.x * v.w;
+  v.y += hdt * (double)F.y * v.w;
+  v.z += hdt * (double)F.z * v.w;
+  const R hdtR = (R)hdt;
+  w.x += hdtR * T.x * w.w;
+  w.y += hdtR * T.y * w.w;
+  w.z += hdtR * T.z * w.w;
+  finish_drift<R>(d, c, i, out, a.step, p, v, w);
+}
+
+template <typename R> void launch_prologue(DevState& d, StepArgs a, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, a);
+}
+template void launch_prologue<double>(DevState&, StepArgs, hipStream_t);
+template void launch_prologue<float>(DevState&, StepArgs, hipStream_t);
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
+  if (*d.abort) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const int in = a.in, out = a.out;
+  const double4* X = d.xr[in];
+  const double4* V = d.vel[in];
+  const R4<R>* W = (const R4<R>*)d.omg[in];
+  const uint8_t* AL = d.alive[in];
+  const double4 pi = X[i];
+  double4 v = V[i];
+  R4<R> w = W[i];
+  if (!AL[i]) {
+    d.xr[out][i] = pi;
+    d.vel[out][i] = v;
+    ((R4<R>*)d.omg[out])[i] = w;
+    d.alive[out][i] = 0;
+    return;
+  }
+  const int s = d.sample[i];
+  const SampleConst& c = d.sc[s];
+  const R4<R>* Hin = (const R4<R>*)d.hdt[in];
+  R4<R>* Hout = (R4<R>*)d.hdt[out];
+  const uint8_t* Fin = d.pfl[in];
+  uint8_t* Fout = d.pfl[out];
+  const bool rolling = d.rolling != 0;
+  const R r = (R)pi.w;
+  R F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  const double ci = d.ccoh ? d.ccoh[i] : 1.0;
+  const int32_t e1 = d.nrow[i + 1];
+  for (int32_t e = d.nrow[i]; e < e1; ++e) {
+    const int32_t j = d.nbr[e];
+    const int32_t p = d.nslot[e];
+    const bool own = j > (int32_t)i;
+    if (!AL[j]) {
+      if (own) {
+        Hout[p] = mk4<R>(0, 0, 0, 0);
+        Fout[p] = 0;
+      }
+      continue;
+    }
+    const double4 pj = X[j];
+    const double4 vj = V[j];
+    const R4<R> wj = W[j];
+    double gam = c.gamma;
+    if (d.ccoh) gam = c.gamma * sqrt(ci * d.ccoh[j]);
+    PairOut<R> po;
+    if (own) pair_eval<R>(c, d.dt, rolling, pi, pj, v, vj, w, wj, gam, Hin[p], Fin[p], po);
+    else pair_eval<R>(c, d.dt, rolling, pj, pi, vj, v, wj, w, gam, Hin[p], Fin[p], po);
+    if (own) {
+      Hout[p] = po.h;
+      Fout[p] = po.fl;
+      if (po.broke) atomicAdd(&d.broken[s], 1ull);
+    }
+    if (!po.active) continue;
+    const R sg = own ? (R)1 : (R)-1;
+    F[0] += sg * po.o.F[0]; F[1] += sg * po.o.F[1]; F[2] += sg * po.o.F[2];
+    T[0] += r * po.o.c[0] + sg * po.o.Tr[0];
+    T[1] += r * po.o.c[1] + sg * po.o.Tr[1];
+    T[2] += r * po.o.c[2] + sg * po.o.Tr[2];
+  }
+  // walls: Hertz with R* = r and m* = m (rigid, static)
+  const double m = c.rho * (4.0 / 3.0) * M_PI * pi.w * pi.w * pi.w;
+  for (int32_t e = d.wrow[i]; e < d.wrow[i + 1]; ++e) {
+    R4<R> h4 = ((const R4<R>*)d.wdt)[e];
+    double sd, nw[3];
+    const Wall& wl = c.walls[d.wid[e]];
+    if (!wall_geom(wl, pi.x, pi.y, pi.z, sd, nw) || !(sd < pi.w)) {
+      ((R4<R>*)d.wdt)[e] = mk4<R>(0, 0, 0, 0);
+      d.wfl[e] = 0;
+      continue;
+    }
+    const R delta = (R)(pi.w - sd);
+    const R n[3] = {(R)(-nw[0]), (R)(-nw[1]), (R)(-nw[2])};
+    const R wr[3] = {r * w.x, r * w.y, r * w.z};
+    const R vrel[3] = {(R)v.x + (wr[1] * n[2] - wr[2] * n[1]), (R)v.y + (wr[2] * n[0] - wr[0] * n[2]),
+                       (R)v.z + (wr[0] * n[1] - wr[1] * n[0])};
+    const R wrel[3] = {w.x, w.y, w.z};
+    R h[3] = {h4.x, h4.y, h4.z};
+    LawOut<R> o;
+    contact_law<R>(c, 0, delta, r, (R)m, (R)0, (R)0, n, vrel, wrel, h, (R)d.dt, true, o);
+    F[0] += o.F[0]; F[1] += o.F[1]; F[2] += o.F[2];
+    T[0] += r * o.c[0] + o.Tr[0];
+    T[1] += r * o.c[1] + o.Tr[1];
+    T[2] += r * o.c[2] + o.Tr[2];
+    ((R4<R>*)d.wdt)[e] = mk4<R>(h[0], h[1], h[2], (R)0);
+    d.wfl[e] = 2;
+  }
+  F[0] += (R)(m * c.g[0]);
+  F[1] += (R)(m * c.g[1]);
+  F[2] += (R)(m * c.g[2]);
+  if (c.fluid_on) {
+    const R4<R> fd = ((const R4<R>*)d.fdr)[i];
+    F[0] += fd.x; F[1] += fd.y; F[2] += fd.z;
+  }
+  if (!isfinite(F[0] + F[1] + F[2] + T[0] + T[1] + T[2])) {
+    atomicOr(d.status, (int)kStNonFinite);
+    atomicOr(d.abort, 1);
+  }
+  // second half kick of this step
+  const double hdt = 0.5 * d.dt;
+  v.x += hdt * (double)F[0] * v.w;
+  v.y += hdt * (double)F[1] * v.w;
+  v.z += hdt * (double)F[2] * v.w;
+  const R hdtR = (R)hdt;
+  w.x += hdtR * T[0] * w.w;
+  w.y += hdtR * T[1] * w.w;
+  w.z += hdtR * T[2] * w.w;
+  if (a.final_step) {
+    d.xr[out][i] = pi;
+    d.vel[out][i] = v;
+    ((R4<R>*)d.omg[out])[i] = w;
+    d.alive[out][i] = 1;
+    ((R4<R>*)d.frc)[i] = mk4<R>(F[0], F[1], F[2], (R)0);
+    ((R4<R>*)d.trq)[i] = mk4<R>(T[0], T[1], T[2], (R)0);
+    return;
+  }
+  // first half kick and drift of the next step
+  v.x += hdt * (double)F[0] * v.w;
+  v.y += hdt * (double)F[1] * v.w;
+  v.z += hdt * (double)F[2] * v.w;
+  w.x += hdtR * T[0] * w.w;
+  w.y += hdtR * T[1] * w.w;
+  w.z += hdtR * T[2] * w.w;
+  finish_drift<R>(d, c, i, out, a.step + 1, pi, v, w);
+}
+
+template <typename R> void launch_step(DevState& d, StepArgs a, hipStream_t s) {
+  hipLaunchKernelGGL(k_step<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, a);
+}
+template void launch_step<double>(DevState&, StepArgs, hipStream_t);
+template void launch_step<float>(DevState&, StepArgs, hipStream_t);
+
+}  // namespace dem

@@ -23,12 +23,12 @@ DEM_PREC_FP64, DEM_PREC_MIXED = 0, 1
 DEM_CG_SSW, DEM_CG_SSP = 0, 1
 DEM_FLAG_AUTO_REGROW = 1
 
-DEM_PROF_KICK, DEM_PROF_REBUILD, DEM_PROF_FLUID, DEM_PROF_PAIR, DEM_PROF_GATHER, DEM_PROF_N = 0, 1, 2, 3, 4, 5
-PROF_NAMES = ["kick_drift", "rebuild", "fluid", "pair_force", "gather_kick"]
+DEM_PROF_PROLOGUE, DEM_PROF_REBUILD, DEM_PROF_FLUID, DEM_PROF_STEP, DEM_PROF_N = 0, 1, 2, 3, 4
+PROF_NAMES = ["prologue", "rebuild", "fluid", "step"]
 
 EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "dem_read_pairs",
                   "dem_read_aggregates", "dem_info", "dem_request_rebuild", "dem_destroy", "dem_status_str",
-                  "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile"])
+                  "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile", "dem_read_fault"])
 
 
 class dem_wall(ctypes.Structure):
@@ -110,6 +110,8 @@ def lib():
         L.dem_profile.argtypes = [vp, i32]
         L.dem_read_profile.restype = i32
         L.dem_read_profile.argtypes = [vp, vp, vp]
+        L.dem_read_fault.restype = i32
+        L.dem_read_fault.argtypes = [vp, vp]
         L.dem_destroy.restype = None
         L.dem_destroy.argtypes = [vp]
         L.dem_status_str.restype = ctypes.c_char_p
@@ -125,14 +127,18 @@ def lib():
 
 
 class DemError(RuntimeError):
-    def __init__(self, code, where):
+    def __init__(self, code, where, fault=0):
         self.code = code
-        super().__init__("%s: %s (%d)" % (where, dem_status_str(code), code))
+        self.fault = fault
+        super().__init__("%s: %s (%d, fault bits %d)" % (where, dem_status_str(code), code, fault))
 
 
-def _check(code, where):
+def _check(code, where, ctx=None):
     if code != DEM_OK:
-        raise DemError(code, where)
+        fault = 0
+        if ctx is not None:
+            fault = dem_read_fault(ctx)[1]
+        raise DemError(code, where, fault)
 
 
 # ---------------------------------------------------------------------------
@@ -197,6 +203,12 @@ def dem_request_rebuild(ctx):
 
 def dem_destroy(ctx):
     lib().dem_destroy(ctx)
+
+
+def dem_read_fault(ctx):
+    b = ctypes.c_int32()
+    rc = lib().dem_read_fault(ctx, ctypes.byref(b))
+    return rc, b.value
 
 
 def dem_profile(ctx, enable):
@@ -347,7 +359,7 @@ class Simulation:
             pass
 
     def step(self, nsteps=1):
-        _check(dem_step(self.ctx, nsteps), "dem_step")
+        _check(dem_step(self.ctx, nsteps), "dem_step", self.ctx)
 
     def map_fluid(self, u_cell, gradp_cell):
         torch = self.torch

@@ -286,3 +286,31 @@ def test_step_without_fluid_fields_is_state_error():
     w = c0_sub(100)
     sim = dem.Simulation(dem.params_from_workload(w), w["x"], w["r"])
     assert dem.dem_step(sim.ctx, 1) == dem.DEM_E_STATE
+
+
+# ---------------------------------------------------------------------------
+# full size: the 200 000-particle cylinder in the launch configuration of the
+# benchmark (mixed precision) against the oracle
+# ---------------------------------------------------------------------------
+def test_c1_full_size_against_oracle():
+    w = synth.c1()
+    g = gpu_for(w, "mixed")
+    o = oracle_for(w, bond_at_init=True)
+    np.testing.assert_array_equal(g.pairs(which=0)["pairs"], oracle.pairs(w["x"], w["r"], extra=0.0))
+    # one step from the identical FP64 state: the per-step bar
+    g.step(1)
+    o.step(1)
+    gs, os_ = g.state(), o.state()
+    assert scaled_err(gs["F"], os_["F"], os_["fscale"]) < 1e-5
+    assert scaled_err(gs["T"], os_["T"], os_["tscale"]) < 1e-5
+    # a few more steps: contact and bond sets stay identical, forces drift only
+    # by what the FP32 forces of the previous steps propagate
+    g.step(4)
+    o.step(4)
+    gs, os_ = g.state(), o.state()
+    np.testing.assert_array_equal(gs["alive"], os_["alive"])
+    assert gs["broken_bonds"] == o.scalars()["broken_bonds"]
+    gp, op_ = g.pairs(which=0), o.pairs()
+    np.testing.assert_array_equal(gp["pairs"], op_["pairs"])
+    np.testing.assert_array_equal(gp["bonded"], op_["bonded"])
+    assert scaled_err(gs["F"], os_["F"], os_["fscale"]) < 1e-3
