@@ -24,6 +24,15 @@ template <typename R> __device__ inline R rsqrt_(R x);
 template <> __device__ inline double rsqrt_<double>(double x) { return sqrt(x); }
 template <> __device__ inline float rsqrt_<float>(float x) { return sqrtf(x); }
 
+// FP32 path: hardware reciprocal and square root (about 1 ulp); FP64 path:
+// correctly rounded operations
+template <typename R> __device__ inline R frcp_(R x);
+template <> __device__ inline double frcp_<double>(double x) { return 1.0 / x; }
+template <> __device__ inline float frcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename R> __device__ inline R fsqrt_(R x);
+template <> __device__ inline double fsqrt_<double>(double x) { return sqrt(x); }
+template <> __device__ inline float fsqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 __device__ inline int bin_coord(double x, double lo, double h, int n) {
   double q = floor((x - lo) / h);
   if (q < 0.0) return 0;
@@ -63,20 +72,20 @@ __device__ inline void jkr_bonded(R delta, R Rs, R gam, R jkrK, R& a, R& Fel) {
   constexpr R kbC = (R)1.1447142425533319;   // (3/2)^(1/3)
   constexpr int kNewton = sizeof(R) == 8 ? 3 : 2;
   R X = rcbrt_<R>(jkrK * Rs);
-  R D = delta / X;
-  R b = rsqrt_<R>(rsqrt_<R>(D + (R)2 * kbC));
-  b = rsqrt_<R>(rsqrt_<R>(D + (R)2 * b));
+  R D = delta * frcp_<R>(X);
+  R b = fsqrt_<R>(fsqrt_<R>(D + (R)2 * kbC));
+  b = fsqrt_<R>(fsqrt_<R>(D + (R)2 * b));
 #pragma unroll
   for (int it = 0; it < kNewton; ++it) {
     R b3 = b * b * b;
     R f = b3 * b - (R)2 * b - D;
     R fp = (R)4 * b3 - (R)2;
-    b -= f / fp;
+    b -= f * frcp_<R>(fp);
   }
   R b3 = b * b * b;
   R u = kPi * gam * Rs;
   Fel = u * ((R)4 / (R)3) * b3 * b3 - u * (R)4 * b3;
-  a = rsqrt_<R>(X * Rs) * b * b;
+  a = fsqrt_<R>(X * Rs) * b * b;
 }
 
 template <typename R> struct LawOut {
@@ -97,47 +106,48 @@ __device__ inline void contact_law(const SampleConst& c, int bonded, R delta, R 
     kn = (R)c.k_lin;
     Fel = kn * delta;
     kt = ((R)2 / (R)7) * kn;
-    etan = (R)2 * (R)c.beta * rsqrt_<R>(kn * ms);
-    etat = (R)2 * (R)c.beta * rsqrt_<R>(kt * ms);
+    etan = (R)2 * (R)c.beta * fsqrt_<R>(kn * ms);
+    etat = (R)2 * (R)c.beta * fsqrt_<R>(kt * ms);
     L = (R)c.mu * Fel;
   } else {
     if (bonded && gam > (R)0) {
       jkr_bonded<R>(delta, Rs, gam, jkrK, a, Fel);
       L = (R)c.mu * (Fel + (R)2 * ((R)3 * (R)3.14159265358979323846 * gam * Rs));
     } else {
-      a = rsqrt_<R>(Rs * (delta > (R)0 ? delta : (R)0));
-      Fel = (R)4 * (R)c.Es * a * a * a / ((R)3 * Rs);
+      a = fsqrt_<R>(Rs * (delta > (R)0 ? delta : (R)0));
+      Fel = (R)4 * (R)c.Es * a * a * a * frcp_<R>((R)3 * Rs);
       L = (R)c.mu * Fel;
     }
     kn = (R)2 * (R)c.Es * a;
     kt = (R)8 * (R)c.Gs * a;
-    etan = (R)c.cdamp * rsqrt_<R>(kn * ms);
-    etat = (R)c.cdamp * rsqrt_<R>(kt * ms);
+    etan = (R)c.cdamp * fsqrt_<R>(kn * ms);
+    etat = (R)c.cdamp * fsqrt_<R>(kt * ms);
   }
   R vn = (vrel[0] * n[0] + vrel[1] * n[1]) + vrel[2] * n[2];
   R vt[3] = {vrel[0] - vn * n[0], vrel[1] - vn * n[1], vrel[2] - vn * n[2]};
   R Fn = Fel + etan * vn;
   // rotate the stored elongation into the tangent plane, keep its length
-  R old = rsqrt_<R>((hdt[0] * hdt[0] + hdt[1] * hdt[1]) + hdt[2] * hdt[2]);
+  R old = fsqrt_<R>((hdt[0] * hdt[0] + hdt[1] * hdt[1]) + hdt[2] * hdt[2]);
   R dn = (hdt[0] * n[0] + hdt[1] * n[1]) + hdt[2] * n[2];
   R tp[3] = {hdt[0] - dn * n[0], hdt[1] - dn * n[1], hdt[2] - dn * n[2]};
-  R tpl = rsqrt_<R>((tp[0] * tp[0] + tp[1] * tp[1]) + tp[2] * tp[2]);
+  R tpl = fsqrt_<R>((tp[0] * tp[0] + tp[1] * tp[1]) + tp[2] * tp[2]);
   if (tpl > (R)0) {
-    R f = old / tpl;
+    R f = old * frcp_<R>(tpl);
     hdt[0] = tp[0] * f; hdt[1] = tp[1] * f; hdt[2] = tp[2] * f;
   } else {
     hdt[0] = hdt[1] = hdt[2] = (R)0;
   }
   hdt[0] += vt[0] * dt; hdt[1] += vt[1] * dt; hdt[2] += vt[2] * dt;
   R Ft[3] = {-kt * hdt[0] - etat * vt[0], -kt * hdt[1] - etat * vt[1], -kt * hdt[2] - etat * vt[2]};
-  R ftm = rsqrt_<R>((Ft[0] * Ft[0] + Ft[1] * Ft[1]) + Ft[2] * Ft[2]);
+  R ftm = fsqrt_<R>((Ft[0] * Ft[0] + Ft[1] * Ft[1]) + Ft[2] * Ft[2]);
   if (ftm > L) {
-    R s = L / ftm;
+    R s = L * frcp_<R>(ftm);
     Ft[0] *= s; Ft[1] *= s; Ft[2] *= s;
     if (kt > (R)0) {
-      hdt[0] = -(Ft[0] + etat * vt[0]) / kt;
-      hdt[1] = -(Ft[1] + etat * vt[1]) / kt;
-      hdt[2] = -(Ft[2] + etat * vt[2]) / kt;
+      R ik = frcp_<R>(kt);
+      hdt[0] = -(Ft[0] + etat * vt[0]) * ik;
+      hdt[1] = -(Ft[1] + etat * vt[1]) * ik;
+      hdt[2] = -(Ft[2] + etat * vt[2]) * ik;
     } else {
       hdt[0] = hdt[1] = hdt[2] = (R)0;
     }
@@ -152,9 +162,9 @@ __device__ inline void contact_law(const SampleConst& c, int bonded, R delta, R 
   if (rolling && c.mu_roll > 0.0) {
     R wn = (wrel[0] * n[0] + wrel[1] * n[1]) + wrel[2] * n[2];
     R wr[3] = {wrel[0] - wn * n[0], wrel[1] - wn * n[1], wrel[2] - wn * n[2]};
-    R wm = rsqrt_<R>((wr[0] * wr[0] + wr[1] * wr[1]) + wr[2] * wr[2]);
+    R wm = fsqrt_<R>((wr[0] * wr[0] + wr[1] * wr[1]) + wr[2] * wr[2]);
     if (wm > (R)0) {
-      R tm = (R)c.mu_roll * Rs * (Fel < (R)0 ? -Fel : Fel) / wm;
+      R tm = (R)c.mu_roll * Rs * (Fel < (R)0 ? -Fel : Fel) * frcp_<R>(wm);
       o.Tr[0] = -tm * wr[0]; o.Tr[1] = -tm * wr[1]; o.Tr[2] = -tm * wr[2];
     }
   }
@@ -190,10 +200,9 @@ __device__ inline void pair_eval(const SampleConst& c, double dt, bool rolling, 
   const double dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
   const double d2 = (dx * dx + dy * dy) + dz * dz;
   const double cs = A.w + B.w;
-  const double Rsd = A.w * B.w / (A.w + B.w);
   const bool touching = d2 < cs * cs;
   const int bonded = fl & 1;
-  if (bonded && !touching && !bond_holds_apart(d2, cs, Rsd, gam, c.Es)) {
+  if (bonded && !touching && !bond_holds_apart(d2, cs, A.w * B.w / (A.w + B.w), gam, c.Es)) {
     out.broke = true;
     out.h = mk4<R>(0, 0, 0, 0);
     out.fl = 0;
@@ -211,9 +220,9 @@ __device__ inline void pair_eval(const SampleConst& c, double dt, bool rolling, 
     n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
   } else {
     // overlap from the FP64 difference of squares, normal in FP32
-    const R dist = rsqrt_<R>((R)d2);
-    delta = (R)(cs * cs - d2) / ((R)cs + dist);
-    const R inv = (R)1 / dist;
+    const R dist = fsqrt_<R>((R)d2);
+    delta = (R)(cs * cs - d2) * frcp_<R>((R)cs + dist);
+    const R inv = frcp_<R>(dist);
     n[0] = (R)dx * inv; n[1] = (R)dy * inv; n[2] = (R)dz * inv;
   }
   const R ra = (R)A.w, rb = (R)B.w;
@@ -222,10 +231,18 @@ __device__ inline void pair_eval(const SampleConst& c, double dt, bool rolling, 
                      (R)(VA.y - VB.y) + (ws[2] * n[0] - ws[0] * n[2]),
                      (R)(VA.z - VB.z) + (ws[0] * n[1] - ws[1] * n[0])};
   const R wrel[3] = {WA.x - WB.x, WA.y - WB.y, WA.z - WB.z};
-  const R ms = (R)(1.0 / (VA.w + VB.w));
+  R ms, Rs;
+  if (sizeof(R) == 8) {
+    ms = (R)(1.0 / (VA.w + VB.w));
+    Rs = (R)(A.w * B.w / (A.w + B.w));
+  } else {
+    ms = frcp_<R>((R)VA.w + (R)VB.w);
+    Rs = ra * rb * frcp_<R>(ra + rb);
+  }
   R h[3] = {h4.x, h4.y, h4.z};
-  const R jkrK = (R)((M_PI * M_PI) * (gam * gam) / (c.Es * c.Es));
-  contact_law<R>(c, bonded, delta, (R)Rsd, ms, (R)gam, jkrK, n, vrel, wrel, h, (R)dt, rolling, out.o);
+  const R gR = (R)gam;
+  const R jkrK = (R)3.14159265358979323846 * (R)3.14159265358979323846 * gR * gR * frcp_<R>((R)c.Es * (R)c.Es);
+  contact_law<R>(c, bonded, delta, Rs, ms, gR, jkrK, n, vrel, wrel, h, (R)dt, rolling, out.o);
   out.h = mk4<R>(h[0], h[1], h[2], (R)0);
   out.fl = (uint8_t)(bonded | (touching ? 2 : 0));
   out.active = true;

@@ -68,13 +68,17 @@ void launch_set_xref(DevState& d, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// candidate search
+// candidate search.  The 27 neighbour cells of a home cell are staged in LDS as
+// FP32 positions relative to the home cell's corner; each lane first applies a
+// conservative FP32 test (cutoff widened by a relative slack far above the FP32
+// rounding of the relative coordinates), and only the survivors take the exact
+// FP64 test on the stored FP64 positions.  The exact test alone decides.
 // ---------------------------------------------------------------------------
-constexpr int kLdsCand = 1536;
+constexpr int kLdsCand = 2048;
 
 template <bool kFill>
 __global__ __launch_bounds__(256) void k_nbr_search(DevState d) {
-  __shared__ double4 sx[kLdsCand];
+  __shared__ float4 sx[kLdsCand];
   __shared__ int32_t sj[kLdsCand];
   __shared__ int32_t srs[27], srl[27];
   const int64_t cbin = blockIdx.x;
@@ -86,6 +90,7 @@ __global__ __launch_bounds__(256) void k_nbr_search(DevState d) {
   const int cx = (int)(local % c.bn[0]);
   const int cy = (int)((local / c.bn[0]) % c.bn[1]);
   const int cz = (int)(local / ((int64_t)c.bn[0] * c.bn[1]));
+  const double ox = c.blo[0] + cx * c.bh[0], oy = c.blo[1] + cy * c.bh[1], oz = c.blo[2] + cz * c.bh[2];
   const int t0 = threadIdx.x;
   if (t0 < 27) {
     int dx = t0 % 3 - 1, dy = (t0 / 3) % 3 - 1, dz = t0 / 9 - 1;
@@ -110,15 +115,21 @@ __global__ __launch_bounds__(256) void k_nbr_search(DevState d) {
         if (j < 0 && t < acc + srl[k]) j = srs[k] + (t - acc);
         acc += srl[k];
       }
-      sx[t] = X[j];
+      const double4 p = X[j];
+      sx[t] = make_float4((float)(p.x - ox), (float)(p.y - oy), (float)(p.z - oz), (float)p.w);
       sj[t] = j;
     }
   }
   __syncthreads();
   const int lane = t0 & 63, wv = t0 >> 6;
   const double margin = c.margin;
+  const float marginf = (float)margin;
+  // absolute slack: the relative coordinates span at most two cells, each
+  // rounded to FP32 (relative error 2^-24); 3e-6 of a cell side covers it many times
+  const float slack = 3e-6f * (float)fmax(c.bh[0], fmax(c.bh[1], c.bh[2]));
   for (int32_t i = h0 + wv; i < h1; i += 4) {
     const double4 pi = X[i];
+    const float pix = (float)(pi.x - ox), piy = (float)(pi.y - oy), piz = (float)(pi.z - oz), pir = (float)pi.w;
     int written = 0, owned = 0;
     int row = 0, pre_n = 0, hbase = 0;
     if (kFill) {
@@ -131,19 +142,23 @@ __global__ __launch_bounds__(256) void k_nbr_search(DevState d) {
       bool pred = false;
       int j = -1;
       if (t < total) {
-        double4 pj;
+        bool maybe;
         if (staged) {
-          pj = sx[t];
+          const float4 q = sx[t];
           j = sj[t];
+          const float ex = q.x - pix, ey = q.y - piy, ez = q.z - piz;
+          const float cf = ((pir + q.w) + marginf) * 1.0001f + slack;
+          maybe = (ex * ex + ey * ey) + ez * ez < cf * cf;
         } else {
           int acc = 0;
           for (int k = 0; k < 27; ++k) {
             if (j < 0 && t < acc + srl[k]) j = srs[k] + (t - acc);
             acc += srl[k];
           }
-          pj = X[j];
+          maybe = true;
         }
-        if (j != i) {
+        if (maybe && j != i) {
+          const double4 pj = X[j];
           double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
           double d2 = (dx * dx + dy * dy) + dz * dz;
           double cc = (pi.w + pj.w) + margin;

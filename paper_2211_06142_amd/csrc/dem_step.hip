@@ -2,7 +2,7 @@
 //
 // k_prologue: first half kick and drift of the first step of a call (eq 1-2,
 // velocity Verlet), outlet removal, rebuild trigger.
-// k_step: one thread per particle.  The particle walks its full neighbour row
+// k_step: a group of lanes per particle.  The particle walks its full neighbour row
 // and evaluates every contact in the pair's canonical orientation (owner =
 // lower sorted index, n from owner to partner), so both partners compute the
 // bit-identical pair force and Newton's third law holds exactly without
@@ -85,11 +85,24 @@ template <typename R> void launch_prologue(DevState& d, StepArgs a, hipStream_t 
 template void launch_prologue<double>(DevState&, StepArgs, hipStream_t);
 template void launch_prologue<float>(DevState&, StepArgs, hipStream_t);
 
+// Lanes per particle: a group of kGroup lanes shares one particle's row; lane
+// s evaluates entries s, s + kGroup, ... and the group sums its partial forces
+// with a fixed xor butterfly (every lane ends with the bit-identical total).
+constexpr int kGroup = 8;
+
+template <typename R>
+__device__ inline R group_sum(R v) {
+#pragma unroll
+  for (int off = kGroup / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kGroup);
+  return v;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
   if (*d.abort) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
+  const int sub = threadIdx.x & (kGroup - 1);
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+  if (i >= d.n) return;   // whole group
   const int in = a.in, out = a.out;
   const double4* X = d.xr[in];
   const double4* V = d.vel[in];
@@ -98,11 +111,13 @@ __global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
   const double4 pi = X[i];
   double4 v = V[i];
   R4<R> w = W[i];
-  if (!AL[i]) {
-    d.xr[out][i] = pi;
-    d.vel[out][i] = v;
-    ((R4<R>*)d.omg[out])[i] = w;
-    d.alive[out][i] = 0;
+  if (!AL[i]) {           // whole group
+    if (sub == 0) {
+      d.xr[out][i] = pi;
+      d.vel[out][i] = v;
+      ((R4<R>*)d.omg[out])[i] = w;
+      d.alive[out][i] = 0;
+    }
     return;
   }
   const int s = d.sample[i];
@@ -116,7 +131,7 @@ __global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
   R F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   const double ci = d.ccoh ? d.ccoh[i] : 1.0;
   const int32_t e1 = d.nrow[i + 1];
-  for (int32_t e = d.nrow[i]; e < e1; ++e) {
+  for (int32_t e = d.nrow[i] + sub; e < e1; e += kGroup) {
     const int32_t j = d.nbr[e];
     const int32_t p = d.nslot[e];
     const bool own = j > (int32_t)i;
@@ -133,8 +148,11 @@ __global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
     double gam = c.gamma;
     if (d.ccoh) gam = c.gamma * sqrt(ci * d.ccoh[j]);
     PairOut<R> po;
-    if (own) pair_eval<R>(c, d.dt, rolling, pi, pj, v, vj, w, wj, gam, Hin[p], Fin[p], po);
-    else pair_eval<R>(c, d.dt, rolling, pj, pi, vj, v, wj, w, gam, Hin[p], Fin[p], po);
+    // canonical orientation: the owner (lower index) is body A
+    const double4 PA = own ? pi : pj, PB = own ? pj : pi;
+    const double4 VA = own ? v : vj, VB = own ? vj : v;
+    const R4<R> WA = own ? w : wj, WB = own ? wj : w;
+    pair_eval<R>(c, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, Hin[p], Fin[p], po);
     if (own) {
       Hout[p] = po.h;
       Fout[p] = po.fl;
@@ -147,9 +165,10 @@ __global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
     T[1] += r * po.o.c[1] + sg * po.o.Tr[1];
     T[2] += r * po.o.c[2] + sg * po.o.Tr[2];
   }
-  // walls: Hertz with R* = r and m* = m (rigid, static)
+  // walls: Hertz with R* = r and m* = m (rigid, static); entries private to i
   const double m = c.rho * (4.0 / 3.0) * M_PI * pi.w * pi.w * pi.w;
-  for (int32_t e = d.wrow[i]; e < d.wrow[i + 1]; ++e) {
+  const int32_t w1 = d.wrow[i + 1];
+  for (int32_t e = d.wrow[i] + sub; e < w1; e += kGroup) {
     R4<R> h4 = ((const R4<R>*)d.wdt)[e];
     double sd, nw[3];
     const Wall& wl = c.walls[d.wid[e]];
@@ -174,6 +193,12 @@ __global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
     ((R4<R>*)d.wdt)[e] = mk4<R>(h[0], h[1], h[2], (R)0);
     d.wfl[e] = 2;
   }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    F[k] = group_sum<R>(F[k]);
+    T[k] = group_sum<R>(T[k]);
+  }
+  if (sub != 0) return;
   F[0] += (R)(m * c.g[0]);
   F[1] += (R)(m * c.g[1]);
   F[2] += (R)(m * c.g[2]);
@@ -214,7 +239,7 @@ __global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
 }
 
 template <typename R> void launch_step(DevState& d, StepArgs a, hipStream_t s) {
-  hipLaunchKernelGGL(k_step<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, a);
+  hipLaunchKernelGGL(k_step<R>, dim3(nblk(d.n * kGroup)), dim3(kBlock), 0, s, d, a);
 }
 template void launch_step<double>(DevState&, StepArgs, hipStream_t);
 template void launch_step<float>(DevState&, StepArgs, hipStream_t);
