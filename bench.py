@@ -125,8 +125,11 @@ def main():
     p = dem.params_from_workload(w)
     sim = dem.Simulation(p, w["x"], w["r"])
     sim.map_fluid(w["u_cell"], w["gradp_cell"])
+    print("bench: %s set up, %d particles" % (w["name"], len(w["r"])), file=sys.stderr, flush=True)
     sim.step(args.warmup)
     n0 = sim.state()["n_alive"]
+    print("bench: %d warm-up steps done, %d rebuilds" % (args.warmup, sim.info()["rebuilds"]), file=sys.stderr,
+          flush=True)
     stream = sim.stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -139,6 +142,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
+    print("bench: %d timed steps done in %.1f ms" % (args.steps, ms), file=sys.stderr, flush=True)
     prof = sim.read_profile()
     sim.profile(0)
     st = sim.state()

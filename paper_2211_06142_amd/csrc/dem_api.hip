@@ -60,6 +60,7 @@ struct dem_ctx {
   NbrSet ns[2];
   WallSet ws[2];
   int live = 0;          // ns[live] / ws[live] is the current list
+  int last_overflow_rows = 0;   // rows the last search could not keep in scratch
   int hist_old = 0;      // history buffer of the previous list at the next rebuild
   int64_t step = 0;
   int64_t rebuilds = 0;
@@ -327,7 +328,7 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   // 1. sort by (sample, cell, id); dead particles to their sample's last bucket
   launch_bin_keys(d, s);
   launch_bucket_sort(d.key, d.n, d.nbins_total, d.orig, d.bucket_cnt, d.cell_start, d.bucket_fill, d.order_tmp,
-                     d.order, d.scan_tmp, s);
+                     d.order, d.scan_tmp, d.bin_sink, nullptr, s);
   // 2. permute into the other buffer
   launch_permute<R>(d, s);
   c->hist_old = d.cur;
@@ -338,19 +339,22 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   // 3. the live list becomes the previous one
   if (!first) c->live = 1 - c->live;
   bind_sets(c);
-  // 4. count and fill (dead particles own no entries: their counts stay zero)
+  // 4. search into scratch rows, scan the row lengths, fill the CSR rows
+  //    (dead particles own no entries: their counts stay zero)
   HIPCHK(hipMemsetAsync(d.ncnt, 0, sizeof(int32_t) * (d.n + 1), s));
   HIPCHK(hipMemsetAsync(d.ocnt, 0, sizeof(int32_t) * (d.n + 1), s));
-  launch_nbr_count(d, s);
+  HIPCHK(hipMemsetAsync(d.novf, 0, sizeof(int), s));
+  launch_nbr_search(d, s);
   scan_exclusive(d.ncnt, d.nrow, d.n + 1, d.scan_tmp, s);
   scan_exclusive(d.ocnt, d.hrow, d.n + 1, d.scan_tmp, s);
   launch_wall_count(d, s);
   HIPCHK(hipMemsetAsync(d.wcnt + d.n, 0, sizeof(int32_t), s));
   scan_exclusive(d.wcnt, d.wrow, d.n + 1, d.scan_tmp, s);
-  int32_t tot[3];
+  int32_t tot[4];
   HIPCHK(hipMemcpyAsync(&tot[0], d.nrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&tot[1], d.hrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&tot[2], d.wrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tot[3], d.novf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   NbrSet& ns = c->ns[c->live];
   WallSet& ws = c->ws[c->live];
@@ -359,15 +363,12 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   ns.nent = tot[0];
   ns.nslots = tot[1];
   ws.n = tot[2];
+  c->last_overflow_rows = tot[3];
   bind_sets(c);
-  launch_nbr_fill(d, s);
-  launch_nbr_mirror(d, s);
+  launch_nbr_fill(d, tot[3], s);
   launch_wall_fill(d, s);
   // 5. carry history
-  int check = first ? 0 : 1;
-  if (check) launch_count_old_bonds(d, s);
-  launch_hist_merge<R>(d, s, check);
-  if (check) launch_check_lost(d, s);
+  launch_hist_carry<R>(d, s, first ? 0 : 1);
   if (mark_bonds) launch_mark_bonds(d, s);
   launch_set_xref(d, s);
   c->rebuilds++;
@@ -645,9 +646,12 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.key, n) == hipSuccess;
   ok &= dalloc(c, &d.bucket_cnt, nbk) == hipSuccess && dalloc(c, &d.bucket_fill, nbk) == hipSuccess;
   ok &= dalloc(c, &d.cell_start, nbk) == hipSuccess && dalloc(c, &d.bin_sample, nbk) == hipSuccess;
+  ok &= dalloc(c, &d.bin_sink, nbk) == hipSuccess && dalloc(c, &d.dual_sink, d.ndual + 2) == hipSuccess;
   ok &= dalloc(c, &d.order, n) == hipSuccess && dalloc(c, &d.order_tmp, n) == hipSuccess;
   ok &= dalloc(c, &d.inv_order, n) == hipSuccess;
   ok &= dalloc(c, &d.ncnt, n + 1) == hipSuccess && dalloc(c, &d.ocnt, n + 1) == hipSuccess;
+  ok &= dalloc(c, &d.scr, n * kRowMax) == hipSuccess && dalloc(c, &d.ovf, n) == hipSuccess;
+  ok &= dalloc(c, &d.novf, 1) == hipSuccess;
   ok &= dalloc(c, &d.wcnt, n + 1) == hipSuccess;
   for (int q = 0; q < 2; ++q) {
     ok &= dalloc(c, &c->ns[q].nrow, n + 1) == hipSuccess;
@@ -676,7 +680,6 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.broken, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.status, 1) == hipSuccess && dalloc(c, &d.abort, 1) == hipSuccess;
   ok &= dalloc(c, &d.abort_step, 1) == hipSuccess;
-  ok &= dalloc(c, &d.scratch_i, 4) == hipSuccess;
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nbk, n + 1), d.ndual + 2);
   d.scan_tmp_n = scan_n / 256 + 4096;
   ok &= dalloc(c, &d.scan_tmp, d.scan_tmp_n) == hipSuccess;
@@ -709,6 +712,12 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
     }
   }
   std::vector<int32_t> cs(nc, 0), bs(nbk, 0);
+  std::vector<uint8_t> bsink(nbk, 0), dsink(d.ndual + 2, 0);
+  for (int s = 0; s < n_samples; ++s) {
+    const SampleConst& k = c->sc[s];
+    bsink[k.bin_base + (int64_t)k.bn[0] * k.bn[1] * k.bn[2]] = 1;
+    dsink[k.dual_base + (int64_t)k.dn[0] * k.dn[1] * k.dn[2]] = 1;
+  }
   for (int s = 0; s < n_samples; ++s) {
     if (params[s].fluid_on)
       for (int64_t q = 0; q < (int64_t)c->sc[s].gn[0] * c->sc[s].gn[1] * c->sc[s].gn[2]; ++q)
@@ -731,6 +740,8 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   up &= hipMemcpyAsync(d.sc, c->sc.data(), sizeof(SampleConst) * n_samples, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.cell_sample, cs.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.bin_sample, bs.data(), sizeof(int32_t) * nbk, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.bin_sink, bsink.data(), nbk, hipMemcpyHostToDevice, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.dual_sink, dsink.data(), d.ndual + 2, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(c->d_offsets, offs.data(), sizeof(int64_t) * (n_samples + 1), hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemsetAsync(d.broken, 0, sizeof(unsigned long long) * n_samples, st) == hipSuccess;
   up &= hipMemsetAsync(d.status, 0, sizeof(int), st) == hipSuccess;

@@ -35,7 +35,7 @@ template <> __device__ inline float fsqrt_<float>(float x) { return __builtin_am
 
 __device__ inline int bin_coord(double x, double lo, double h, int n) {
   double q = floor((x - lo) / h);
-  if (q < 0.0) return 0;
+  if (!(q >= 0.0)) return 0;   // also a NaN coordinate
   if (q > (double)(n - 1)) return n - 1;
   return (int)q;
 }

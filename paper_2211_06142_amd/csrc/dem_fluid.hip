@@ -15,14 +15,18 @@
 
 namespace dem {
 
+// Every particle gets a key in range, also when the window was aborted (then
+// buffer `buf` may never have been written and every particle goes to its
+// sample's skip bucket): the bucket sort that follows is not gated.
 __global__ void k_fluid_key(DevState d, int buf) {
-  if (*d.abort) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   const SampleConst& c = d.sc[d.sample[i]];
   int64_t nd = (int64_t)c.dn[0] * c.dn[1] * c.dn[2];
-  if (!d.alive[buf][i] || !c.fluid_on) { d.dkey[i] = (int32_t)(c.dual_base + nd); return; }
+  const int32_t skip = (int32_t)(c.dual_base + nd);
+  if (*d.abort || !d.alive[buf][i] || !c.fluid_on) { d.dkey[i] = skip; return; }
   const double4 p = d.xr[buf][i];
+  if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) { d.dkey[i] = skip; return; }
   const double xs[3] = {p.x, p.y, p.z};
   int b[3];
   double f[3];
@@ -207,7 +211,7 @@ __global__ void k_fluid_drag(DevState d, int buf) {
 template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
   hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, buf);
   launch_bucket_sort((const uint32_t*)d.dkey, d.n, d.ndual, nullptr, d.dcnt, d.doff, d.dfill, d.dmem_tmp,
-                     d.dmem, d.scan_tmp, s);
+                     d.dmem, d.scan_tmp, d.dual_sink, d.abort, s);
   hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d);
   hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, buf);

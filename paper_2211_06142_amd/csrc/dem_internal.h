@@ -27,6 +27,7 @@
 namespace dem {
 
 constexpr int kMaxWalls = DEM_MAX_WALLS;
+constexpr int kRowMax = 32;      // stride of the scratch rows of the candidate search
 
 enum StatusBits : int {
   kStCapacity = 1,
@@ -97,12 +98,16 @@ struct DevState {
   int64_t nbins_total;
   int32_t* cell_start;             // nbins_total + 1
   int32_t* bin_sample;             // nbins_total: sample of each bin
+  uint8_t* bin_sink;               // nbins_total: 1 for each sample's dead bucket
   // live neighbour list
   int64_t ent_cap, nent, slot_cap, nslots;
   int32_t *nrow, *nbr, *nslot, *hrow, *sown, *spart;
   void* hdt[2];
   uint8_t* pfl[2];
   int32_t *ncnt, *ocnt;
+  int32_t* scr;                    // n * kRowMax: rows found by the search
+  int32_t* ovf;                    // rows longer than kRowMax or found outside LDS
+  int* novf;
   // previous list (history source at a rebuild)
   int32_t *nrow_o, *nbr_o, *nslot_o;
   void* hdt_o;
@@ -125,13 +130,13 @@ struct DevState {
   double4* dfr;                    // CIC fractions (fx, fy, fz, volume)
   double4* fpart;                  // particle drag of the latest evaluation
   int32_t *dcnt, *doff, *dfill, *dmem, *dmem_tmp;
+  uint8_t* dual_sink;              // ndual: 1 for each sample's skip bucket
   // per-sample, status
   SampleConst* sc;
   unsigned long long* broken;      // per sample
   int* status;
   int* abort;                      // set when a rebuild is due before the next step
   int* abort_step;
-  int* scratch_i;
   int32_t* scan_tmp;
   int64_t scan_tmp_n;
 };
@@ -146,19 +151,16 @@ struct StepArgs {
 void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s);
 void launch_bucket_sort(const uint32_t* key, int64_t n, int64_t nb, const int32_t* tiebreak, int32_t* cnt,
                         int32_t* off, int32_t* fill, int32_t* order_tmp, int32_t* out_order,
-                        int32_t* scan_tmp, hipStream_t s);
+                        int32_t* scan_tmp, const uint8_t* sink, const int* gate, hipStream_t s);
 
 // rebuild
 void launch_bin_keys(DevState& d, hipStream_t s);
 template <typename R> void launch_permute(DevState& d, hipStream_t s);
-void launch_nbr_count(DevState& d, hipStream_t s);
-void launch_nbr_fill(DevState& d, hipStream_t s);
-void launch_nbr_mirror(DevState& d, hipStream_t s);
+void launch_nbr_search(DevState& d, hipStream_t s);
+void launch_nbr_fill(DevState& d, int novf, hipStream_t s);
 void launch_wall_count(DevState& d, hipStream_t s);
 void launch_wall_fill(DevState& d, hipStream_t s);
-template <typename R> void launch_hist_merge(DevState& d, hipStream_t s, int check_lost);
-void launch_count_old_bonds(DevState& d, hipStream_t s);
-void launch_check_lost(DevState& d, hipStream_t s);
+template <typename R> void launch_hist_carry(DevState& d, hipStream_t s, int check_lost);
 void launch_mark_bonds(DevState& d, hipStream_t s);
 void launch_set_xref(DevState& d, hipStream_t s);
 

@@ -1,11 +1,9 @@
 // dem_rebuild.hip -- neighbour-list rebuild.
 //
 //   bin keys -> stable bucket sort by (sample, cell, id) -> permute the particle
-//   arrays -> candidate search (one workgroup per binning cell: the 27
-//   neighbour cells are staged in LDS, one wavefront per home particle tests
-//   64 candidates at a time and compacts hits with a ballot and prefix
-//   popcount; count pass, scan, fill pass) -> slot of every mirror entry ->
-//   history of every half pair carried over from the previous list.
+//   arrays -> candidate search into fixed-stride scratch rows (one workgroup
+//   per binning cell) -> scan of the row lengths -> rows and half-pair slots
+//   in CSR -> history of every half pair carried over from the previous list.
 // Candidate predicate, in FP64 with a fixed operation order:
 //   ((dx dx + dy dy) + dz dz) < ((r_i + r_j) + margin)^2.
 #include "dem_device.h"
@@ -68,18 +66,89 @@ void launch_set_xref(DevState& d, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// candidate search.  The 27 neighbour cells of a home cell are staged in LDS as
-// FP32 positions relative to the home cell's corner; each lane first applies a
-// conservative FP32 test (cutoff widened by a relative slack far above the FP32
-// rounding of the relative coordinates), and only the survivors take the exact
-// FP64 test on the stored FP64 positions.  The exact test alone decides.
+// candidate search, one pass.  One workgroup per binning cell: the 27
+// neighbour cells are staged in LDS as FP32 positions relative to the home
+// cell's corner.  Phase 1: a wavefront per home particle applies a
+// conservative FP32 test to 64 candidates at a time (cutoff widened by a
+// slack far above the FP32 rounding of the relative coordinates) and compacts
+// the survivors in candidate order.  Phase 2: every survivor of the cell takes
+// the exact FP64 test, one survivor per lane, all in one round of loads.
+// Phase 3: each confirmed row goes to its fixed scratch row (stride kRowMax),
+// with its counts.  The exact test alone decides.
+// Rows with more FP32 survivors than kRowMax, and every row of a cell whose
+// neighbourhood does not fit in LDS, are searched straight from global memory;
+// rows longer than kRowMax are listed as overflow rows, which the fill
+// searches again and writes directly.
+// Candidates come in increasing partner index: the 27 cells in increasing
+// binning index, each cell's particles in sorted order.
 // ---------------------------------------------------------------------------
-constexpr int kLdsCand = 2048;
+constexpr int kLdsCand = 1024;   // staged candidates per home cell
+constexpr int kHomeMax = 64;     // home particles of a staged cell
 
-template <bool kFill>
-__global__ __launch_bounds__(256) void k_nbr_search(DevState d) {
+__device__ inline bool is_candidate(const double4& pi, const double4& pj, double margin) {
+  double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+  double d2 = (dx * dx + dy * dy) + dz * dz;
+  double cc = (pi.w + pj.w) + margin;
+  return d2 < cc * cc;
+}
+
+// start and length of neighbour cell t (0..26) of binning cell (cx, cy, cz)
+__device__ inline void cell_range(const DevState& d, const SampleConst& c, int cx, int cy, int cz, int t,
+                                  int32_t& st, int32_t& len) {
+  int qx = cx + t % 3 - 1, qy = cy + (t / 3) % 3 - 1, qz = cz + t / 9 - 1;
+  st = 0;
+  len = 0;
+  if (qx >= 0 && qy >= 0 && qz >= 0 && qx < c.bn[0] && qy < c.bn[1] && qz < c.bn[2]) {
+    int64_t q = c.bin_base + ((int64_t)qz * c.bn[1] + qy) * c.bn[0] + qx;
+    st = d.cell_start[q];
+    len = d.cell_start[q + 1] - st;
+  }
+}
+
+// particle index of candidate t of the concatenated 27 cells
+__device__ inline int32_t cand_index(const int32_t* srs, const int32_t* srl, int t) {
+  int acc = 0, j = -1;
+#pragma unroll 1
+  for (int k = 0; k < 27; ++k) {
+    if (j < 0 && t < acc + srl[k]) j = srs[k] + (t - acc);
+    acc += srl[k];
+  }
+  return j;
+}
+
+// row i straight from global memory (wavefront-wide): counts, and the row in
+// its scratch row as far as it fits
+__device__ inline void search_row_global(DevState& d, const double4* X, int32_t i, const int32_t* srs,
+                                         const int32_t* srl, int total, double margin, int lane, int& written,
+                                         int& owned) {
+  const double4 pi = X[i];
+  for (int base = 0; base < total; base += 64) {
+    const int t = base + lane;
+    bool pred = false;
+    int32_t j = -1;
+    if (t < total) {
+      j = cand_index(srs, srl, t);
+      pred = j != i && is_candidate(pi, X[j], margin);
+    }
+    const unsigned long long m = __ballot(pred);
+    const int pos = written + __popcll(m & ((1ull << lane) - 1ull));
+    if (pred && pos < kRowMax) d.scr[(int64_t)i * kRowMax + pos] = j;
+    written += __popcll(m);
+    owned += __popcll(__ballot(pred && j > i));
+  }
+}
+
+__device__ inline void push_overflow(DevState& d, int32_t i) {
+  int k = atomicAdd(d.novf, 1);
+  d.ovf[k] = i;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_nbr_search(DevState d) {
   __shared__ float4 sx[kLdsCand];
   __shared__ int32_t sj[kLdsCand];
+  __shared__ int16_t surv[kHomeMax][kRowMax];   // candidate of each survivor; -1 once rejected
+  __shared__ int32_t nsurv[kHomeMax];
+  __shared__ int32_t pre[kHomeMax + 1];
   __shared__ int32_t srs[27], srl[27];
   const int64_t cbin = blockIdx.x;
   const int32_t h0 = d.cell_start[cbin], h1 = d.cell_start[cbin + 1];
@@ -90,129 +159,224 @@ __global__ __launch_bounds__(256) void k_nbr_search(DevState d) {
   const int cx = (int)(local % c.bn[0]);
   const int cy = (int)((local / c.bn[0]) % c.bn[1]);
   const int cz = (int)(local / ((int64_t)c.bn[0] * c.bn[1]));
-  const double ox = c.blo[0] + cx * c.bh[0], oy = c.blo[1] + cy * c.bh[1], oz = c.blo[2] + cz * c.bh[2];
   const int t0 = threadIdx.x;
-  if (t0 < 27) {
-    int dx = t0 % 3 - 1, dy = (t0 / 3) % 3 - 1, dz = t0 / 9 - 1;
-    int qx = cx + dx, qy = cy + dy, qz = cz + dz;
-    srs[t0] = 0;
-    srl[t0] = 0;
-    if (qx >= 0 && qy >= 0 && qz >= 0 && qx < c.bn[0] && qy < c.bn[1] && qz < c.bn[2]) {
-      int64_t q = c.bin_base + ((int64_t)qz * c.bn[1] + qy) * c.bn[0] + qx;
-      srs[t0] = d.cell_start[q];
-      srl[t0] = d.cell_start[q + 1] - srs[t0];
+  if (t0 < 27) cell_range(d, c, cx, cy, cz, t0, srs[t0], srl[t0]);
+  __syncthreads();
+  int total = 0, home_off = 0;
+  for (int k = 0; k < 27; ++k) {
+    if (k == 13) home_off = total;
+    total += srl[k];
+  }
+  const int nh = h1 - h0;
+  const int lane = t0 & 63, wv = t0 >> 6;
+  const double margin = c.margin;
+  const double4* X = d.xr[d.cur];
+  if (total > kLdsCand || nh > kHomeMax) {
+    // crowded neighbourhood: count every home row from global memory
+    for (int32_t i = h0 + wv; i < h1; i += 4) {
+      int written = 0, owned = 0;
+      search_row_global(d, X, i, srs, srl, total, margin, lane, written, owned);
+      if (lane == 0) {
+        d.ncnt[i] = written;
+        d.ocnt[i] = owned;
+        if (written > kRowMax) push_overflow(d, i);
+      }
+    }
+    return;
+  }
+  const double ox = c.blo[0] + cx * c.bh[0], oy = c.blo[1] + cy * c.bh[1], oz = c.blo[2] + cz * c.bh[2];
+  for (int t = t0; t < total; t += 256) {
+    const int32_t j = cand_index(srs, srl, t);
+    const double4 p = X[j];
+    sx[t] = make_float4((float)(p.x - ox), (float)(p.y - oy), (float)(p.z - oz), (float)p.w);
+    sj[t] = j;
+  }
+  __syncthreads();
+  const float marginf = (float)margin;
+  // the relative coordinates span at most two cells, each rounded to FP32
+  // (relative error 2^-24); 3e-6 of a cell side covers that many times over
+  const float slack = 3e-6f * (float)fmax(c.bh[0], fmax(c.bh[1], c.bh[2]));
+  // phase 1: FP32 prefilter
+  for (int h = wv; h < nh; h += 4) {
+    const int32_t i = h0 + h;
+    const float4 q0 = sx[home_off + h];
+    int cnt = 0;
+    for (int base = 0; base < total; base += 64) {
+      const int t = base + lane;
+      bool maybe = false;
+      if (t < total && sj[t] != i) {
+        const float4 q = sx[t];
+        const float ex = q.x - q0.x, ey = q.y - q0.y, ez = q.z - q0.z;
+        const float cf = ((q0.w + q.w) + marginf) * 1.0001f + slack;
+        maybe = (ex * ex + ey * ey) + ez * ez < cf * cf;
+      }
+      const unsigned long long m = __ballot(maybe);
+      const int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
+      if (maybe && pos < kRowMax) surv[h][pos] = (int16_t)t;
+      cnt += __popcll(m);
+    }
+    if (lane == 0) nsurv[h] = cnt;
+  }
+  __syncthreads();
+  // phase 2: exact FP64 test of every kept survivor (rows with more survivors
+  // than kRowMax are counted directly in phase 3)
+  if (wv == 0) {
+    int v = lane < nh && nsurv[lane] <= kRowMax ? nsurv[lane] : 0;
+    for (int off = 1; off < 64; off <<= 1) {
+      int u = __shfl_up(v, off, 64);
+      if (lane >= off) v += u;
+    }
+    pre[lane + 1] = v;
+    if (lane == 0) pre[0] = 0;
+  }
+  __syncthreads();
+  const int nsv = pre[nh];
+  for (int q = t0; q < nsv; q += 256) {
+    int lo = 0, hi = nh;
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (pre[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int k = q - pre[lo];
+    if (!is_candidate(X[h0 + lo], X[sj[surv[lo][k]]], margin)) surv[lo][k] = -1;
+  }
+  __syncthreads();
+  // phase 3: rows to scratch in candidate order
+  for (int h = wv; h < nh; h += 4) {
+    const int32_t i = h0 + h;
+    const int ns = nsurv[h];
+    int written = 0, owned = 0;
+    if (ns <= kRowMax) {
+      const int t = lane < ns ? surv[h][lane] : -1;
+      const bool pred = t >= 0;
+      const int32_t j = pred ? sj[t] : -1;
+      const unsigned long long m = __ballot(pred);
+      if (pred) d.scr[(int64_t)i * kRowMax + __popcll(m & ((1ull << lane) - 1ull))] = j;
+      written = __popcll(m);
+      owned = __popcll(__ballot(pred && j > i));
+    } else {
+      search_row_global(d, X, i, srs, srl, total, margin, lane, written, owned);
+    }
+    if (lane == 0) {
+      d.ncnt[i] = written;
+      d.ocnt[i] = owned;
+      if (written > kRowMax) push_overflow(d, i);
     }
   }
+}
+
+void launch_nbr_search(DevState& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_search, dim3((unsigned)d.nbins_total), dim3(256), 0, s, d);
+}
+
+// overflow rows: one wavefront per row, candidates straight from global memory,
+// written to the final row with the slots of the owner entries
+__global__ __launch_bounds__(64) void k_nbr_fill_overflow(DevState d) {
+  __shared__ int32_t srs[27], srl[27];
+  const int32_t i = d.ovf[blockIdx.x];
+  const SampleConst& c = d.sc[d.sample[i]];
+  const double4* X = d.xr[d.cur];
+  const double4 pi = X[i];
+  const int cx = bin_coord(pi.x, c.blo[0], c.bh[0], c.bn[0]);
+  const int cy = bin_coord(pi.y, c.blo[1], c.bh[1], c.bn[1]);
+  const int cz = bin_coord(pi.z, c.blo[2], c.bh[2], c.bn[2]);
+  const int lane = threadIdx.x;
+  if (lane < 27) cell_range(d, c, cx, cy, cz, lane, srs[lane], srl[lane]);
   __syncthreads();
   int total = 0;
   for (int k = 0; k < 27; ++k) total += srl[k];
-  const bool staged = total <= kLdsCand;
-  const double4* X = d.xr[d.cur];
-  if (staged) {
-    for (int t = t0; t < total; t += 256) {
-      int acc = 0, j = -1;
-      for (int k = 0; k < 27; ++k) {
-        if (j < 0 && t < acc + srl[k]) j = srs[k] + (t - acc);
-        acc += srl[k];
+  const int32_t row = d.nrow[i], hbase = d.hrow[i];
+  const int pre_n = d.ncnt[i] - d.ocnt[i];
+  int written = 0;
+  for (int base = 0; base < total; base += 64) {
+    const int t = base + lane;
+    bool pred = false;
+    int32_t j = -1;
+    if (t < total) {
+      j = cand_index(srs, srl, t);
+      pred = j != i && is_candidate(pi, X[j], c.margin);
+    }
+    const unsigned long long m = __ballot(pred);
+    if (pred) {
+      const int pos = written + __popcll(m & ((1ull << lane) - 1ull));
+      d.nbr[row + pos] = j;
+      if (j > i) {
+        const int slot = hbase + (pos - pre_n);
+        d.nslot[row + pos] = slot;
+        d.sown[slot] = i;
+        d.spart[slot] = j;
       }
-      const double4 p = X[j];
-      sx[t] = make_float4((float)(p.x - ox), (float)(p.y - oy), (float)(p.z - oz), (float)p.w);
-      sj[t] = j;
     }
-  }
-  __syncthreads();
-  const int lane = t0 & 63, wv = t0 >> 6;
-  const double margin = c.margin;
-  const float marginf = (float)margin;
-  // absolute slack: the relative coordinates span at most two cells, each
-  // rounded to FP32 (relative error 2^-24); 3e-6 of a cell side covers it many times
-  const float slack = 3e-6f * (float)fmax(c.bh[0], fmax(c.bh[1], c.bh[2]));
-  for (int32_t i = h0 + wv; i < h1; i += 4) {
-    const double4 pi = X[i];
-    const float pix = (float)(pi.x - ox), piy = (float)(pi.y - oy), piz = (float)(pi.z - oz), pir = (float)pi.w;
-    int written = 0, owned = 0;
-    int row = 0, pre_n = 0, hbase = 0;
-    if (kFill) {
-      row = d.nrow[i];
-      pre_n = d.ncnt[i] - d.ocnt[i];
-      hbase = d.hrow[i];
-    }
-    for (int base = 0; base < total; base += 64) {
-      const int t = base + lane;
-      bool pred = false;
-      int j = -1;
-      if (t < total) {
-        bool maybe;
-        if (staged) {
-          const float4 q = sx[t];
-          j = sj[t];
-          const float ex = q.x - pix, ey = q.y - piy, ez = q.z - piz;
-          const float cf = ((pir + q.w) + marginf) * 1.0001f + slack;
-          maybe = (ex * ex + ey * ey) + ez * ez < cf * cf;
-        } else {
-          int acc = 0;
-          for (int k = 0; k < 27; ++k) {
-            if (j < 0 && t < acc + srl[k]) j = srs[k] + (t - acc);
-            acc += srl[k];
-          }
-          maybe = true;
-        }
-        if (maybe && j != i) {
-          const double4 pj = X[j];
-          double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-          double d2 = (dx * dx + dy * dy) + dz * dz;
-          double cc = (pi.w + pj.w) + margin;
-          pred = d2 < cc * cc;
-        }
-      }
-      const unsigned long long mask = __ballot(pred);
-      const unsigned long long omask = __ballot(pred && j > i);
-      if (kFill && pred) {
-        int pos = written + __popcll(mask & ((1ull << lane) - 1ull));
-        d.nbr[row + pos] = j;
-        if (j > i) {
-          int slot = hbase + (pos - pre_n);
-          d.nslot[row + pos] = slot;
-          d.sown[slot] = i;
-          d.spart[slot] = j;
-        }
-      }
-      written += __popcll(mask);
-      owned += __popcll(omask);
-    }
-    if (!kFill && lane == 0) {
-      d.ncnt[i] = written;
-      d.ocnt[i] = owned;
-    }
+    written += __popcll(m);
   }
 }
 
-void launch_nbr_count(DevState& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_search<false>, dim3((unsigned)d.nbins_total), dim3(256), 0, s, d);
-}
-void launch_nbr_fill(DevState& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_search<true>, dim3((unsigned)d.nbins_total), dim3(256), 0, s, d);
-}
-
-// slot of every mirror entry (j < i): the owner entry i in row j, found by
-// binary search in that row's sorted partners
-__global__ void k_nbr_mirror(DevState d) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// scratch rows to the final rows: a group of 8 lanes per particle.  Owner
+// entries (j > i) get the next half-pair slot of the row; a mirror entry takes
+// the slot of the owner entry i in row j, found by binary search in row j
+// (its scratch row, or its final row when row j overflowed).
+__global__ __launch_bounds__(256) void k_nbr_copy(DevState d) {
+  const int sub = threadIdx.x & 7;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   if (i >= d.n) return;
+  const int cnt = d.ncnt[i];
+  if (cnt > kRowMax) return;
+  const int32_t row = d.nrow[i], hbase = d.hrow[i];
+  const int pre_n = cnt - d.ocnt[i];
+  const int32_t* src = d.scr + i * kRowMax;
+  for (int k = sub; k < cnt; k += 8) {
+    const int32_t j = src[k];
+    d.nbr[row + k] = j;
+    int32_t slot;
+    if (j > (int32_t)i) {
+      slot = hbase + (k - pre_n);
+      d.sown[slot] = (int32_t)i;
+      d.spart[slot] = j;
+    } else {
+      const int cj = d.ncnt[j];
+      if (cj <= kRowMax) {
+        const int32_t* rj = d.scr + (int64_t)j * kRowMax;
+        int lo = 0, hi = cj;
+        while (lo < hi) {
+          int mid = (lo + hi) >> 1;
+          if (rj[mid] < (int32_t)i) lo = mid + 1; else hi = mid;
+        }
+        slot = d.hrow[j] + (lo - (cj - d.ocnt[j]));
+      } else {
+        int32_t lo = d.nrow[j], hi = d.nrow[j + 1];
+        while (lo < hi) {
+          int32_t mid = (lo + hi) >> 1;
+          if (d.nbr[mid] < (int32_t)i) lo = mid + 1; else hi = mid;
+        }
+        slot = d.nslot[lo];
+      }
+    }
+    d.nslot[row + k] = slot;
+  }
+}
+
+// mirror entries of the overflow rows (after every owner entry is final)
+__global__ void k_nbr_mirror_overflow(DevState d, int novf) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= novf) return;
+  const int32_t i = d.ovf[q];
   const int32_t r0 = d.nrow[i];
   const int32_t nmir = d.ncnt[i] - d.ocnt[i];
   for (int32_t e = r0; e < r0 + nmir; ++e) {
-    int32_t j = d.nbr[e];
+    const int32_t j = d.nbr[e];
     int32_t lo = d.nrow[j], hi = d.nrow[j + 1];
     while (lo < hi) {
       int32_t mid = (lo + hi) >> 1;
-      if (d.nbr[mid] < (int32_t)i) lo = mid + 1; else hi = mid;
+      if (d.nbr[mid] < i) lo = mid + 1; else hi = mid;
     }
     d.nslot[e] = d.nslot[lo];
   }
 }
-void launch_nbr_mirror(DevState& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_mirror, dim3(nblk(d.n)), dim3(kBlock), 0, s, d);
+
+void launch_nbr_fill(DevState& d, int novf, hipStream_t s) {
+  if (novf > 0) hipLaunchKernelGGL(k_nbr_fill_overflow, dim3(novf), dim3(64), 0, s, d);
+  hipLaunchKernelGGL(k_nbr_copy, dim3(nblk(d.n * 8)), dim3(kBlock), 0, s, d);
+  if (novf > 0) hipLaunchKernelGGL(k_nbr_mirror_overflow, dim3(nblk(novf)), dim3(kBlock), 0, s, d, novf);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,78 +409,74 @@ void launch_wall_fill(DevState& d, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// history merge: every half pair and wall entry that existed in the previous
-// list keeps its elongation and flags (found through the permutation)
+// history carry: every half pair and wall entry of the previous list keeps its
+// elongation and flags in the new list (found through the permutation)
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_hist_merge(DevState d, int check_lost) {
+__global__ void k_zero_slots(DevState d) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < d.nslots) {
-    int32_t i = d.sown[p], j = d.spart[p];
-    int32_t oi = d.order[i], oj = d.order[j];
-    int32_t o = oi < oj ? oi : oj, q = oi < oj ? oj : oi;
-    int32_t lo = d.nrow_o[o], hi = d.nrow_o[o + 1];
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (d.nbr_o[mid] < q) lo = mid + 1; else hi = mid;
-    }
-    R4<R> h = mk4<R>(0, 0, 0, 0);
-    uint8_t fl = 0;
-    if (lo < d.nrow_o[o + 1] && d.nbr_o[lo] == q) {
-      int32_t so = d.nslot_o[lo];
-      h = ((const R4<R>*)d.hdt_o)[so];
-      fl = d.pfl_o[so];
-      if (oi > oj) { h.x = -h.x; h.y = -h.y; h.z = -h.z; }
-      if (check_lost && (fl & 1)) atomicAdd(&d.scratch_i[1], 1);
-    }
+  if (p >= d.nslots) return;
+  ((R4<R>*)d.hdt[d.cur])[p] = mk4<R>(0, 0, 0, 0);
+  d.pfl[d.cur][p] = 0;
+}
+
+// one thread per half pair of the previous list; pairs with no state (not
+// touching, not bonded, zero elongation) have nothing to carry.  A bonded pair
+// whose partners are both alive must be in the new list: the candidate margin
+// covers the largest pull-off separation, so a miss means the margin failed.
+template <typename R>
+__global__ void k_carry_pairs(DevState d, int check_lost) {
+  int64_t so = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (so >= d.nslots_o) return;
+  const uint8_t fl = d.pfl_o[so];
+  R4<R> h = ((const R4<R>*)d.hdt_o)[so];
+  if (fl == 0 && h.x == (R)0 && h.y == (R)0 && h.z == (R)0) return;
+  const int32_t A = d.inv_order[d.sown_o[so]], B = d.inv_order[d.spart_o[so]];
+  const uint8_t* al = d.alive[d.cur];
+  if (!al[A] || !al[B]) return;
+  const int32_t o = A < B ? A : B, q = A < B ? B : A;
+  int32_t lo = d.nrow[o], hi = d.nrow[o + 1];
+  while (lo < hi) {
+    int32_t mid = (lo + hi) >> 1;
+    if (d.nbr[mid] < q) lo = mid + 1; else hi = mid;
+  }
+  if (lo < d.nrow[o + 1] && d.nbr[lo] == q) {
+    const int32_t p = d.nslot[lo];
+    if (A > B) { h.x = -h.x; h.y = -h.y; h.z = -h.z; }
     ((R4<R>*)d.hdt[d.cur])[p] = h;
     d.pfl[d.cur][p] = fl;
+  } else if (check_lost && (fl & 1)) {
+    atomicOr(d.status, (int)kStLostBond);
   }
-  int64_t e = p;
-  if (e < d.nwall) {
-    int32_t lo = 0, hi = (int32_t)d.n;
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (d.wrow[mid + 1] <= e) lo = mid + 1; else hi = mid;
-    }
-    int32_t i = lo;
-    int32_t w = d.wid[e];
-    int32_t oi = d.order[i];
+}
+
+// one thread per particle: its wall entries, matched by wall id in its old row
+template <typename R>
+__global__ void k_carry_walls(DevState d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const int32_t e0 = d.wrow[i], e1 = d.wrow[i + 1];
+  if (e0 == e1) return;
+  const int32_t oi = d.order[i];
+  const int32_t q0 = d.wrow_o[oi], q1 = d.wrow_o[oi + 1];
+  for (int32_t e = e0; e < e1; ++e) {
+    const int32_t w = d.wid[e];
     R4<R> h = mk4<R>(0, 0, 0, 0);
     uint8_t fl = 0;
-    for (int32_t q = d.wrow_o[oi]; q < d.wrow_o[oi + 1]; ++q)
+    for (int32_t q = q0; q < q1; ++q)
       if (d.wid_o[q] == w) { h = ((const R4<R>*)d.wdt_o)[q]; fl = d.wfl_o[q]; }
     ((R4<R>*)d.wdt)[e] = h;
     d.wfl[e] = fl;
   }
 }
 
-template <typename R> void launch_hist_merge(DevState& d, hipStream_t s, int check_lost) {
-  int64_t m = d.nslots > d.nwall ? d.nslots : d.nwall;
-  if (m > 0) hipLaunchKernelGGL(k_hist_merge<R>, dim3(nblk(m)), dim3(kBlock), 0, s, d, check_lost);
+template <typename R> void launch_hist_carry(DevState& d, hipStream_t s, int check_lost) {
+  if (d.nslots > 0) hipLaunchKernelGGL(k_zero_slots<R>, dim3(nblk(d.nslots)), dim3(kBlock), 0, s, d);
+  if (d.nslots_o > 0) hipLaunchKernelGGL(k_carry_pairs<R>, dim3(nblk(d.nslots_o)), dim3(kBlock), 0, s, d, check_lost);
+  if (d.nwall > 0) hipLaunchKernelGGL(k_carry_walls<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d);
 }
-template void launch_hist_merge<double>(DevState&, hipStream_t, int);
-template void launch_hist_merge<float>(DevState&, hipStream_t, int);
-
-// bonded half pairs of the previous list whose partners are both alive
-__global__ void k_count_old_bonds(DevState d) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= d.nslots_o) return;
-  if (!(d.pfl_o[p] & 1)) return;
-  int32_t a = d.inv_order[d.sown_o[p]], b = d.inv_order[d.spart_o[p]];
-  if (d.alive[d.cur][a] && d.alive[d.cur][b]) atomicAdd(&d.scratch_i[0], 1);
-}
-void launch_count_old_bonds(DevState& d, hipStream_t s) {
-  (void)hipMemsetAsync(d.scratch_i, 0, 2 * sizeof(int), s);
-  if (d.nslots_o > 0) hipLaunchKernelGGL(k_count_old_bonds, dim3(nblk(d.nslots_o)), dim3(kBlock), 0, s, d);
-}
-
-__global__ void k_check_lost(DevState d) {
-  if (d.scratch_i[0] != d.scratch_i[1]) atomicOr(d.status, (int)kStLostBond);
-}
-void launch_check_lost(DevState& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_lost, dim3(1), dim3(1), 0, s, d);
-}
+template void launch_hist_carry<double>(DevState&, hipStream_t, int);
+template void launch_hist_carry<float>(DevState&, hipStream_t, int);
 
 // bond every touching pair (initial state of the modified JKR model)
 __global__ void k_mark_bonds(DevState d) {

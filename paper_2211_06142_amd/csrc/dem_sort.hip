@@ -59,15 +59,21 @@ void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hi
 // ---------------------------------------------------------------------------
 // stable bucket sort: count, scan, scatter to arbitrary slots, then rank every
 // bucket's members by (tiebreak, index) -- one wavefront per bucket, members
-// staged in LDS when the bucket holds at most 64 of them
+// staged in LDS when the bucket holds at most 64 of them.  Sink buckets (dead
+// particles, particles outside every fluid grid) keep the scatter order: their
+// order reaches no result, and a sink can hold a large share of all particles,
+// where the rank (quadratic in the bucket size) would not scale.  With a gate
+// flag set, the whole sort does nothing.
 // ---------------------------------------------------------------------------
-__global__ void k_bucket_count(const uint32_t* key, int64_t n, int32_t* cnt) {
+__global__ void k_bucket_count(const uint32_t* key, int64_t n, int32_t* cnt, const int* gate) {
+  if (gate && *gate) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) atomicAdd(&cnt[key[i]], 1);
 }
 
 __global__ void k_bucket_scatter(const uint32_t* key, int64_t n, const int32_t* off, int32_t* fill,
-                                 int32_t* order) {
+                                 int32_t* order, const int* gate) {
+  if (gate && *gate) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t k = key[i];
@@ -76,9 +82,11 @@ __global__ void k_bucket_scatter(const uint32_t* key, int64_t n, const int32_t* 
 }
 
 __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t nb, const int32_t* src,
-                                                     const int32_t* tiebreak, int32_t* dst) {
+                                                     const int32_t* tiebreak, int32_t* dst, const uint8_t* sink,
+                                                     const int* gate) {
   __shared__ int32_t sm[4][64];
   __shared__ int32_t sk[4][64];
+  if (gate && *gate) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t b = (int64_t)blockIdx.x * 4 + w;
   int32_t lo = 0, k = 0;
@@ -94,6 +102,10 @@ __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t
   }
   __syncthreads();
   if (b >= nb || k == 0) return;
+  if (sink && sink[b]) {
+    for (int32_t t = lane; t < k; t += 64) dst[lo + t] = src[lo + t];
+    return;
+  }
   if (small) {
     if (lane < k) {
       int32_t v = sm[w][lane], kv = sk[w][lane], rank = 0;
@@ -120,14 +132,15 @@ __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t
 
 void launch_bucket_sort(const uint32_t* key, int64_t n, int64_t nb, const int32_t* tiebreak, int32_t* cnt,
                         int32_t* off, int32_t* fill, int32_t* order_tmp, int32_t* out_order,
-                        int32_t* scan_tmp, hipStream_t s) {
+                        int32_t* scan_tmp, const uint8_t* sink, const int* gate, hipStream_t s) {
   (void)hipMemsetAsync(cnt, 0, sizeof(int32_t) * (nb + 1), s);
   (void)hipMemsetAsync(fill, 0, sizeof(int32_t) * (nb + 1), s);
-  if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt);
+  if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt, gate);
   scan_exclusive(cnt, off, nb + 1, scan_tmp, s);
   if (n > 0)
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, off, fill, order_tmp);
-  hipLaunchKernelGGL(k_bucket_rank, dim3(nblk(nb, 4)), dim3(256), 0, s, off, nb, order_tmp, tiebreak, out_order);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, off, fill, order_tmp, gate);
+  hipLaunchKernelGGL(k_bucket_rank, dim3(nblk(nb, 4)), dim3(256), 0, s, off, nb, order_tmp, tiebreak, out_order,
+                     sink, gate);
 }
 
 }  // namespace dem

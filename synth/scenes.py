@@ -57,3 +57,35 @@ def plane(normal, offset):
 def incline_gravity(theta, g=9.81):
     """Gravity for a floor z = 0 tilted by theta about y: the slope points +x."""
     return (g * math.sin(theta), 0.0, -g * math.cos(theta))
+
+
+def shells_in_gas(rng, side=2.0e-3, r_big=3.0e-4, r_small=4.0e-5, shell_n=100, n_gas=3000, overlap=1e-7):
+    """Two large spheres, each carrying a shell of shell_n small spheres that
+    touch it (Fibonacci points, overlap `overlap`), in a gas of n_gas small
+    spheres placed by rejection sampling.  The large spheres have rows of more
+    than shell_n partners and the binning cells (sized by the large radius)
+    hold many small spheres: the crowded corners of the neighbour search."""
+    centres = np.array([[0.3 * side, 0.5 * side, 0.5 * side], [0.7 * side, 0.5 * side, 0.5 * side]])
+    xs, rs = [c for c in centres], [r_big, r_big]
+    k = np.arange(shell_n) + 0.5
+    phi = np.arccos(1.0 - 2.0 * k / shell_n)
+    th = math.pi * (1.0 + 5.0 ** 0.5) * k
+    u = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
+    for c in centres:
+        for e in u:
+            xs.append(c + (r_big + r_small - overlap) * e)
+            rs.append(r_small)
+    x = np.array(xs)
+    r = np.array(rs)
+    placed = 0
+    gas = []
+    while placed < n_gas:
+        p = rng.uniform(r_small, side - r_small, 3)
+        allx = np.vstack([x] + gas) if gas else x
+        allr = np.concatenate([r, np.full(len(gas), r_small)])
+        if np.all(np.linalg.norm(allx - p, axis=1) > allr + r_small + 1e-6):
+            gas.append(p[None, :])
+            placed += 1
+    x = np.vstack([x] + gas)
+    r = np.concatenate([r, np.full(n_gas, r_small)])
+    return x, r

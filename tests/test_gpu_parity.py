@@ -87,6 +87,37 @@ def test_contact_sets_random_polydisperse(seed):
     np.testing.assert_array_equal(g.pairs(which=2)["pairs"], oracle.pairs(x, r, extra=margin))
 
 
+def test_long_rows_and_crowded_cells():
+    """Rows longer than the scratch stride and binning cells too full for LDS
+    (a large sphere with a shell of 100 touching small ones, in a dense gas):
+    contact sets bit-exact, then 10 FP64 steps against the oracle, so the
+    half-pair slots of the long rows must be right for the history to agree."""
+    x, r = scenes.shells_in_gas(np.random.default_rng(5))
+    w = dict(synth.c0())
+    w["fluid"] = None
+    w["walls"] = []
+    g = gpu_for(w, "fp64", x=x, r=r)
+    margin = g.info()["cutoff_margin"]
+    cand = oracle.pairs(x, r, extra=margin)
+    assert np.bincount(cand.ravel(), minlength=len(r)).max() > 64
+    np.testing.assert_array_equal(g.pairs(which=1)["pairs"], oracle.pairs(x, r, extra=0.0))
+    np.testing.assert_array_equal(g.pairs(which=2)["pairs"], cand)
+    o = oracle_for(w, x=x, r=r, bond_at_init=True)
+    g.step(5)
+    g.request_rebuild()       # the history of the long rows is carried through a rebuild
+    g.step(5)
+    o.step(10)
+    gs, os_ = g.state(), o.state()
+    assert scaled_err(gs["F"], os_["F"], os_["fscale"]) < 1e-12
+    assert scaled_err(gs["T"], os_["T"], os_["tscale"]) < 1e-12
+    np.testing.assert_allclose(gs["x"], os_["x"], rtol=0, atol=1e-16)
+    gp, op_ = g.pairs(which=0), o.pairs()
+    np.testing.assert_array_equal(gp["pairs"], op_["pairs"])
+    np.testing.assert_array_equal(gp["bonded"], op_["bonded"])
+    dts = np.abs(op_["dt"]).max() + 1e-30
+    np.testing.assert_allclose(gp["dt"], op_["dt"], rtol=0, atol=1e-11 * dts)
+
+
 # ---------------------------------------------------------------------------
 # one and several steps, FP64
 # ---------------------------------------------------------------------------
