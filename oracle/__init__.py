@@ -100,6 +100,14 @@ def lib():
         L.or_set_fluid.argtypes = [vp, vp, vp]
         L.or_set_closure.restype = ctypes.c_int
         L.or_set_closure.argtypes = [vp, vp, vp]
+        L.or_set_closure_mlp.restype = ctypes.c_int
+        L.or_set_closure_mlp.argtypes = [vp, vp, vp]
+        L.or_closure_features.restype = ctypes.c_int
+        L.or_closure_features.argtypes = [vp, vp]
+        L.or_mlp_forward.restype = None
+        L.or_mlp_forward.argtypes = [vp, vp, vp]
+        L.or_get_closure.restype = None
+        L.or_get_closure.argtypes = [vp, vp, vp]
         L.or_step.restype = ctypes.c_int
         L.or_step.argtypes = [vp, i64]
         L.or_get_state.restype = None
@@ -150,6 +158,18 @@ def bond_holds(d2, c, Rs, Es, gamma):
 
 def beta_of_e(e):
     return lib().or_beta_of_e(e)
+
+
+def mlp_forward(params, xh):
+    """the C oracle's forward pass of the closure network, one row at a time"""
+    pp = _f64(params, (8898,))
+    xs = np.ascontiguousarray(np.asarray(xh, np.float64).reshape(-1, 6))
+    y = np.zeros((xs.shape[0], 2))
+    for k in range(xs.shape[0]):
+        row, out = np.ascontiguousarray(xs[k]), np.zeros(2)
+        lib().or_mlp_forward(_ptr(pp), _ptr(row), _ptr(out))
+        y[k] = out
+    return y
 
 
 def drag(slip, d, k_cg, n, rho_f, mu_f, c_drag=1.0):
@@ -278,6 +298,27 @@ class OracleSim:
         cd = None if c_drag is None else _f64(c_drag)
         cc = None if c_coh is None else _f64(c_coh)
         lib().or_set_closure(self.h, _ptr(cd), _ptr(cc))
+
+    def set_closure_mlp(self, params=None, norm=None):
+        """Learned closure: FP64 parameters (8898) and norm = (mean[6], sd[6]);
+        params None switches it off."""
+        if params is None:
+            lib().or_set_closure_mlp(self.h, None, None)
+            return
+        pp = _f64(params, (8898,))
+        nn = _f64(norm, (12,))
+        lib().or_set_closure_mlp(self.h, _ptr(pp), _ptr(nn))
+
+    def closure_features(self):
+        f = np.zeros((self.n, 6))
+        lib().or_closure_features(self.h, _ptr(f))
+        return f
+
+    def closure_factors(self):
+        """(c_drag, c_coh) of the last coupling evaluation (ones when unset)"""
+        cd, cc = np.zeros(self.n), np.zeros(self.n)
+        lib().or_get_closure(self.h, _ptr(cd), _ptr(cc))
+        return cd, cc
 
     def step(self, nsteps=1):
         rc = lib().or_step(self.h, int(nsteps))

@@ -259,6 +259,8 @@ struct or_sim {
   double *u_cell, *gp_cell; int have_fluid;
   double *eps_cell, *fd_cell;
   double *c_drag, *c_coh;
+  double* mlp;                    /* closure network parameters (NULL: off) */
+  double mlp_norm[12];            /* feature mean[6], standard deviation[6] */
   double Es, Gs, beta;
   double produced;
   int64_t broken, step;
@@ -349,7 +351,7 @@ void or_destroy(or_sim* s) {
   free(s->fscale); free(s->tscale); free(s->m); free(s->I); free(s->alive);
   free(s->h); free(s->wall_dt); free(s->fdrag); free(s->fbuoy);
   free(s->u_cell); free(s->gp_cell); free(s->eps_cell); free(s->fd_cell);
-  free(s->c_drag); free(s->c_coh);
+  free(s->c_drag); free(s->c_coh); free(s->mlp);
   free(s);
 }
 
@@ -522,13 +524,18 @@ static void particle_cells(const or_sim* s, const double* x, cellw* o) {
       }
 }
 
-static void coupling(or_sim* s) {
+static double cell_volume(const or_sim* s) {
+  const or_grid* g = &s->p.grid;
+  return ((g->hi[0] - g->lo[0]) / g->n[0]) * ((g->hi[1] - g->lo[1]) / g->n[1]) *
+         ((g->hi[2] - g->lo[2]) / g->n[2]);
+}
+
+/* solid volume fraction per cell (porosity n of eq 6 is 1 - eps), clamped
+ * porosity and interstitial fluid velocity per cell */
+static void porosity_fields(or_sim* s, double* ncell, double* ucell) {
   const or_params* p = &s->p;
-  const or_grid* g = &p->grid;
   int64_t nc = ncells(s);
-  double vcell = ((g->hi[0] - g->lo[0]) / g->n[0]) * ((g->hi[1] - g->lo[1]) / g->n[1]) *
-                 ((g->hi[2] - g->lo[2]) / g->n[2]);
-  /* solid volume fraction per cell (porosity n of eq 6 is 1 - eps) */
+  double vcell = cell_volume(s);
   for (int64_t c = 0; c < nc; ++c) s->eps_cell[c] = 0.0;
   for (int64_t i = 0; i < s->n; ++i) {
     if (!s->alive[i]) continue;
@@ -537,8 +544,6 @@ static void coupling(or_sim* s) {
     for (int k = 0; k < cw.cnt; ++k) s->eps_cell[cw.cell[k]] += cw.w[k] * V;
   }
   for (int64_t c = 0; c < nc; ++c) s->eps_cell[c] /= vcell;
-  double* ncell = (double*)malloc(sizeof(double) * nc);
-  double* ucell = (double*)malloc(sizeof(double) * 3 * nc);
   for (int64_t c = 0; c < nc; ++c) {
     double nn = 1.0 - s->eps_cell[c];
     if (nn < p->n_min) nn = p->n_min;
@@ -546,19 +551,153 @@ static void coupling(or_sim* s) {
     ncell[c] = nn;
     for (int k = 0; k < 3; ++k) ucell[3 * c + k] = p->u_superficial ? s->u_cell[3 * c + k] / nn : s->u_cell[3 * c + k];
   }
+}
+
+/* porosity, fluid velocity and dynamic pressure gradient at particle i (the
+ * same cell weights as the deposition) */
+static void particle_fluid(const or_sim* s, int64_t i, const double* ncell, const double* ucell, double* np,
+                           double u[3], double gp[3]) {
+  cellw cw; particle_cells(s, &s->x[3 * i], &cw);
+  *np = 0.0;
+  for (int c = 0; c < 3; ++c) { u[c] = 0.0; gp[c] = 0.0; }
+  for (int k = 0; k < cw.cnt; ++k) {
+    *np += cw.w[k] * ncell[cw.cell[k]];
+    for (int c = 0; c < 3; ++c) {
+      u[c] += cw.w[k] * ucell[3 * cw.cell[k] + c];
+      gp[c] += cw.w[k] * s->gp_cell[3 * cw.cell[k] + c];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* learned closure (an extension; not in the paper)                     */
+/* ------------------------------------------------------------------ */
+/* Features of particle i: porosity at the particle, slip speed |u - v|, the
+ * particle Reynolds number of the drag law (eq 11, fine diameter d/k), the
+ * coarse-graining factor k, the mean of delta/R* over the pairs that took part
+ * in the last force evaluation (delta = r_i + r_j - |x_j - x_i| at the current
+ * positions) and the number of those pairs.  Dead particles: all zero. */
+static void closure_features(const or_sim* s, const double* ncell, const double* ucell, double* feat) {
+  const or_params* p = &s->p;
+  int64_t n = s->n;
+  double* sum = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double* cnt = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  for (int64_t k = 0; k < s->nh; ++k) {
+    int64_t i = s->h[k].i, j = s->h[k].j;
+    if (!s->alive[i] || !s->alive[j]) continue;
+    double dx[3];
+    for (int c = 0; c < 3; ++c) dx[c] = s->x[3 * j + c] - s->x[3 * i + c];
+    double delta = (s->r[i] + s->r[j]) - norm3(dx);
+    double Rs = s->r[i] * s->r[j] / (s->r[i] + s->r[j]);
+    sum[i] += delta / Rs; sum[j] += delta / Rs;
+    cnt[i] += 1.0; cnt[j] += 1.0;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    double* f = &feat[6 * i];
+    for (int c = 0; c < 6; ++c) f[c] = 0.0;
+    if (!s->alive[i]) continue;
+    double np, u[3], gp[3];
+    particle_fluid(s, i, ncell, ucell, &np, u, gp);
+    double sl[3];
+    for (int c = 0; c < 3; ++c) sl[c] = u[c] - s->v[3 * i + c];
+    double sm = norm3(sl);
+    f[0] = np;
+    f[1] = sm;
+    f[2] = p->rho_f * (2.0 * s->r[i] / p->k_cg) * sm / p->mu_f;
+    f[3] = p->k_cg;
+    f[4] = cnt[i] > 0.0 ? sum[i] / cnt[i] : 0.0;
+    f[5] = cnt[i];
+  }
+  free(sum); free(cnt);
+}
+
+static double gelu(double x) { return 0.5 * x * (1.0 + erf(x / sqrt(2.0))); }
+
+/* network 6 -> 64 -> 64 -> 64 -> 2, GELU on the hidden layers; flat parameters
+ * W1 6x64 | b1 | W2 64x64 | b2 | W3 64x64 | b3 | W4 64x2 | b4, W[k][m] row-major */
+void or_mlp_forward(const double* prm, const double* xh, double* y) {
+  static const int sz[5] = {6, 64, 64, 64, 2};
+  double h[64], z[64];
+  for (int k = 0; k < 6; ++k) h[k] = xh[k];
+  const double* q = prm;
+  for (int l = 0; l < 4; ++l) {
+    int K = sz[l], M = sz[l + 1];
+    const double* W = q;
+    const double* b = q + K * M;
+    for (int m = 0; m < M; ++m) {
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k) acc += h[k] * W[k * M + m];
+      z[m] = acc + b[m];
+    }
+    for (int m = 0; m < M; ++m) h[m] = l < 3 ? gelu(z[m]) : z[m];
+    q += K * M + M;
+  }
+  y[0] = h[0];
+  y[1] = h[1];
+}
+
+/* closure factors c = exp(clip(y, -ln 2, ln 2)) of every particle */
+static void closure_apply(or_sim* s, const double* ncell, const double* ucell) {
+  int64_t n = s->n;
+  double* feat = (double*)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
+  closure_features(s, ncell, ucell, feat);
+  if (!s->c_drag) s->c_drag = dup(NULL, n);
+  if (!s->c_coh) s->c_coh = dup(NULL, n);
+  const double L2 = log(2.0);
+  for (int64_t i = 0; i < n; ++i) {
+    double xh[6], y[2];
+    for (int c = 0; c < 6; ++c) xh[c] = (feat[6 * i + c] - s->mlp_norm[c]) / s->mlp_norm[6 + c];
+    or_mlp_forward(s->mlp, xh, y);
+    for (int c = 0; c < 2; ++c) {
+      if (y[c] < -L2) y[c] = -L2;
+      if (y[c] > L2) y[c] = L2;
+    }
+    s->c_drag[i] = exp(y[0]);
+    s->c_coh[i] = exp(y[1]);
+  }
+  free(feat);
+}
+
+int or_set_closure_mlp(or_sim* s, const double* params, const double* norm) {
+  free(s->mlp);
+  s->mlp = NULL;
+  if (!params) return 0;
+  s->mlp = dup(params, OR_MLP_NPARAMS);
+  for (int c = 0; c < 12; ++c) s->mlp_norm[c] = norm[c];
+  return 0;
+}
+
+void or_get_closure(const or_sim* s, double* c_drag, double* c_coh) {
+  for (int64_t i = 0; i < s->n; ++i) {
+    c_drag[i] = s->c_drag ? s->c_drag[i] : 1.0;
+    c_coh[i] = s->c_coh ? s->c_coh[i] : 1.0;
+  }
+}
+
+int or_closure_features(or_sim* s, double* feat) {
+  int64_t nc = ncells(s);
+  double* ncell = (double*)malloc(sizeof(double) * (nc > 0 ? nc : 1));
+  double* ucell = (double*)malloc(sizeof(double) * 3 * (nc > 0 ? nc : 1));
+  porosity_fields(s, ncell, ucell);
+  closure_features(s, ncell, ucell, feat);
+  free(ncell); free(ucell);
+  return 0;
+}
+
+static void coupling(or_sim* s) {
+  const or_params* p = &s->p;
+  int64_t nc = ncells(s);
+  double vcell = cell_volume(s);
+  double* ncell = (double*)malloc(sizeof(double) * nc);
+  double* ucell = (double*)malloc(sizeof(double) * 3 * nc);
+  porosity_fields(s, ncell, ucell);
+  if (s->mlp) closure_apply(s, ncell, ucell);
   for (int64_t c = 0; c < 3 * nc; ++c) s->fd_cell[c] = 0.0;
   for (int64_t i = 0; i < s->n; ++i) {
     for (int k = 0; k < 3; ++k) { s->fdrag[3 * i + k] = 0.0; s->fbuoy[3 * i + k] = 0.0; }
     if (!s->alive[i]) continue;
-    cellw cw; particle_cells(s, &s->x[3 * i], &cw);
-    double np = 0.0, u[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
-    for (int k = 0; k < cw.cnt; ++k) {
-      np += cw.w[k] * ncell[cw.cell[k]];
-      for (int c = 0; c < 3; ++c) {
-        u[c] += cw.w[k] * ucell[3 * cw.cell[k] + c];
-        gp[c] += cw.w[k] * s->gp_cell[3 * cw.cell[k] + c];
-      }
-    }
+    double np, u[3], gp[3];
+    particle_fluid(s, i, ncell, ucell, &np, u, gp);
     double sl[3];
     for (int c = 0; c < 3; ++c) sl[c] = u[c] - s->v[3 * i + c];
     double cd = s->c_drag ? s->c_drag[i] : 1.0;
@@ -567,6 +706,7 @@ static void coupling(or_sim* s) {
     double V = (4.0 / 3.0) * M_PI * s->r[i] * s->r[i] * s->r[i];
     for (int c = 0; c < 3; ++c) s->fbuoy[3 * i + c] = -V * (gp[c] + p->rho_f * p->g[c]);
     /* eq 7: drag source of each cell */
+    cellw cw; particle_cells(s, &s->x[3 * i], &cw);
     for (int k = 0; k < cw.cnt; ++k)
       for (int c = 0; c < 3; ++c) s->fd_cell[3 * cw.cell[k] + c] += cw.w[k] * s->fdrag[3 * i + c];
   }

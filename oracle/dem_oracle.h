@@ -94,6 +94,14 @@ or_sim* or_create(const or_params* p, int64_t n, const double* x, const double* 
 void    or_destroy(or_sim* s);
 int     or_set_fluid(or_sim* s, const double* u_cell, const double* gradp_cell);
 int     or_set_closure(or_sim* s, const double* c_drag, const double* c_coh);
+/* learned closure (an extension): flat FP64 parameters (OR_MLP_NPARAMS) and the
+ * feature normalisation mean[6], sd[6]; params NULL switches it off.  While on,
+ * every coupling evaluation recomputes c_drag and c_coh of every particle. */
+#define OR_MLP_NPARAMS 8898
+int     or_set_closure_mlp(or_sim* s, const double* params, const double* norm);
+int     or_closure_features(or_sim* s, double* feat);   /* n x 6 at the current state */
+void    or_mlp_forward(const double* params, const double* xh, double* y);
+void    or_get_closure(const or_sim* s, double* c_drag, double* c_coh);   /* ones when unset */
 int     or_step(or_sim* s, int64_t nsteps);
 void    or_get_state(const or_sim* s, double* x, double* v, double* w, double* F, double* T,
                      uint8_t* alive, double* fscale, double* tscale);
