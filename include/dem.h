@@ -223,6 +223,53 @@ dem_status dem_read_fault(dem_ctx* ctx, int32_t* bits);
 void dem_destroy(dem_ctx* ctx);
 const char* dem_status_str(dem_status s);
 
+/* ---- learned closure (an extension of the method; not in the paper) ----
+ * A network 6 -> 64 -> 64 -> 64 -> 2 (GELU, erf form) maps per-particle
+ * features x = [porosity at the particle, slip speed |u - v|, Re of eq 11,
+ * k, mean delta/R* over the pairs of the last force evaluation, their count],
+ * normalised as (x - mean) / sd, to y; the factors c = exp(clip(y, -ln 2,
+ * ln 2)) in [0.5, 2] multiply the particle's drag force (eq 8: c_drag = c[0])
+ * and scale the surface energy of a pair as gamma sqrt(c_i c_j) (c_coh = c[1]).
+ * Matrix products run on the matrix cores in BF16 with FP32 accumulation.
+ *
+ * Parameters: DEM_MLP_NPARAMS FP32 values, W1 6x64 | b1 64 | W2 64x64 | b2 64 |
+ * W3 64x64 | b3 64 | W4 64x2 | b4 2, each W[k][m] row-major with k the input.
+ * A dem_mlp holds FP32 master parameters, a BF16 copy used by every product,
+ * and Adam moments (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).  It is
+ * used on the stream given at creation; not thread-safe.
+ *
+ * dem_mlp_set_params / get_params: host or device pointer (8898 FP32); set
+ *   also zeroes the Adam moments and step count.
+ * dem_mlp_forward: x = batch x 6 normalised features (FP32, device), y =
+ *   batch x 2 raw outputs (FP32, device).  Asynchronous.
+ * dem_mlp_grad: loss L = mean over the batch and both outputs of (y - t)^2
+ *   for targets t (batch x 2, FP32, device); writes dL/dparams (8898 FP32, host
+ *   or device) and the loss (host, may be NULL).  Synchronises.
+ * dem_mlp_train_step: the same gradient, then one Adam step with learning rate
+ *   lr > 0 on the master parameters.  Synchronises when loss is not NULL.
+ * Errors: DEM_E_INVAL for NULL handles or buffers, batch < 0 or lr <= 0;
+ *   DEM_E_NOMEM when the batch buffers cannot grow.
+ *
+ * dem_set_closure: mlp NULL switches the closure off (factors 1).  Otherwise
+ *   the context takes a snapshot of the network's current parameters and
+ *   norm = mean[6], sd[6] (host, sd > 0); from the next coupling evaluation on,
+ *   every evaluation recomputes the features and factors of every particle
+ *   before the drag.  Until then the factors are 1.
+ * dem_read_closure: features (n x 6), c_drag, c_coh (n) of the latest
+ *   evaluation, in caller order, into host arrays (any may be NULL);
+ *   DEM_E_STATE if the closure is off.  Synchronises. */
+#define DEM_MLP_NPARAMS 8898
+typedef struct dem_mlp dem_mlp;
+dem_status dem_mlp_create(dem_mlp** out, int32_t device, void* hip_stream);
+void dem_mlp_destroy(dem_mlp* mlp);
+dem_status dem_mlp_set_params(dem_mlp* mlp, const float* params);
+dem_status dem_mlp_get_params(dem_mlp* mlp, float* params);
+dem_status dem_mlp_forward(dem_mlp* mlp, const float* x, float* y, int64_t batch);
+dem_status dem_mlp_grad(dem_mlp* mlp, const float* x, const float* t, int64_t batch, float* grad, float* loss);
+dem_status dem_mlp_train_step(dem_mlp* mlp, const float* x, const float* t, int64_t batch, float lr, float* loss);
+dem_status dem_set_closure(dem_ctx* ctx, const dem_mlp* mlp, const double* norm);
+dem_status dem_read_closure(dem_ctx* ctx, double* features, double* c_drag, double* c_coh);
+
 /* ---- coarse-graining helpers (host only, no device needed) ----
  * dem_cg_material: grain-scale surface energy and drag factor of section 2.4
  * (Table 3: rho, E, nu, e, mu unchanged, gamma x k).

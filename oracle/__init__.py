@@ -108,6 +108,8 @@ def lib():
         L.or_mlp_forward.argtypes = [vp, vp, vp]
         L.or_get_closure.restype = None
         L.or_get_closure.argtypes = [vp, vp, vp]
+        L.or_get_closure_features.restype = None
+        L.or_get_closure_features.argtypes = [vp, vp]
         L.or_step.restype = ctypes.c_int
         L.or_step.argtypes = [vp, i64]
         L.or_get_state.restype = None
@@ -312,6 +314,12 @@ class OracleSim:
     def closure_features(self):
         f = np.zeros((self.n, 6))
         lib().or_closure_features(self.h, _ptr(f))
+        return f
+
+    def closure_last_features(self):
+        """features of the latest coupling evaluation that ran the closure"""
+        f = np.zeros((self.n, 6))
+        lib().or_get_closure_features(self.h, _ptr(f))
         return f
 
     def closure_factors(self):

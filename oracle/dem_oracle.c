@@ -260,6 +260,7 @@ struct or_sim {
   double *eps_cell, *fd_cell;
   double *c_drag, *c_coh;
   double* mlp;                    /* closure network parameters (NULL: off) */
+  double* cfeat;                  /* n x 6 features of the latest closure evaluation */
   double mlp_norm[12];            /* feature mean[6], standard deviation[6] */
   double Es, Gs, beta;
   double produced;
@@ -351,7 +352,7 @@ void or_destroy(or_sim* s) {
   free(s->fscale); free(s->tscale); free(s->m); free(s->I); free(s->alive);
   free(s->h); free(s->wall_dt); free(s->fdrag); free(s->fbuoy);
   free(s->u_cell); free(s->gp_cell); free(s->eps_cell); free(s->fd_cell);
-  free(s->c_drag); free(s->c_coh); free(s->mlp);
+  free(s->c_drag); free(s->c_coh); free(s->mlp); free(s->cfeat);
   free(s);
 }
 
@@ -639,7 +640,8 @@ void or_mlp_forward(const double* prm, const double* xh, double* y) {
 /* closure factors c = exp(clip(y, -ln 2, ln 2)) of every particle */
 static void closure_apply(or_sim* s, const double* ncell, const double* ucell) {
   int64_t n = s->n;
-  double* feat = (double*)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
+  if (!s->cfeat) s->cfeat = dup(NULL, 6 * n);
+  double* feat = s->cfeat;
   closure_features(s, ncell, ucell, feat);
   if (!s->c_drag) s->c_drag = dup(NULL, n);
   if (!s->c_coh) s->c_coh = dup(NULL, n);
@@ -655,7 +657,6 @@ static void closure_apply(or_sim* s, const double* ncell, const double* ucell) {
     s->c_drag[i] = exp(y[0]);
     s->c_coh[i] = exp(y[1]);
   }
-  free(feat);
 }
 
 int or_set_closure_mlp(or_sim* s, const double* params, const double* norm) {
@@ -665,6 +666,10 @@ int or_set_closure_mlp(or_sim* s, const double* params, const double* norm) {
   s->mlp = dup(params, OR_MLP_NPARAMS);
   for (int c = 0; c < 12; ++c) s->mlp_norm[c] = norm[c];
   return 0;
+}
+
+void or_get_closure_features(const or_sim* s, double* feat) {
+  for (int64_t k = 0; k < 6 * s->n; ++k) feat[k] = s->cfeat ? s->cfeat[k] : 0.0;
 }
 
 void or_get_closure(const or_sim* s, double* c_drag, double* c_coh) {

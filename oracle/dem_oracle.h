@@ -102,6 +102,7 @@ int     or_set_closure_mlp(or_sim* s, const double* params, const double* norm);
 int     or_closure_features(or_sim* s, double* feat);   /* n x 6 at the current state */
 void    or_mlp_forward(const double* params, const double* xh, double* y);
 void    or_get_closure(const or_sim* s, double* c_drag, double* c_coh);   /* ones when unset */
+void    or_get_closure_features(const or_sim* s, double* feat);   /* latest evaluation, n x 6 */
 int     or_step(or_sim* s, int64_t nsteps);
 void    or_get_state(const or_sim* s, double* x, double* v, double* w, double* F, double* T,
                      uint8_t* alive, double* fscale, double* tscale);

@@ -7,6 +7,7 @@
 // device order.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <cmath>
 #include <string.h>
 
 #include <algorithm>
@@ -61,6 +62,11 @@ struct dem_ctx {
   WallSet ws[2];
   int live = 0;          // ns[live] / ws[live] is the current list
   int last_overflow_rows = 0;   // rows the last search could not keep in scratch
+  // learned closure: factor arrays and their permutation scratch (kept while off)
+  double* cl_buf[4] = {nullptr, nullptr, nullptr, nullptr};
+  double *cl_feat = nullptr, *cl_feat_tmp = nullptr, *cl_norm = nullptr;
+  short* cl_wb = nullptr;
+  float* cl_pf = nullptr;
   int hist_old = 0;      // history buffer of the previous list at the next rebuild
   int64_t step = 0;
   int64_t rebuilds = 0;
@@ -336,6 +342,7 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   swp(d.frc, d.t_r4[0]); swp(d.trq, d.t_r4[1]); swp(d.fdr, d.t_r4[2]);
   swp(d.sample, d.t_i[0]); swp(d.orig, d.t_i[1]);
   if (d.cdrag) { swp(d.cdrag, d.t_d[0]); swp(d.ccoh, d.t_d[1]); }
+  if (d.closure_on) swp(d.cfeat, d.t_feat);
   // 3. the live list becomes the previous one
   if (!first) c->live = 1 - c->live;
   bind_sets(c);
@@ -1019,6 +1026,79 @@ dem_status dem_read_profile(dem_ctx* c, double* total_ms, int64_t* launches) {
 dem_status dem_read_fault(dem_ctx* c, int32_t* bits) {
   if (!c || !bits) return DEM_E_INVAL;
   *bits = c->failed;
+  return DEM_OK;
+}
+
+dem_status dem_set_closure(dem_ctx* c, const dem_mlp* mlp, const double* norm) {
+  if (!c) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  DevState& d = c->d;
+  hipStream_t s = c->stream;
+  if (!mlp) {
+    if (d.cdrag) {
+      c->cl_buf[0] = d.cdrag; c->cl_buf[1] = d.ccoh; c->cl_buf[2] = d.t_d[0]; c->cl_buf[3] = d.t_d[1];
+    }
+    d.cdrag = d.ccoh = nullptr;
+    d.closure_on = 0;
+    return DEM_OK;
+  }
+  if (!norm) return DEM_E_INVAL;
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(norm[k]) || (k >= 6 && !(norm[k] > 0.0))) return DEM_E_INVAL;
+  const int64_t n = d.n;
+  if (!c->cl_buf[0] && !d.cdrag) {
+    bool ok = true;
+    for (int q = 0; q < 4; ++q) ok &= dalloc(c, &c->cl_buf[q], n) == hipSuccess;
+    ok &= dalloc(c, &c->cl_feat, 6 * n) == hipSuccess && dalloc(c, &c->cl_feat_tmp, 6 * n) == hipSuccess;
+    ok &= dalloc(c, &c->cl_norm, 12) == hipSuccess;
+    ok &= dalloc(c, &c->cl_wb, DEM_MLP_NPARAMS) == hipSuccess && dalloc(c, &c->cl_pf, DEM_MLP_NPARAMS) == hipSuccess;
+    if (!ok) return DEM_E_NOMEM;
+    d.cfeat = c->cl_feat;
+    d.t_feat = c->cl_feat_tmp;
+  }
+  if (!d.cdrag) {
+    d.cdrag = c->cl_buf[0]; d.ccoh = c->cl_buf[1]; d.t_d[0] = c->cl_buf[2]; d.t_d[1] = c->cl_buf[3];
+  }
+  // snapshot of the network and the normalisation; factors 1 until the next evaluation
+  if (hipStreamSynchronize(mlp_stream(mlp)) != hipSuccess) return DEM_E_DEVICE;
+  std::vector<double> ones(n > 0 ? n : 1, 1.0), zf(6 * (n > 0 ? n : 1), 0.0);
+  HIPCHK(hipMemcpyAsync(c->cl_wb, mlp_weights_bf16(mlp), sizeof(short) * DEM_MLP_NPARAMS, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->cl_pf, mlp_params_f32(mlp), sizeof(float) * DEM_MLP_NPARAMS, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->cl_norm, norm, sizeof(double) * 12, hipMemcpyHostToDevice, s));
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(d.cdrag, ones.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.ccoh, ones.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.cfeat, zf.data(), sizeof(double) * 6 * n, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  d.cl_wb = c->cl_wb;
+  d.cl_pf = c->cl_pf;
+  d.cl_norm = c->cl_norm;
+  d.closure_on = 1;
+  return DEM_OK;
+}
+
+dem_status dem_read_closure(dem_ctx* c, double* features, double* c_drag, double* c_coh) {
+  if (!c) return DEM_E_INVAL;
+  if (!c->d.closure_on) return DEM_E_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  DevState& d = c->d;
+  const int64_t n = d.n;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<int32_t> orig(n > 0 ? n : 1);
+  std::vector<double> f(6 * (n > 0 ? n : 1)), a(n > 0 ? n : 1), b(n > 0 ? n : 1);
+  if (n > 0) {
+    HIPCHK(hipMemcpy(orig.data(), d.orig, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(f.data(), d.cfeat, sizeof(double) * 6 * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(a.data(), d.cdrag, sizeof(double) * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(b.data(), d.ccoh, sizeof(double) * n, hipMemcpyDeviceToHost));
+  }
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t o = orig[k];
+    if (features) for (int q = 0; q < 6; ++q) features[6 * o + q] = f[6 * k + q];
+    if (c_drag) c_drag[o] = a[k];
+    if (c_coh) c_coh[o] = b[k];
+  }
   return DEM_OK;
 }
 

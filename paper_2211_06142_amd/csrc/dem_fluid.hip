@@ -151,23 +151,18 @@ __global__ void k_fluid_cells(DevState d) {
 
 // Di Felice drag (eq 8-11) with the coarse-grained rule, buoyancy and the
 // dynamic pressure gradient; trilinear interpolation of n, u, grad p
-template <typename R>
-__global__ void k_fluid_drag(DevState d, int buf) {
-  if (*d.abort) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  const SampleConst& c = d.sc[d.sample[i]];
-  if (!d.alive[buf][i] || !c.fluid_on) {
-    ((R4<R>*)d.fdr)[i] = mk4<R>(0, 0, 0, 0);
-    d.fpart[i] = make_double4(0, 0, 0, 0);
-    return;
-  }
+// porosity, fluid velocity and dynamic pressure gradient at particle i, with
+// the weights of its deposition (trilinear over the 8 surrounding cell centres,
+// or its own cell for centroid deposition)
+__device__ inline void particle_fluid(const DevState& d, const SampleConst& c, int64_t i, double& np, double u[3],
+                                      double gp[3]) {
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
   int64_t l = d.dkey[i] - c.dual_base;
   int b[3] = {(int)(l % c.dn[0]), (int)((l / c.dn[0]) % c.dn[1]), (int)(l / ((int64_t)c.dn[0] * c.dn[1]))};
   double4 fr = d.dfr[i];
   double f[3] = {fr.x, fr.y, fr.z};
-  double np = 0.0, u[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+  np = 0.0;
+  for (int k = 0; k < 3; ++k) { u[k] = 0.0; gp[k] = 0.0; }
   int up = cen ? 1 : 2;
   for (int dz = 0; dz < up; ++dz)
     for (int dy = 0; dy < up; ++dy)
@@ -185,6 +180,64 @@ __global__ void k_fluid_drag(DevState d, int buf) {
           gp[k] += w * d.gp_in[3 * C + k];
         }
       }
+}
+
+// Learned-closure features of particle i (an extension): porosity at the
+// particle, slip speed |u - v|, particle Reynolds number of the drag law
+// (eq 11, fine diameter d/k), k, and the mean of delta/R* over the pairs that
+// took part in the last force evaluation, with their count.  Dead: zeros.
+template <typename R>
+__global__ void k_closure_features(DevState d, int buf) {
+  if (*d.abort) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  double* f = d.cfeat + 6 * i;
+  const SampleConst& c = d.sc[d.sample[i]];
+  if (!d.alive[buf][i] || !c.fluid_on) {
+    for (int k = 0; k < 6; ++k) f[k] = 0.0;
+    return;
+  }
+  double np, u[3], gp[3];
+  particle_fluid(d, c, i, np, u, gp);
+  const double4 v = d.vel[buf][i];
+  const double4 pi = d.xr[buf][i];
+  double s[3] = {u[0] - v.x, u[1] - v.y, u[2] - v.z};
+  double sm = sqrt((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
+  double sum = 0.0, cnt = 0.0;
+  const uint8_t* al = d.alive[buf];
+  const uint8_t* fl = d.pfl[buf];
+  for (int32_t e = d.nrow[i]; e < d.nrow[i + 1]; ++e) {
+    const int32_t j = d.nbr[e];
+    if (!al[j] || !(fl[d.nslot[e]] & 3)) continue;
+    const double4 pj = d.xr[buf][j];
+    double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    double delta = (pi.w + pj.w) - sqrt((dx * dx + dy * dy) + dz * dz);
+    double Rs = pi.w * pj.w / (pi.w + pj.w);
+    sum += delta / Rs;
+    cnt += 1.0;
+  }
+  f[0] = np;
+  f[1] = sm;
+  f[2] = c.rho_f * (2.0 * pi.w / c.kcg) * sm / c.mu_f;
+  f[3] = c.kcg;
+  f[4] = cnt > 0.0 ? sum / cnt : 0.0;
+  f[5] = cnt;
+}
+
+template <typename R>
+__global__ void k_fluid_drag(DevState d, int buf) {
+  if (*d.abort) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const SampleConst& c = d.sc[d.sample[i]];
+  if (!d.alive[buf][i] || !c.fluid_on) {
+    ((R4<R>*)d.fdr)[i] = mk4<R>(0, 0, 0, 0);
+    d.fpart[i] = make_double4(0, 0, 0, 0);
+    return;
+  }
+  double np, u[3], gp[3];
+  particle_fluid(d, c, i, np, u, gp);
+  const double4 fr = d.dfr[i];
   const double4 v = d.vel[buf][i];
   const double r = d.xr[buf][i].w;
   double s[3] = {u[0] - v.x, u[1] - v.y, u[2] - v.z};
@@ -214,6 +267,10 @@ template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
                      d.dmem, d.scan_tmp, d.dual_sink, d.abort, s);
   hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d);
+  if (d.closure_on) {
+    hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, buf);
+    launch_closure_infer(d, s);
+  }
   hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, buf);
   hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d);

@@ -87,6 +87,12 @@ struct DevState {
   double4* xref;
   int32_t *sample, *orig;
   double *cdrag, *ccoh;            // closure factors (NULL when off)
+  int closure_on;                  // learned closure evaluated at every coupling step
+  double* cfeat;                   // n x 6 closure features of the latest evaluation
+  double* t_feat;                  // permutation scratch of cfeat
+  const void* cl_wb;               // closure network: BF16 weights, FP32 parameters,
+  const float* cl_pf;              //   feature mean[6] and standard deviation[6]
+  const double* cl_norm;
   // permutation scratch
   void *t_r4[3];
   double4* t_d4;
@@ -168,6 +174,10 @@ void launch_set_xref(DevState& d, hipStream_t s);
 template <typename R> void launch_prologue(DevState& d, StepArgs a, hipStream_t s);
 template <typename R> void launch_step(DevState& d, StepArgs a, hipStream_t s);
 template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s);
+void launch_closure_infer(DevState& d, hipStream_t s);
+const short* mlp_weights_bf16(const dem_mlp* n);
+const float* mlp_params_f32(const dem_mlp* n);
+hipStream_t mlp_stream(const dem_mlp* n);
 
 // read-back
 template <typename R> void launch_unpermute(DevState& d, double* x, double* v, double* w, double* F,

@@ -1,0 +1,561 @@
+// dem_mlp.hip -- the learned closure network on the matrix cores (an extension
+// of the method; not in arXiv:2211.06142).
+//
+// Network 6 -> 64 -> 64 -> 64 -> 2, GELU (erf form) on the hidden layers,
+// BF16 operands with FP32 accumulation on v_mfma_f32_16x16x16_bf16.  Flat
+// parameter layout (FP32 master, BF16 copy at the same offsets):
+//   W1 6x64 | b1 | W2 64x64 | b2 | W3 64x64 | b3 | W4 64x2 | b4,  W[k][m] row-major
+//
+// Transposed evaluation.  One wavefront takes 16 samples and computes
+// Z^T = W^T H^T: the 16x16 output fragment of one MFMA holds features
+// 4(lane/16)+i of sample lane%16, which is exactly the layout of the B operand
+// of the next layer, so activations never leave the registers between layers
+// (no LDS transposes).  The backward pass runs the same way with W in place of
+// W^T.  Weight gradients contract over the samples: a split-K MFMA product per
+// chunk of samples, then a fixed-order sum over chunks, so every result is
+// bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "dem_device.h"
+
+namespace dem {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kW1 = 0, kB1 = 384, kW2 = 448, kB2 = 4544, kW3 = 4608, kB3 = 8704, kW4 = 8768, kB4 = 8896;
+constexpr int kNParams = 8898;
+constexpr int kChunk = 1024;   // samples per split-K chunk of the weight gradients
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ inline short f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ inline float bf2f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+__device__ inline float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_df(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+__device__ inline f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// A fragment of W^T (rows = outputs m, columns = inputs k) for output tile mt
+// and input tile kt of a K x M layer: lane holds W[16kt + 4q + i][16mt + r]
+__device__ inline bf16x4 wt_frag(const short* wb, int off, int K, int M, int mt, int kt, int q, int r) {
+  bf16x4 a;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int k = 16 * kt + 4 * q + i, m = 16 * mt + r;
+    a[i] = (k < K && m < M) ? wb[off + k * M + m] : (short)0;
+  }
+  return a;
+}
+// A fragment of W (rows = inputs k, columns = outputs m) for input tile kt and
+// output tile mt: lane holds W[16kt + r][16mt + 4q + i]
+__device__ inline bf16x4 w_frag(const short* wb, int off, int K, int M, int kt, int mt, int q, int r) {
+  bf16x4 a;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int k = 16 * kt + r, m = 16 * mt + 4 * q + i;
+    a[i] = (k < K && m < M) ? wb[off + k * M + m] : (short)0;
+  }
+  return a;
+}
+__device__ inline f32x4 bias_frag(const float* pf, int off, int M, int mt, int q) {
+  f32x4 b;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int m = 16 * mt + 4 * q + i;
+    b[i] = m < M ? pf[off + m] : 0.0f;
+  }
+  return b;
+}
+
+// training record of a batch (sample-major rows)
+struct MlpTrainBuf {
+  short* h0;     // B x 16 (input, padded)
+  short* h[3];   // B x 64 activations of the hidden layers
+  float* z[3];   // B x 64 pre-activations
+  short* g[3];   // B x 64 loss gradients w.r.t. the hidden pre-activations
+  float* g4;     // B x 2 loss gradient w.r.t. the output
+  float* err;    // B: squared error of the sample
+};
+
+// One tile of 16 samples (rows s0 .. s0+15; rows >= B are padding).  Returns
+// the output fragment: lanes 0-15, items 0-1 hold y0, y1 of sample lane.
+template <bool kTrain>
+__device__ f32x4 forward_tile(const short* wb, const float* pf, bf16x4 a0, int q, int r, int64_t s0, int64_t B,
+                              const MlpTrainBuf& tb) {
+  const int64_t s = s0 + r;
+  const bool valid = s < B;
+  if (kTrain && valid && q < 4) {
+    short* dst = tb.h0 + s * 16 + 4 * q;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dst[i] = a0[i];
+  }
+  bf16x4 h[4];
+  // layer 1: 6 -> 64
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = bias_frag(pf, kB1, 64, mt, q);
+    acc = mfma16(wt_frag(wb, kW1, 6, 64, mt, 0, q, r), a0, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[mt][i] = f2bf(gelu_f(acc[i]));
+    if (kTrain && valid) {
+      *(f32x4*)(tb.z[0] + s * 64 + 16 * mt + 4 * q) = acc;
+      *(bf16x4*)(tb.h[0] + s * 64 + 16 * mt + 4 * q) = h[mt];
+    }
+  }
+  // layers 2 and 3: 64 -> 64
+#pragma unroll
+  for (int l = 1; l < 3; ++l) {
+    const int offW = l == 1 ? kW2 : kW3, offB = l == 1 ? kB2 : kB3;
+    bf16x4 hn[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = bias_frag(pf, offB, 64, mt, q);
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) acc = mfma16(wt_frag(wb, offW, 64, 64, mt, kt, q, r), h[kt], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hn[mt][i] = f2bf(gelu_f(acc[i]));
+      if (kTrain && valid) {
+        *(f32x4*)(tb.z[l] + s * 64 + 16 * mt + 4 * q) = acc;
+        *(bf16x4*)(tb.h[l] + s * 64 + 16 * mt + 4 * q) = hn[mt];
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) h[mt] = hn[mt];
+  }
+  // layer 4: 64 -> 2 (one padded output tile)
+  f32x4 y = bias_frag(pf, kB4, 2, 0, q);
+#pragma unroll
+  for (int kt = 0; kt < 4; ++kt) y = mfma16(wt_frag(wb, kW4, 64, 2, 0, kt, q, r), h[kt], y);
+  return y;
+}
+
+// input fragment of layer 1 from FP32 normalised features (row stride ldx)
+__device__ inline bf16x4 input_frag(const float* x, int64_t ldx, int64_t s, int64_t B, int q) {
+  bf16x4 a;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int k = 4 * q + i;
+    a[i] = (s < B && k < 6) ? f2bf(x[s * ldx + k]) : (short)0;
+  }
+  return a;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const short* wb, const float* pf, const float* x, int64_t B,
+                                                     float* y) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+  const int64_t nt = (B + 15) / 16;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  MlpTrainBuf none{};
+  for (int64_t t = w0; t < nt; t += nw) {
+    const int64_t s = t * 16 + r;
+    f32x4 out = forward_tile<false>(wb, pf, input_frag(x, 6, s, B, q), q, r, t * 16, B, none);
+    if (q == 0 && s < B) {
+      y[2 * s] = out[0];
+      y[2 * s + 1] = out[1];
+    }
+  }
+}
+
+// forward of a training batch: records activations, the output gradient of
+// L = mean (y - t)^2 and the squared error per sample
+__global__ __launch_bounds__(256) void k_mlp_forward_train(const short* wb, const float* pf, const float* x,
+                                                           const float* tgt, int64_t B, MlpTrainBuf tb) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+  const int64_t nt = (B + 15) / 16;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const float scale = 2.0f / (2.0f * (float)B);
+  for (int64_t t = w0; t < nt; t += nw) {
+    const int64_t s = t * 16 + r;
+    f32x4 out = forward_tile<true>(wb, pf, input_frag(x, 6, s, B, q), q, r, t * 16, B, tb);
+    if (q == 0 && s < B) {
+      float e0 = out[0] - tgt[2 * s], e1 = out[1] - tgt[2 * s + 1];
+      tb.g4[2 * s] = scale * e0;
+      tb.g4[2 * s + 1] = scale * e1;
+      tb.err[s] = e0 * e0 + e1 * e1;
+    }
+  }
+}
+
+// backward through the hidden layers: G_l = (W_l G_{l+1}) * gelu'(Z_l)
+__global__ __launch_bounds__(256) void k_mlp_backward(const short* wb, int64_t B, MlpTrainBuf tb) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+  const int64_t nt = (B + 15) / 16;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t t = w0; t < nt; t += nw) {
+    const int64_t s = t * 16 + r;
+    const bool valid = s < B;
+    bf16x4 g4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int m = 4 * q + i;
+      g4[i] = (valid && m < 2) ? f2bf(tb.g4[2 * s + m]) : (short)0;
+    }
+    // dH3 = W4 G4 (input tile kt = 0: the 2 outputs, padded)
+    bf16x4 g[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma16(w_frag(wb, kW4, 64, 2, mt, 0, q, r), g4, acc);
+      f32x4 z = valid ? *(const f32x4*)(tb.z[2] + s * 64 + 16 * mt + 4 * q) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) g[mt][i] = f2bf(acc[i] * gelu_df(z[i]));
+      if (valid) *(bf16x4*)(tb.g[2] + s * 64 + 16 * mt + 4 * q) = g[mt];
+    }
+    // dH2 = W3 G3, dH1 = W2 G2
+#pragma unroll
+    for (int l = 1; l >= 0; --l) {
+      const int offW = l == 1 ? kW3 : kW2;
+      bf16x4 gn[4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) acc = mfma16(w_frag(wb, offW, 64, 64, mt, kt, q, r), g[kt], acc);
+        f32x4 z = valid ? *(const f32x4*)(tb.z[l] + s * 64 + 16 * mt + 4 * q) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) gn[mt][i] = f2bf(acc[i] * gelu_df(z[i]));
+        if (valid) *(bf16x4*)(tb.g[l] + s * 64 + 16 * mt + 4 * q) = gn[mt];
+      }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) g[mt] = gn[mt];
+    }
+  }
+}
+
+// Weight and bias gradients of one chunk of samples: dW[k][m] = sum_s H[s][k] G[s][m]
+// as MFMA products with the samples as the contraction; a bias gradient uses
+// an all-ones A operand.  Jobs: (layer, input tile or bias, output tile).
+struct GradJob {
+  int layer, kt, mt;   // kt = -1: bias
+};
+__device__ inline GradJob grad_job(int j) {
+  // layer 0: 1 x 4 weight tiles + 4 bias; layers 1, 2: 16 + 4; layer 3: 4 + 1
+  if (j < 8) return j < 4 ? GradJob{0, 0, j} : GradJob{0, -1, j - 4};
+  j -= 8;
+  if (j < 40) {
+    int l = 1 + j / 20, u = j % 20;
+    return u < 16 ? GradJob{l, u / 4, u % 4} : GradJob{l, -1, u - 16};
+  }
+  j -= 40;
+  return j < 4 ? GradJob{3, j, 0} : GradJob{3, -1, 0};
+}
+constexpr int kGradJobs = 53;
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad(int64_t B, MlpTrainBuf tb, float* part) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15, wv = threadIdx.x >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+  const int64_t c1 = c0 + kChunk < B ? c0 + kChunk : B;
+  float* out = part + (int64_t)blockIdx.x * kNParams;
+  for (int j = wv; j < kGradJobs; j += 4) {
+    const GradJob jb = grad_job(j);
+    const int K = jb.layer == 0 ? 6 : 64, M = jb.layer == 3 ? 2 : 64;
+    const int ldh = jb.layer == 0 ? 16 : 64;
+    const short* H = jb.layer == 0 ? tb.h0 : tb.h[jb.layer - 1];
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t s0 = c0; s0 < c1; s0 += 16) {
+      bf16x4 a, b;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t s = s0 + 4 * q + i;
+        const bool ok = s < c1;
+        const int k = 16 * (jb.kt < 0 ? 0 : jb.kt) + r;
+        a[i] = jb.kt < 0 ? (short)0x3F80 : ((ok && k < K) ? H[s * ldh + k] : (short)0);   // 0x3F80 = 1.0
+        const int m = 16 * jb.mt + r;
+        if (jb.layer == 3) b[i] = (ok && m < 2) ? f2bf(tb.g4[2 * s + m]) : (short)0;
+        else b[i] = ok ? tb.g[jb.layer][s * 64 + m] : (short)0;
+      }
+      acc = mfma16(a, b, acc);
+    }
+    // D[row][col]: row 4q + i of the tile, column r
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 4 * q + i, m = 16 * jb.mt + r;
+      if (m >= M) continue;
+      const int offW = jb.layer == 0 ? kW1 : jb.layer == 1 ? kW2 : jb.layer == 2 ? kW3 : kW4;
+      const int offB = jb.layer == 0 ? kB1 : jb.layer == 1 ? kB2 : jb.layer == 2 ? kB3 : kB4;
+      if (jb.kt < 0) {
+        if (row == 0) out[offB + m] = acc[i];
+      } else {
+        const int k = 16 * jb.kt + row;
+        if (k < K) out[offW + k * M + m] = acc[i];
+      }
+    }
+  }
+}
+
+// fixed-order sum of the squared errors (one block)
+__global__ __launch_bounds__(256) void k_mlp_loss(const float* err, int64_t B, float* loss) {
+  __shared__ float sh[256];
+  float a = 0.f;
+  for (int64_t s = threadIdx.x; s < B; s += 256) a += err[s];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = sh[0] / (2.0f * (float)B);
+}
+
+// gradient = fixed-order sum over chunks; optional Adam step on the FP32
+// master parameters, then the BF16 copy
+__global__ void k_mlp_reduce_adam(const float* part, int nchunk, float* grad, float* p, float* m, float* v,
+                                  short* wb, int do_adam, float lr, float bc1, float bc2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kNParams) return;
+  float g = 0.f;
+  for (int c = 0; c < nchunk; ++c) g += part[(int64_t)c * kNParams + k];
+  grad[k] = g;
+  if (!do_adam) return;
+  const float mk = 0.9f * m[k] + 0.1f * g;
+  const float vk = 0.999f * v[k] + 0.001f * g * g;
+  m[k] = mk;
+  v[k] = vk;
+  const float pk = p[k] - lr * (mk / bc1) / (sqrtf(vk / bc2) + 1e-8f);
+  p[k] = pk;
+  wb[k] = f2bf(pk);
+}
+
+__global__ void k_mlp_to_bf16(const float* p, short* wb) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < kNParams) wb[k] = f2bf(p[k]);
+}
+
+// ---------------------------------------------------------------------------
+// closure inference inside the DEM: features (FP64, n x 6) -> normalised ->
+// network -> factors c = exp(clip(y, -ln 2, ln 2)) into cdrag, ccoh
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_closure_infer(DevState d) {
+  if (*d.abort) return;
+  const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+  const int64_t nt = (d.n + 15) / 16;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const short* wb = (const short*)d.cl_wb;
+  const float* pf = d.cl_pf;
+  MlpTrainBuf none{};
+  const float L2 = 0.69314718055994531f;
+  for (int64_t t = w0; t < nt; t += nw) {
+    const int64_t s = t * 16 + r;
+    bf16x4 a;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int k = 4 * q + i;
+      a[i] = (s < d.n && k < 6) ? f2bf((float)((d.cfeat[6 * s + k] - d.cl_norm[k]) / d.cl_norm[6 + k]))
+                                : (short)0;
+    }
+    f32x4 y = forward_tile<false>(wb, pf, a, q, r, t * 16, d.n, none);
+    if (q == 0 && s < d.n) {
+      float y0 = fminf(fmaxf(y[0], -L2), L2), y1 = fminf(fmaxf(y[1], -L2), L2);
+      d.cdrag[s] = (double)expf(y0);
+      d.ccoh[s] = (double)expf(y1);
+    }
+  }
+}
+
+void launch_closure_infer(DevState& d, hipStream_t s) {
+  int64_t tiles = (d.n + 15) / 16;
+  int64_t blocks = (tiles + 3) / 4;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks > 0) hipLaunchKernelGGL(k_closure_infer, dim3((unsigned)blocks), dim3(256), 0, s, d);
+}
+
+}  // namespace dem
+
+// ---------------------------------------------------------------------------
+// C-ABI: the network object
+// ---------------------------------------------------------------------------
+using namespace dem;
+
+struct dem_mlp {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+  short* wb = nullptr;
+  int64_t step = 0;
+  int64_t cap = 0;            // batch capacity of the training buffers
+  MlpTrainBuf tb{};
+  float* part = nullptr;
+  int64_t part_chunks = 0;
+  std::vector<void*> batch_allocs;
+};
+
+namespace {
+void free_batch(dem_mlp* n) {
+  for (void* q : n->batch_allocs) (void)hipFree(q);
+  n->batch_allocs.clear();
+  n->tb = MlpTrainBuf{};
+  n->part = nullptr;
+  n->cap = 0;
+}
+template <typename T> hipError_t balloc(dem_mlp* n, T** q, int64_t count) {
+  hipError_t e = hipMalloc((void**)q, sizeof(T) * (size_t)(count > 0 ? count : 1));
+  if (e == hipSuccess) n->batch_allocs.push_back((void*)*q);
+  return e;
+}
+dem_status ensure_batch(dem_mlp* n, int64_t B) {
+  if (B <= n->cap) return DEM_OK;
+  if (hipStreamSynchronize(n->stream) != hipSuccess) return DEM_E_DEVICE;
+  free_batch(n);
+  int64_t cap = std::max<int64_t>(B, 1024);
+  int64_t nch = (cap + kChunk - 1) / kChunk;
+  bool ok = balloc(n, &n->tb.h0, cap * 16) == hipSuccess;
+  for (int l = 0; l < 3; ++l) {
+    ok &= balloc(n, &n->tb.h[l], cap * 64) == hipSuccess;
+    ok &= balloc(n, &n->tb.z[l], cap * 64) == hipSuccess;
+    ok &= balloc(n, &n->tb.g[l], cap * 64) == hipSuccess;
+  }
+  ok &= balloc(n, &n->tb.g4, cap * 2) == hipSuccess;
+  ok &= balloc(n, &n->tb.err, cap) == hipSuccess;
+  ok &= balloc(n, &n->part, nch * kNParams) == hipSuccess;
+  if (!ok) {
+    free_batch(n);
+    return DEM_E_NOMEM;
+  }
+  n->cap = cap;
+  n->part_chunks = nch;
+  return DEM_OK;
+}
+int grid_for(int64_t B) {
+  int64_t tiles = (B + 15) / 16;
+  int64_t blocks = (tiles + 3) / 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 2048));
+}
+// forward + backward + chunk gradients + fixed-order reduction (+ Adam)
+dem_status train_pass(dem_mlp* n, const float* x, const float* t, int64_t B, int adam, float lr, float* loss_host) {
+  if (!n || !x || !t || B <= 0) return DEM_E_INVAL;
+  if (hipSetDevice(n->device) != hipSuccess) return DEM_E_DEVICE;
+  dem_status st = ensure_batch(n, B);
+  if (st != DEM_OK) return st;
+  hipStream_t s = n->stream;
+  int g = grid_for(B);
+  hipLaunchKernelGGL(k_mlp_forward_train, dim3(g), dim3(256), 0, s, n->wb, n->p, x, t, B, n->tb);
+  hipLaunchKernelGGL(k_mlp_backward, dim3(g), dim3(256), 0, s, n->wb, B, n->tb);
+  int nch = (int)((B + kChunk - 1) / kChunk);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nch), dim3(256), 0, s, B, n->tb, n->part);
+  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, n->tb.err, B, n->loss);
+  float bc1 = 1.f, bc2 = 1.f;
+  if (adam) {
+    n->step += 1;
+    bc1 = (float)(1.0 - std::pow(0.9, (double)n->step));
+    bc2 = (float)(1.0 - std::pow(0.999, (double)n->step));
+  }
+  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, n->part, nch, n->grad, n->p,
+                     n->m, n->v, n->wb, adam, lr, bc1, bc2);
+  if (hipGetLastError() != hipSuccess) return DEM_E_DEVICE;
+  if (loss_host) {
+    if (hipMemcpyAsync(loss_host, n->loss, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess) return DEM_E_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return DEM_E_DEVICE;
+  }
+  return DEM_OK;
+}
+}  // namespace
+
+namespace dem {
+const short* mlp_weights_bf16(const dem_mlp* n) { return n ? n->wb : nullptr; }
+const float* mlp_params_f32(const dem_mlp* n) { return n ? n->p : nullptr; }
+hipStream_t mlp_stream(const dem_mlp* n) { return n ? n->stream : nullptr; }
+}  // namespace dem
+
+extern "C" {
+
+dem_status dem_mlp_create(dem_mlp** out, int32_t device, void* hip_stream) {
+  if (!out) return DEM_E_INVAL;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return DEM_E_DEVICE;
+  dem_mlp* n = new dem_mlp();
+  n->device = device;
+  n->stream = (hipStream_t)hip_stream;
+  bool ok = hipMalloc((void**)&n->p, sizeof(float) * kNParams) == hipSuccess;
+  ok &= hipMalloc((void**)&n->m, sizeof(float) * kNParams) == hipSuccess;
+  ok &= hipMalloc((void**)&n->v, sizeof(float) * kNParams) == hipSuccess;
+  ok &= hipMalloc((void**)&n->grad, sizeof(float) * kNParams) == hipSuccess;
+  ok &= hipMalloc((void**)&n->loss, sizeof(float)) == hipSuccess;
+  ok &= hipMalloc((void**)&n->wb, sizeof(short) * kNParams) == hipSuccess;
+  if (!ok) {
+    dem_mlp_destroy(n);
+    return DEM_E_NOMEM;
+  }
+  ok &= hipMemsetAsync(n->p, 0, sizeof(float) * kNParams, n->stream) == hipSuccess;
+  ok &= hipMemsetAsync(n->m, 0, sizeof(float) * kNParams, n->stream) == hipSuccess;
+  ok &= hipMemsetAsync(n->v, 0, sizeof(float) * kNParams, n->stream) == hipSuccess;
+  ok &= hipMemsetAsync(n->wb, 0, sizeof(short) * kNParams, n->stream) == hipSuccess;
+  if (!ok) {
+    dem_mlp_destroy(n);
+    return DEM_E_DEVICE;
+  }
+  *out = n;
+  return DEM_OK;
+}
+
+void dem_mlp_destroy(dem_mlp* n) {
+  if (!n) return;
+  (void)hipSetDevice(n->device);
+  (void)hipStreamSynchronize(n->stream);
+  free_batch(n);
+  (void)hipFree(n->p); (void)hipFree(n->m); (void)hipFree(n->v);
+  (void)hipFree(n->grad); (void)hipFree(n->loss); (void)hipFree(n->wb);
+  delete n;
+}
+
+dem_status dem_mlp_set_params(dem_mlp* n, const float* params) {
+  if (!n || !params) return DEM_E_INVAL;
+  if (hipSetDevice(n->device) != hipSuccess) return DEM_E_DEVICE;
+  hipStream_t s = n->stream;
+  if (hipMemcpyAsync(n->p, params, sizeof(float) * kNParams, hipMemcpyDefault, s) != hipSuccess) return DEM_E_DEVICE;
+  if (hipMemsetAsync(n->m, 0, sizeof(float) * kNParams, s) != hipSuccess) return DEM_E_DEVICE;
+  if (hipMemsetAsync(n->v, 0, sizeof(float) * kNParams, s) != hipSuccess) return DEM_E_DEVICE;
+  n->step = 0;
+  hipLaunchKernelGGL(k_mlp_to_bf16, dim3((kNParams + 255) / 256), dim3(256), 0, s, n->p, n->wb);
+  if (hipStreamSynchronize(s) != hipSuccess) return DEM_E_DEVICE;
+  return DEM_OK;
+}
+
+dem_status dem_mlp_get_params(dem_mlp* n, float* params) {
+  if (!n || !params) return DEM_E_INVAL;
+  if (hipSetDevice(n->device) != hipSuccess) return DEM_E_DEVICE;
+  if (hipMemcpyAsync(params, n->p, sizeof(float) * kNParams, hipMemcpyDefault, n->stream) != hipSuccess)
+    return DEM_E_DEVICE;
+  if (hipStreamSynchronize(n->stream) != hipSuccess) return DEM_E_DEVICE;
+  return DEM_OK;
+}
+
+dem_status dem_mlp_forward(dem_mlp* n, const float* x, float* y, int64_t batch) {
+  if (!n || batch < 0 || (batch > 0 && (!x || !y))) return DEM_E_INVAL;
+  if (batch == 0) return DEM_OK;
+  if (hipSetDevice(n->device) != hipSuccess) return DEM_E_DEVICE;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid_for(batch)), dim3(256), 0, n->stream, n->wb, n->p, x, batch, y);
+  return hipGetLastError() == hipSuccess ? DEM_OK : DEM_E_DEVICE;
+}
+
+dem_status dem_mlp_grad(dem_mlp* n, const float* x, const float* t, int64_t batch, float* grad, float* loss) {
+  dem_status st = train_pass(n, x, t, batch, 0, 0.f, loss);
+  if (st != DEM_OK) return st;
+  if (grad) {
+    if (hipMemcpyAsync(grad, n->grad, sizeof(float) * kNParams, hipMemcpyDefault, n->stream) != hipSuccess)
+      return DEM_E_DEVICE;
+    if (hipStreamSynchronize(n->stream) != hipSuccess) return DEM_E_DEVICE;
+  }
+  return DEM_OK;
+}
+
+dem_status dem_mlp_train_step(dem_mlp* n, const float* x, const float* t, int64_t batch, float lr, float* loss) {
+  if (!(lr > 0.f)) return DEM_E_INVAL;
+  return train_pass(n, x, t, batch, 1, lr, loss);
+}
+
+}  // extern "C"

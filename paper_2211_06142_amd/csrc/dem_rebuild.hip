@@ -48,6 +48,8 @@ __global__ void k_permute(DevState d) {
     d.t_d[0][k] = d.cdrag[o];
     d.t_d[1][k] = d.ccoh[o];
   }
+  if (d.closure_on)
+    for (int c = 0; c < 6; ++c) d.t_feat[6 * k + c] = d.cfeat[6 * o + c];
   d.inv_order[o] = (int32_t)k;
 }
 

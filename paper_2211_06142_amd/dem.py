@@ -28,7 +28,10 @@ PROF_NAMES = ["prologue", "rebuild", "fluid", "step"]
 
 EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "dem_read_pairs",
                   "dem_read_aggregates", "dem_info", "dem_request_rebuild", "dem_destroy", "dem_status_str",
-                  "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile", "dem_read_fault"])
+                  "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile",
+                  "dem_read_fault", "dem_mlp_create", "dem_mlp_destroy", "dem_mlp_set_params", "dem_mlp_get_params",
+                  "dem_mlp_forward", "dem_mlp_grad", "dem_mlp_train_step", "dem_set_closure", "dem_read_closure"])
+MLP_NPARAMS = 8898
 
 
 class dem_wall(ctypes.Structure):
@@ -122,6 +125,24 @@ def lib():
         L.dem_cg_diameters.argtypes = [i32, d, vp, i64, vp, i64]
         L.dem_rayleigh_dt.restype = d
         L.dem_rayleigh_dt.argtypes = [d, d, d, d]
+        L.dem_mlp_create.restype = i32
+        L.dem_mlp_create.argtypes = [ctypes.POINTER(vp), i32, vp]
+        L.dem_mlp_destroy.restype = None
+        L.dem_mlp_destroy.argtypes = [vp]
+        L.dem_mlp_set_params.restype = i32
+        L.dem_mlp_set_params.argtypes = [vp, vp]
+        L.dem_mlp_get_params.restype = i32
+        L.dem_mlp_get_params.argtypes = [vp, vp]
+        L.dem_mlp_forward.restype = i32
+        L.dem_mlp_forward.argtypes = [vp, vp, vp, i64]
+        L.dem_mlp_grad.restype = i32
+        L.dem_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.dem_mlp_train_step.restype = i32
+        L.dem_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp]
+        L.dem_set_closure.restype = i32
+        L.dem_set_closure.argtypes = [vp, vp, vp]
+        L.dem_read_closure.restype = i32
+        L.dem_read_closure.argtypes = [vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -242,6 +263,109 @@ def dem_rayleigh_dt(radius, rho, E, nu):
 # ---------------------------------------------------------------------------
 # parameter marshalling from a workload description
 # ---------------------------------------------------------------------------
+def dem_mlp_create(device, hip_stream):
+    h = ctypes.c_void_p()
+    rc = lib().dem_mlp_create(ctypes.byref(h), device, hip_stream)
+    return rc, h
+
+
+def dem_mlp_destroy(mlp):
+    lib().dem_mlp_destroy(mlp)
+
+
+def dem_mlp_set_params(mlp, params_ptr):
+    return lib().dem_mlp_set_params(mlp, params_ptr)
+
+
+def dem_mlp_get_params(mlp, params_ptr):
+    return lib().dem_mlp_get_params(mlp, params_ptr)
+
+
+def dem_mlp_forward(mlp, x_ptr, y_ptr, batch):
+    return lib().dem_mlp_forward(mlp, x_ptr, y_ptr, batch)
+
+
+def dem_mlp_grad(mlp, x_ptr, t_ptr, batch, grad_ptr):
+    loss = ctypes.c_float()
+    rc = lib().dem_mlp_grad(mlp, x_ptr, t_ptr, batch, grad_ptr, ctypes.byref(loss))
+    return rc, loss.value
+
+
+def dem_mlp_train_step(mlp, x_ptr, t_ptr, batch, lr):
+    loss = ctypes.c_float()
+    rc = lib().dem_mlp_train_step(mlp, x_ptr, t_ptr, batch, lr, ctypes.byref(loss))
+    return rc, loss.value
+
+
+def dem_set_closure(ctx, mlp, norm_ptr):
+    return lib().dem_set_closure(ctx, mlp, norm_ptr)
+
+
+def dem_read_closure(ctx, feat_ptr, cd_ptr, cc_ptr):
+    return lib().dem_read_closure(ctx, feat_ptr, cd_ptr, cc_ptr)
+
+
+class Mlp:
+    """Owns one dem_mlp (the learned closure network).  Inputs and targets are
+    torch CUDA (HIP) tensors; every product runs in libdem.so."""
+
+    def __init__(self, params=None, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        rc, h = dem_mlp_create(device, self.stream.cuda_stream)
+        _check(rc, "dem_mlp_create")
+        self.h = h
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if getattr(self, "h", None):
+            dem_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(MLP_NPARAMS))
+        _check(dem_mlp_set_params(self.h, p.ctypes.data), "dem_mlp_set_params")
+
+    def params(self):
+        p = np.zeros(MLP_NPARAMS, np.float32)
+        _check(dem_mlp_get_params(self.h, p.ctypes.data), "dem_mlp_get_params")
+        return p
+
+    def _dev32(self, a, cols):
+        t = self.torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1, cols)),
+                                 device=self.dev)
+        return t
+
+    def forward(self, x):
+        xt = self._dev32(x, 6)
+        y = self.torch.zeros((xt.shape[0], 2), dtype=self.torch.float32, device=self.dev)
+        _check(dem_mlp_forward(self.h, xt.data_ptr(), y.data_ptr(), xt.shape[0]), "dem_mlp_forward")
+        self.torch.cuda.synchronize(self.dev)
+        return y.cpu().numpy()
+
+    def grad(self, x, t):
+        xt, tt = self._dev32(x, 6), self._dev32(t, 2)
+        g = np.zeros(MLP_NPARAMS, np.float32)
+        rc, loss = dem_mlp_grad(self.h, xt.data_ptr(), tt.data_ptr(), xt.shape[0], g.ctypes.data)
+        _check(rc, "dem_mlp_grad")
+        return loss, g
+
+    def train_step(self, x, t, lr):
+        xt, tt = self._dev32(x, 6), self._dev32(t, 2)
+        rc, loss = dem_mlp_train_step(self.h, xt.data_ptr(), tt.data_ptr(), xt.shape[0], lr)
+        _check(rc, "dem_mlp_train_step")
+        return loss
+
+
 def make_params(material, dt, k=1.0, scheme="ssw", g=(0.0, 0.0, -9.81), walls=(), grid=None, fluid=None,
                 outlet=None, precision="fp64", normal_model=DEM_NORMAL_JKR_MOD, k_lin=0.0, bond_at_init=True,
                 skin=0.0, pair_capacity=0, dt_rayleigh_max_frac=0.0):
@@ -431,3 +555,18 @@ class Simulation:
 
     def request_rebuild(self):
         _check(dem_request_rebuild(self.ctx), "dem_request_rebuild")
+
+    def set_closure(self, mlp=None, norm=None):
+        """learned closure from the current parameters of `mlp` (an Mlp), with
+        norm = (mean[6], sd[6]); None switches it off"""
+        if mlp is None:
+            _check(dem_set_closure(self.ctx, None, None), "dem_set_closure")
+            return
+        nn = np.ascontiguousarray(np.asarray(norm, dtype=np.float64).reshape(12))
+        _check(dem_set_closure(self.ctx, mlp.h, nn.ctypes.data), "dem_set_closure")
+
+    def read_closure(self):
+        f = np.zeros((self.n, 6))
+        cd, cc = np.zeros(self.n), np.zeros(self.n)
+        _check(dem_read_closure(self.ctx, f.ctypes.data, cd.ctypes.data, cc.ctypes.data), "dem_read_closure")
+        return {"features": f, "c_drag": cd, "c_coh": cc}
