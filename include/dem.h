@@ -205,6 +205,16 @@ dem_status dem_info(dem_ctx* ctx, int64_t* ncell, int64_t* n_pairs, int64_t* pai
 /* Force a neighbour-list rebuild at the start of the next step. */
 dem_status dem_request_rebuild(dem_ctx* ctx);
 
+/* Step windows as recorded HIP graphs (enable 1) or direct launches (0, the
+ * default).  A window that does not contain the last step of a dem_step call
+ * is recorded once per (state buffer, step modulo the coupling interval,
+ * length) and replayed; the kernels read the context's state through a device
+ * copy refreshed at every call and rebuild, so a recording survives list
+ * rebuilds.  Results are identical either way.  Recording is skipped while
+ * kernel timing (dem_profile) is on, and abandoned for the context if the
+ * runtime refuses it. */
+dem_status dem_set_graphs(dem_ctx* ctx, int32_t enable);
+
 /* Kernel-class timing with HIP events recorded on the context's stream
  * around every launch of each class (for roofline reporting).  enable = 1
  * starts (and zeroes) the accumulators, 0 stops.  dem_read_profile fills

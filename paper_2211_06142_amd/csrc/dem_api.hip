@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <vector>
 
 #include "dem_internal.h"
@@ -62,6 +63,9 @@ struct dem_ctx {
   WallSet ws[2];
   int live = 0;          // ns[live] / ws[live] is the current list
   int last_overflow_rows = 0;   // rows the last search could not keep in scratch
+  DevState* d_dev = nullptr;    // device copy of d
+  int use_graphs = 0;           // replay recorded step windows
+  std::map<int64_t, hipGraphExec_t> graphs;
   // learned closure: factor arrays and their permutation scratch (kept while off)
   double* cl_buf[4] = {nullptr, nullptr, nullptr, nullptr};
   double *cl_feat = nullptr, *cl_feat_tmp = nullptr, *cl_norm = nullptr;
@@ -402,45 +406,97 @@ dem_status fault(dem_ctx* c, int st) {
 // step; every later launch of the window exits at entry.  At the end of the
 // window the host reads the flags, rebuilds the list from the state the last
 // completed step left, and resumes at the recorded step.
+// the step-window kernels read the context's state from its device copy
+dem_status upload_state(dem_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->d_dev, &c->d, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  return DEM_OK;
+}
+
+void drop_graphs(dem_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+// Enqueue the steps [t, t1) of a window starting from buffer b0.  StepArgs.step
+// is relative to the window start (the recorded abort step is too), so a
+// window's launches depend only on (b0, t mod couple_every, length): windows
+// without the last step of the call replay one recorded graph per such key.
+template <typename R> void enqueue_window(dem_ctx* c, int64_t t, int64_t t1, int64_t s_end, int b0, bool eager) {
+  DevState& d = c->d;
+  hipStream_t s = c->stream;
+  const bool fluid = c->any_fluid && c->have_fluid;
+  auto body = [&](bool prof) {
+    int b = b0;
+    for (int64_t q = t; q < t1; ++q) {
+      if (fluid && (q % d.couple_every) == 0) {
+        int pf = prof ? prof_begin(c) : -1;
+        launch_fluid<R>(d, b, s);
+        if (prof) prof_end(c, DEM_PROF_FLUID, pf, q);
+      }
+      StepArgs a{q - t, b, 1 - b, q == s_end - 1 ? 1 : 0};
+      int pk = prof ? prof_begin(c) : -1;
+      launch_step<R>(d, a, s);
+      if (prof) prof_end(c, DEM_PROF_STEP, pk, q);
+      b = 1 - b;
+    }
+  };
+  if (eager || c->prof || !c->use_graphs) {
+    body(c->prof != 0);
+    return;
+  }
+  const int64_t key = ((int64_t)b0 << 40) | ((fluid ? t % d.couple_every : 0) << 20) | (t1 - t);
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      body(false);
+      ok = hipStreamEndCapture(s, &g) == hipSuccess && g != nullptr;
+    }
+    if (ok) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {   // recording failed: run this window eagerly and stop recording
+      c->use_graphs = 0;
+      body(false);
+      return;
+    }
+    it = c->graphs.emplace(key, ge).first;
+  }
+  (void)hipGraphLaunch(it->second, s);
+}
+
+// Steps are enqueued in windows without waiting for the device.  A step that
+// finds a particle beyond half the skin raises `abort` and records the next
+// step; every later launch of the window exits at entry.  At the end of the
+// window the host reads the flags, rebuilds the list from the state the last
+// completed step left, and resumes at the recorded step.
 template <typename R> dem_status step_impl(dem_ctx* c, int64_t nsteps) {
   DevState& d = c->d;
   hipStream_t s = c->stream;
   if (nsteps <= 0) return DEM_OK;
   const int64_t s_end = c->step + nsteps;
+  if (upload_state(c) != DEM_OK) return DEM_E_DEVICE;
   HIPCHK(hipMemsetAsync(d.abort, 0, sizeof(int), s));
-  HIPCHK(hipMemsetAsync(d.abort_step, 0xff, sizeof(int), s));
+  HIPCHK(hipMemsetAsync(d.abort_step, 0x7f, sizeof(int), s));   // none: 0x7f7f7f7f
   // first half kick and drift of the first step
   // (in place: the pair history stays in the buffer of the particle state)
   int ps = prof_begin(c);
-  StepArgs pa{c->step, d.cur, d.cur, 0};
+  StepArgs pa{0, d.cur, d.cur, 0};
   launch_prologue<R>(d, pa, s);
   prof_end(c, DEM_PROF_PROLOGUE, ps);
   int buf = d.cur;           // buffer holding the drifted state of step c->step
   if (c->force_rebuild) {
     HIPCHK(hipStreamSynchronize(s));
-    c->h_flags[3] = (int)c->step;
+    c->h_flags[3] = 0;
     HIPCHK(hipMemsetAsync(d.abort, 0xff, sizeof(int), s));
     HIPCHK(hipMemcpyAsync(d.abort_step, c->h_flags + 3, sizeof(int), hipMemcpyHostToDevice, s));
     c->force_rebuild = 0;
   }
   int64_t t = c->step;
   while (t < s_end) {
-    std::vector<int> bufs;
-    bufs.push_back(buf);
     int64_t t1 = std::min<int64_t>(s_end, t + c->window);
-    for (int64_t q = t; q < t1; ++q) {
-      int b = bufs.back();
-      if (c->any_fluid && c->have_fluid && (q % d.couple_every) == 0) {
-        int pf = prof_begin(c);
-        launch_fluid<R>(d, b, s);
-        prof_end(c, DEM_PROF_FLUID, pf, q);
-      }
-      StepArgs a{q, b, 1 - b, q == s_end - 1 ? 1 : 0};
-      int pk = prof_begin(c);
-      launch_step<R>(d, a, s);
-      prof_end(c, DEM_PROF_STEP, pk, q);
-      bufs.push_back(1 - b);
-    }
+    enqueue_window<R>(c, t, t1, s_end, buf, t1 == s_end);
     dem_status rs = read_flags(c);
     if (rs != DEM_OK) return rs;
     int abort = c->h_flags[0], astep = c->h_flags[1], status = c->h_flags[2];
@@ -450,22 +506,23 @@ template <typename R> dem_status step_impl(dem_ctx* c, int64_t nsteps) {
     }
     if (!abort) {
       prof_collect(c);
-      buf = bufs.back();
+      if ((t1 - t) & 1) buf = 1 - buf;
       t = t1;
       continue;
     }
     // resume at the recorded step after a rebuild from the state before it
-    int64_t ta = astep;
-    if (ta < t || ta > t1) return fault(c, kStBadAbort);
+    if (astep < 0 || astep > t1 - t) return fault(c, kStBadAbort);
+    int64_t ta = t + astep;
     prof_collect(c, ta);
-    buf = bufs[ta - t];
+    if (astep & 1) buf = 1 - buf;
     d.cur = buf;
     HIPCHK(hipMemsetAsync(d.abort, 0, sizeof(int), s));
-    HIPCHK(hipMemsetAsync(d.abort_step, 0xff, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(d.abort_step, 0x7f, sizeof(int), s));   // none: 0x7f7f7f7f
     int pr = prof_begin(c);
     dem_status st = rebuild<R>(c, 0, 0);
     if (st != DEM_OK) return st;
     prof_end(c, DEM_PROF_REBUILD, pr);
+    if (upload_state(c) != DEM_OK) return DEM_E_DEVICE;
     buf = d.cur;
     t = ta;
   }
@@ -687,6 +744,8 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.broken, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.status, 1) == hipSuccess && dalloc(c, &d.abort, 1) == hipSuccess;
   ok &= dalloc(c, &d.abort_step, 1) == hipSuccess;
+  ok &= dalloc_bytes(c, (void**)&c->d_dev, sizeof(DevState)) == hipSuccess;
+  d.self = c->d_dev;
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nbk, n + 1), d.ndual + 2);
   d.scan_tmp_n = scan_n / 256 + 4096;
   ok &= dalloc(c, &d.scan_tmp, d.scan_tmp_n) == hipSuccess;
@@ -840,6 +899,7 @@ dem_status dem_map_fluid(dem_ctx* c, const double* u_cell, const double* gradp_c
   if (u_cell && gradp_cell && nc > 0) {
     HIPCHK(hipMemcpyAsync(c->d.u_in, u_cell, sizeof(double) * 3 * nc, hipMemcpyDefault, s));
     HIPCHK(hipMemcpyAsync(c->d.gp_in, gradp_cell, sizeof(double) * 3 * nc, hipMemcpyDefault, s));
+    if (!c->have_fluid) drop_graphs(c);   // recorded windows hold no coupling yet
     c->have_fluid = 1;
   } else if (u_cell || gradp_cell) {
     return DEM_E_INVAL;
@@ -1032,6 +1092,7 @@ dem_status dem_read_fault(dem_ctx* c, int32_t* bits) {
 dem_status dem_set_closure(dem_ctx* c, const dem_mlp* mlp, const double* norm) {
   if (!c) return DEM_E_INVAL;
   if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  drop_graphs(c);
   DevState& d = c->d;
   hipStream_t s = c->stream;
   if (!mlp) {
@@ -1102,6 +1163,15 @@ dem_status dem_read_closure(dem_ctx* c, double* features, double* c_drag, double
   return DEM_OK;
 }
 
+dem_status dem_set_graphs(dem_ctx* c, int32_t enable) {
+  if (!c) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  c->use_graphs = enable ? 1 : 0;
+  return DEM_OK;
+}
+
 dem_status dem_request_rebuild(dem_ctx* c) {
   if (!c) return DEM_E_INVAL;
   c->force_rebuild = 1;
@@ -1113,6 +1183,7 @@ void dem_destroy(dem_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  drop_graphs(c);
   for (void* p : c->allocs)
     if (p) (void)hipFree(p);
   if (c->stage) (void)hipFree(c->stage);

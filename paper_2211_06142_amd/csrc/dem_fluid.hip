@@ -18,7 +18,8 @@ namespace dem {
 // Every particle gets a key in range, also when the window was aborted (then
 // buffer `buf` may never have been written and every particle goes to its
 // sample's skip bucket): the bucket sort that follows is not gated.
-__global__ void k_fluid_key(DevState d, int buf) {
+__global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
+  const DevState& d = *dp;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   const SampleConst& c = d.sc[d.sample[i]];
@@ -64,7 +65,8 @@ __device__ inline double corner_w(const double4& fr, int kx, int ky, int kz) {
 
 // corner partials of every bucket: kind 0 volume (8 per bucket), kind 1 drag (24 per bucket)
 template <int kKind>
-__global__ void k_fluid_partials(DevState d) {
+__global__ void k_fluid_partials(const DevState* __restrict__ dp) {
+  const DevState& d = *dp;
   if (*d.abort) return;
   int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= d.ndual) return;
@@ -94,7 +96,8 @@ __global__ void k_fluid_partials(DevState d) {
 
 // per fluid cell: fixed-order sum of the corner partials of the adjacent buckets
 template <int kKind>
-__global__ void k_fluid_cells(DevState d) {
+__global__ void k_fluid_cells(const DevState* __restrict__ dp) {
+  const DevState& d = *dp;
   if (*d.abort) return;
   int64_t C = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (C >= d.ncell) return;
@@ -187,7 +190,8 @@ __device__ inline void particle_fluid(const DevState& d, const SampleConst& c, i
 // (eq 11, fine diameter d/k), k, and the mean of delta/R* over the pairs that
 // took part in the last force evaluation, with their count.  Dead: zeros.
 template <typename R>
-__global__ void k_closure_features(DevState d, int buf) {
+__global__ void k_closure_features(const DevState* __restrict__ dp, int buf) {
+  const DevState& d = *dp;
   if (*d.abort) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
@@ -225,7 +229,8 @@ __global__ void k_closure_features(DevState d, int buf) {
 }
 
 template <typename R>
-__global__ void k_fluid_drag(DevState d, int buf) {
+__global__ void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
+  const DevState& d = *dp;
   if (*d.abort) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
@@ -262,18 +267,18 @@ __global__ void k_fluid_drag(DevState d, int buf) {
 }
 
 template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
-  hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, buf);
+  hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
   launch_bucket_sort((const uint32_t*)d.dkey, d.n, d.ndual, nullptr, d.dcnt, d.doff, d.dfill, d.dmem_tmp,
                      d.dmem, d.scan_tmp, d.dual_sink, d.abort, s);
-  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d);
-  if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d);
+  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d.self);
+  if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
   if (d.closure_on) {
-    hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, buf);
+    hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
     launch_closure_infer(d, s);
   }
-  hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d, buf);
-  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d);
-  if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d);
+  hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
+  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d.self);
+  if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
 }
 template void launch_fluid<double>(DevState&, int, hipStream_t);
 template void launch_fluid<float>(DevState&, int, hipStream_t);

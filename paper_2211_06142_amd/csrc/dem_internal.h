@@ -72,6 +72,7 @@ template <> struct Vec4<float> { using type = float4; };
 template <typename R> using R4 = typename Vec4<R>::type;
 
 struct DevState {
+  const DevState* self;            // device copy of this struct (read by the step-window kernels)
   int64_t n;
   int nsamples;
   double dt;

@@ -339,7 +339,8 @@ __global__ void k_mlp_to_bf16(const float* p, short* wb) {
 // closure inference inside the DEM: features (FP64, n x 6) -> normalised ->
 // network -> factors c = exp(clip(y, -ln 2, ln 2)) into cdrag, ccoh
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_closure_infer(DevState d) {
+__global__ __launch_bounds__(256) void k_closure_infer(const DevState* __restrict__ dp) {
+  const DevState& d = *dp;
   if (*d.abort) return;
   const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
   const int64_t nt = (d.n + 15) / 16;
@@ -371,7 +372,7 @@ void launch_closure_infer(DevState& d, hipStream_t s) {
   int64_t tiles = (d.n + 15) / 16;
   int64_t blocks = (tiles + 3) / 4;
   if (blocks > 2048) blocks = 2048;
-  if (blocks > 0) hipLaunchKernelGGL(k_closure_infer, dim3((unsigned)blocks), dim3(256), 0, s, d);
+  if (blocks > 0) hipLaunchKernelGGL(k_closure_infer, dim3((unsigned)blocks), dim3(256), 0, s, d.self);
 }
 
 }  // namespace dem

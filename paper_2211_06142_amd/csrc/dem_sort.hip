@@ -65,6 +65,14 @@ void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hi
 // where the rank (quadratic in the bucket size) would not scale.  With a gate
 // flag set, the whole sort does nothing.
 // ---------------------------------------------------------------------------
+__global__ void k_zero2(int32_t* a, int32_t* b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    a[i] = 0;
+    b[i] = 0;
+  }
+}
+
 __global__ void k_bucket_count(const uint32_t* key, int64_t n, int32_t* cnt, const int* gate) {
   if (gate && *gate) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -133,8 +141,8 @@ __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t
 void launch_bucket_sort(const uint32_t* key, int64_t n, int64_t nb, const int32_t* tiebreak, int32_t* cnt,
                         int32_t* off, int32_t* fill, int32_t* order_tmp, int32_t* out_order,
                         int32_t* scan_tmp, const uint8_t* sink, const int* gate, hipStream_t s) {
-  (void)hipMemsetAsync(cnt, 0, sizeof(int32_t) * (nb + 1), s);
-  (void)hipMemsetAsync(fill, 0, sizeof(int32_t) * (nb + 1), s);
+  // cleared by a kernel, not a memset: the sort is also recorded into graphs
+  hipLaunchKernelGGL(k_zero2, dim3(nblk(nb + 1)), dim3(kBlock), 0, s, cnt, fill, nb + 1);
   if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt, gate);
   scan_exclusive(cnt, off, nb + 1, scan_tmp, s);
   if (n > 0)

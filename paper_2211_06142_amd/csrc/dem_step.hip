@@ -16,7 +16,7 @@
 namespace dem {
 
 template <typename R>
-__device__ inline void finish_drift(DevState& d, const SampleConst& c, int64_t i, int out, int64_t next_step,
+__device__ inline void finish_drift(const DevState& d, const SampleConst& c, int64_t i, int out, int64_t next_step,
                                     double4 p, double4 v, R4<R> w) {
   const double dt = d.dt;
   double sx = dt * v.x, sy = dt * v.y, sz = dt * v.z;
@@ -45,7 +45,7 @@ __device__ inline void finish_drift(DevState& d, const SampleConst& c, int64_t i
     double ux = p.x - q.x, uy = p.y - q.y, uz = p.z - q.z;
     if ((ux * ux + uy * uy) + uz * uz > hs * hs) {
       atomicOr(d.abort, 1);
-      atomicMax(d.abort_step, (int)next_step);
+      atomicMin(d.abort_step, (int)next_step);
     }
   }
 }
@@ -97,9 +97,14 @@ __device__ inline R group_sum(R v) {
   return v;
 }
 
+// A launch exits at entry when a rebuild is due at or before its step: the
+// recorded abort step (no rebuild: a large value) is written only by an
+// earlier launch or by the launch that finds it due for the NEXT step, so every
+// block of one launch takes the same decision.
 template <typename R>
-__global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
-  if (*d.abort) return;
+__global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, StepArgs a) {
+  const DevState& d = *dp;
+  if (*d.abort_step <= a.step) return;
   const int sub = threadIdx.x & (kGroup - 1);
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
   if (i >= d.n) return;   // whole group
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(256) void k_step(DevState d, StepArgs a) {
 }
 
 template <typename R> void launch_step(DevState& d, StepArgs a, hipStream_t s) {
-  hipLaunchKernelGGL(k_step<R>, dim3(nblk(d.n * kGroup)), dim3(kBlock), 0, s, d, a);
+  hipLaunchKernelGGL(k_step<R>, dim3(nblk(d.n * kGroup)), dim3(kBlock), 0, s, d.self, a);
 }
 template void launch_step<double>(DevState&, StepArgs, hipStream_t);
 template void launch_step<float>(DevState&, StepArgs, hipStream_t);

@@ -290,3 +290,44 @@ def c3_sample(s, n_s, gamma):
                      name="c3_s%d_n%d" % (s, n_s))
     w.update(precision="mixed", steps=2000, n_fine=int(n_s))
     return w
+
+
+def c3_crop(s, n_s, gamma, base=None):
+    """Ensemble sample s: the spheres of the settled C1 bed (annulus 2-12 mm) whose centres lie in
+    an axis-aligned box of the bed's height (0.05 mm to 2.4 mm) and a square
+    footprint holding about n_s of them, centred at radius 7 mm and angle
+    2 pi s / 37 in the annulus; shifted to the origin, with six walls one
+    largest radius outside the box (no initial wall overlap), a grid of 8-16
+    cells per side and a uniform upward flow.  Dense, settled and cheap: no
+    packing run per sample."""
+    base = base if base is not None else c1()
+    x, r = base["x"], base["r"]
+    z0, z1 = 0.05e-3, 2.4e-3
+    dens = len(r) / (math.pi * (12e-3 ** 2 - 2e-3 ** 2) * base["bed_top"])   # C1 annulus
+    a = math.sqrt(n_s / (dens * (z1 - z0)))
+    th = 2.0 * math.pi * s / 37.0
+    cx, cy = 7.0e-3 * math.cos(th), 7.0e-3 * math.sin(th)
+    lo = np.array([cx - a / 2, cy - a / 2, z0])
+    hi = np.array([cx + a / 2, cy + a / 2, z1])
+    sel = np.all((x >= lo) & (x < hi), axis=1)
+    xs, rs = x[sel] - lo, r[sel].copy()
+    pad = rs.max()
+    wlo, whi = -pad * np.ones(3), (hi - lo) + pad
+    gn = int(min(16, max(8, round(8 * (len(rs) / 2000.0) ** (1.0 / 3.0)))))
+    grid = (tuple(wlo), tuple(whi), (gn, gn, gn))
+    u, gp = uniform_field(grid, (0.0, 0.0, 0.02))
+    mat = dict(MATERIAL)
+    mat["gamma"] = gamma
+    return dict(name="c3_s%d_n%d" % (s, n_s), x=xs, r=rs, material=mat, k=1.0, scheme="ssw",
+                walls=box_walls(tuple(wlo), tuple(whi)), grid=grid, u_cell=u, gradp_cell=gp,
+                fluid=dict(WATER, n_min=N_MIN, voidfrac=0, u_superficial=1, couple_every=COUPLE_EVERY),
+                outlet=None, dt=DT, g=GRAV, sha256=base["sha256"], precision="mixed", steps=2000,
+                n_fine=len(rs))
+
+
+def c3(n_samples=256, seed=SEED0 + 3):
+    """The batched ensemble: n_samples crops with sizes 500-20 000 and surface
+    energies 0.1-1.0 J/m^2 (c3_sizes)."""
+    ns, gam = c3_sizes(n_samples, seed)
+    base = c1()
+    return [c3_crop(s, int(ns[s]), float(gam[s]), base) for s in range(n_samples)]

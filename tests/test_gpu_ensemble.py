@@ -1,0 +1,85 @@
+"""GPU parity of the batched ensemble (an extension; not in arXiv:2211.06142):
+independent samples with their own surface energy, walls and fluid grid share
+one context and one launch per kernel; each must reproduce the oracle run of
+that sample alone, and its own single-sample GPU run bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2211_06142_amd import dem  # noqa: E402
+
+SIZES = [(0, 700, 0.15), (3, 1500, 0.9), (7, 300, 0.5), (11, 2200, 0.3), (19, 1000, 0.7)]
+
+
+def _samples(precision="fp64"):
+    base = synth.c1()
+    ws = [synth.c3_crop(s, n, g, base) for s, n, g in SIZES]
+    for w in ws:
+        w["precision"] = precision
+    return ws
+
+
+def _batched(ws, precision):
+    params = [dem.params_from_workload(w, precision=precision) for w in ws]
+    offs = np.cumsum([0] + [len(w["r"]) for w in ws]).astype(np.int64)
+    x = np.concatenate([w["x"] for w in ws])
+    r = np.concatenate([w["r"] for w in ws])
+    sim = dem.Simulation(params, x, r, sample_offsets=offs)
+    sim.map_fluid(np.concatenate([w["u_cell"] for w in ws]), np.concatenate([w["gradp_cell"] for w in ws]))
+    return sim, offs
+
+
+def _oracle(w):
+    mat = cg.scale_material(w["material"], w.get("k", 1.0))
+    op = oracle.make_params(mat, w["dt"], g=w["g"], walls=w["walls"], grid=w["grid"], fluid=w["fluid"],
+                            outlet=w["outlet"])
+    o = oracle.OracleSim(op, w["x"], w["r"], bond_at_init=True)
+    o.set_fluid(w["u_cell"], w["gradp_cell"])
+    return o
+
+
+def test_ensemble_matches_oracle_per_sample():
+    ws = _samples()
+    sim, offs = _batched(ws, "fp64")
+    nsteps = 2 * ws[0]["fluid"]["couple_every"] + 3
+    sim.step(nsteps)
+    st = sim.state()
+    pairs = sim.pairs()["pairs"]
+    agg = sim.aggregates()
+    for s, w in enumerate(ws):
+        o = _oracle(w)
+        o.step(nsteps)
+        os_ = o.state()
+        a, b = offs[s], offs[s + 1]
+        err = np.linalg.norm(st["F"][a:b] - os_["F"], axis=1) / (os_["fscale"] + 1e-300)
+        assert err.max() < 1e-12, s
+        np.testing.assert_allclose(st["x"][a:b], os_["x"], rtol=0, atol=1e-16)
+        mine = pairs[(pairs[:, 0] >= a) & (pairs[:, 0] < b)] - a
+        np.testing.assert_array_equal(mine, o.pairs()["pairs"])
+        assert agg["broken_bonds"][s] == o.scalars()["broken_bonds"]
+
+
+def test_ensemble_sample_equals_its_single_run():
+    ws = _samples("mixed")
+    sim, offs = _batched(ws, "mixed")
+    k = 3
+    one = dem.Simulation(dem.params_from_workload(ws[k], precision="mixed"), ws[k]["x"], ws[k]["r"])
+    one.map_fluid(ws[k]["u_cell"], ws[k]["gradp_cell"])
+    sim.step(25)
+    one.step(25)
+    a, b = offs[k], offs[k + 1]
+    # no rebuild after the initial one on either side, so the rows (and the
+    # summation order of every force) are the same
+    assert sim.info()["rebuilds"] == 1 and one.info()["rebuilds"] == 1
+    sb, so = sim.state(), one.state()
+    for key in ("x", "v", "w", "F", "T"):
+        np.testing.assert_array_equal(sb[key][a:b], so[key], err_msg=key)
