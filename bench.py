@@ -1,6 +1,7 @@
 """Benchmark: DEM + fluid-coupling steps on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c3] [--no-cpu]
+                [--skin-factor F] [--lanes L] [--graphs 0|1] [--tune]
 
 Workload c1: 200 000 polydisperse spheres in the hollow cylinder with the radial
 Darcy inflow (mixed precision: FP64 positions/velocities, FP32 forces), inputs
@@ -22,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SKIN_FACTOR = 0.2   # neighbour skin / smallest radius (the library default)
+LANES = 8           # lanes per particle of the step kernel
 
 
 def source_hash():
@@ -98,14 +101,36 @@ def cpu_baseline(w, budget_s=15.0):
                       % (w["name"], len(w["r"]), steps, w["fluid"]["couple_every"], el, t_init)}
 
 
+def build_sim(ws, skin_factor, lanes, graphs):
+    from paper_2211_06142_amd import dem
+    rmin = min(float(np.min(w["r"])) for w in ws)
+    skin = skin_factor * rmin if skin_factor > 0 else 0.0
+    params = [dem.params_from_workload(w, skin=skin) for w in ws]
+    if len(ws) == 1:
+        sim = dem.Simulation(params[0], ws[0]["x"], ws[0]["r"])
+    else:
+        offs = np.cumsum([0] + [len(w["r"]) for w in ws]).astype(np.int64)
+        sim = dem.Simulation(params, np.concatenate([w["x"] for w in ws]), np.concatenate([w["r"] for w in ws]),
+                             sample_offsets=offs)
+    sim.map_fluid(np.concatenate([w["u_cell"] for w in ws]), np.concatenate([w["gradp_cell"] for w in ws]))
+    sim.set_lanes(lanes)
+    sim.set_graphs(graphs)
+    return sim
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c0", "c3"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--skin-factor", type=float, default=SKIN_FACTOR,
+                    help="neighbour skin as a multiple of the smallest radius")
+    ap.add_argument("--lanes", type=int, default=LANES, help="lanes per particle of the step kernel")
+    ap.add_argument("--graphs", type=int, default=0, help="replay recorded step windows (timing off)")
+    ap.add_argument("--tune", action="store_true", help="autotune skin and lanes before the timed run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU sharding of the DEM step is a "
@@ -114,18 +139,25 @@ def main():
 
     import torch
     import synth
-    from paper_2211_06142_amd import dem
+    from paper_2211_06142_amd import tune
 
     if args.workload == "c1":
-        w = synth.c1()
+        ws = [synth.c1()]
     elif args.workload == "c0":
-        w = synth.c0()
+        ws = [synth.c0()]
     else:
-        raise SystemExit("unknown workload")
-    p = dem.params_from_workload(w)
-    sim = dem.Simulation(p, w["x"], w["r"])
-    sim.map_fluid(w["u_cell"], w["gradp_cell"])
-    print("bench: %s set up, %d particles" % (w["name"], len(w["r"])), file=sys.stderr, flush=True)
+        ws = synth.c3()
+    w = ws[0]
+    tuned = None
+    if args.tune:
+        best, table = tune.tune_workload(ws if len(ws) > 1 else w, log=lambda m: print(m, file=sys.stderr, flush=True))
+        rmin = min(float(np.min(x["r"])) for x in ws)
+        args.skin_factor, args.lanes = best["skin"] / rmin, best["lanes"]
+        tuned = {"skin_factor": args.skin_factor, "lanes": args.lanes, "trials": table}
+    sim = build_sim(ws, args.skin_factor, args.lanes, args.graphs)
+    n_total = sum(len(x["r"]) for x in ws)
+    print("bench: %s set up, %d particles in %d sample(s)" % (args.workload, n_total, len(ws)), file=sys.stderr,
+          flush=True)
     sim.step(args.warmup)
     n0 = sim.state()["n_alive"]
     print("bench: %d warm-up steps done, %d rebuilds" % (args.warmup, sim.info()["rebuilds"]), file=sys.stderr,
@@ -133,7 +165,9 @@ def main():
     stream = sim.stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    sim.profile(1)
+    profiled = not args.graphs
+    if profiled:
+        sim.profile(1)
     torch.cuda.synchronize()
     ev0.record(stream)
     t0 = time.perf_counter()
@@ -143,26 +177,42 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
     print("bench: %d timed steps done in %.1f ms" % (args.steps, ms), file=sys.stderr, flush=True)
-    prof = sim.read_profile()
-    sim.profile(0)
+    prof = sim.read_profile() if profiled else None
+    if profiled:
+        sim.profile(0)
     st = sim.state()
     inf = sim.info()
     n1 = st["n_alive"]
     n_alive = 0.5 * (n0 + n1)
     value = n_alive * args.steps / (ms * 1e-3)
     rsz = 8 if w["precision"] == "fp64" else 4
-    dom = max(prof, key=lambda k: prof[k][0])
-    dom_ms, dom_n = prof[dom]
-    avg_s = dom_ms * 1e-3 / max(dom_n, 1)
-    ab = alg_bytes(dom, n_alive, inf["n_pairs"], inf["ncell"], rsz)
-    achieved = ab / avg_s / 1e9
-    kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
-                   "avg_us": round(1e3 * v[0] / max(v[1], 1), 3),
-                   "alg_GBs": round(alg_bytes(k, n_alive, inf["n_pairs"], inf["ncell"], rsz) /
-                                    (v[0] * 1e-3 / max(v[1], 1)) / 1e9, 1) if v[1] else None}
-               for k, v in prof.items()}
+    roofline, kernels = None, None
+    if prof:
+        dom = max(prof, key=lambda k: prof[k][0])
+        dom_ms, dom_n = prof[dom]
+        avg_s = dom_ms * 1e-3 / max(dom_n, 1)
+        ab = alg_bytes(dom, n_alive, inf["n_pairs"], inf["ncell"], rsz)
+        achieved = ab / avg_s / 1e9
+        kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
+                       "avg_us": round(1e3 * v[0] / max(v[1], 1), 3),
+                       "alg_GBs": round(alg_bytes(k, n_alive, inf["n_pairs"], inf["ncell"], rsz) /
+                                        (v[0] * 1e-3 / max(v[1], 1)) / 1e9, 1) if v[1] else None}
+                   for k, v in prof.items()}
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(dom, args.workload),
+                    "alg_bytes_per_launch": ab, "avg_launch_us": avg_s * 1e6}
+    if args.workload == "c3":
+        desc = ("c3: batched ensemble of %d independent samples (crops of the settled C1 bed, 500-20 000 "
+                "spheres each, surface energy 0.1-1.0 J/m^2, own walls and 8-16^3 fluid grid), %d spheres in "
+                "total, dt 1e-7 s, coupling every %d steps" % (len(ws), n_total, w["fluid"]["couple_every"]))
+        metric = "particle-steps/s, batched ensemble of 256 samples, 1 GPU"
+    else:
+        desc = ("%s: %d polydisperse spheres (lognormal d, median 0.15 mm), hollow cylinder R 12 mm / cavity "
+                "2 mm, 48x48x24 fluid grid, radial Darcy inflow, dt 1e-7 s, coupling every %d steps"
+                % (w["name"], len(w["r"]), w["fluid"]["couple_every"]))
+        metric = "particle-steps/s at 200k particles, 1 GPU"
     out = {
-        "metric": "particle-steps/s at 200k particles, 1 GPU",
+        "metric": metric,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -174,21 +224,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f64-positions/f32-forces" if rsz == 4 else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %d polydisperse spheres (lognormal d, median 0.15 mm), hollow cylinder "
-                               "R 12 mm / cavity 2 mm, 48x48x24 fluid grid, radial Darcy inflow, dt 1e-7 s, "
-                               "coupling every %d steps" % (w["name"], len(w["r"]), w["fluid"]["couple_every"]),
-                   "n_particles": len(w["r"]), "n_alive_mean": n_alive, "n_pairs": inf["n_pairs"],
-                   "rebuilds": inf["rebuilds"], "packing_sha256": w["sha256"][:16],
+        "config": {"workload": desc, "n_particles": n_total, "n_samples": len(ws), "n_alive_mean": n_alive,
+                   "n_pairs": inf["n_pairs"], "rebuilds": inf["rebuilds"], "packing_sha256": w["sha256"][:16],
                    "produced_mass_kg": st["produced_mass"], "coordination": st["coordination"],
-                   "broken_bonds": st["broken_bonds"], "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(dom, args.workload),
-                     "alg_bytes_per_launch": ab, "avg_launch_us": avg_s * 1e6},
+                   "broken_bonds": st["broken_bonds"], "skin_factor": args.skin_factor, "lanes": args.lanes,
+                   "graphs": bool(args.graphs), "parallelism": "single GPU"},
+        "roofline": roofline,
         "kernels": kernels,
         "wall_s": wall,
     }
+    if tuned:
+        out["config"]["tuned"] = tuned
     sim.close()
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload != "c3":
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
 

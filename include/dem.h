@@ -215,6 +215,12 @@ dem_status dem_request_rebuild(dem_ctx* ctx);
  * runtime refuses it. */
 dem_status dem_set_graphs(dem_ctx* ctx, int32_t enable);
 
+/* Lanes of the step kernel that share one particle's neighbour row: 4, 8
+ * (default) or 16; anything else is DEM_E_INVAL.  A tuning knob: forces are
+ * summed in a fixed tree within the group, so results differ between settings
+ * by rounding only, and are reproducible for each. */
+dem_status dem_set_lanes(dem_ctx* ctx, int32_t lanes);
+
 /* Kernel-class timing with HIP events recorded on the context's stream
  * around every launch of each class (for roofline reporting).  enable = 1
  * starts (and zeroes) the accumulators, 0 stops.  dem_read_profile fills

@@ -65,6 +65,7 @@ struct dem_ctx {
   int last_overflow_rows = 0;   // rows the last search could not keep in scratch
   DevState* d_dev = nullptr;    // device copy of d
   int use_graphs = 0;           // replay recorded step windows
+  hipStream_t cap_stream = nullptr;   // records them
   std::map<int64_t, hipGraphExec_t> graphs;
   // learned closure: factor arrays and their permutation scratch (kept while off)
   double* cl_buf[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -401,11 +402,6 @@ dem_status fault(dem_ctx* c, int st) {
   return DEM_E_STATE;
 }
 
-// Steps are enqueued in windows without waiting for the device.  A step that
-// finds a particle beyond half the skin raises `abort` and records the next
-// step; every later launch of the window exits at entry.  At the end of the
-// window the host reads the flags, rebuilds the list from the state the last
-// completed step left, and resumes at the recorded step.
 // the step-window kernels read the context's state from its device copy
 dem_status upload_state(dem_ctx* c) {
   HIPCHK(hipMemcpyAsync(c->d_dev, &c->d, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
@@ -423,9 +419,8 @@ void drop_graphs(dem_ctx* c) {
 // without the last step of the call replay one recorded graph per such key.
 template <typename R> void enqueue_window(dem_ctx* c, int64_t t, int64_t t1, int64_t s_end, int b0, bool eager) {
   DevState& d = c->d;
-  hipStream_t s = c->stream;
   const bool fluid = c->any_fluid && c->have_fluid;
-  auto body = [&](bool prof) {
+  auto body = [&](bool prof, hipStream_t s) {
     int b = b0;
     for (int64_t q = t; q < t1; ++q) {
       if (fluid && (q % d.couple_every) == 0) {
@@ -441,29 +436,34 @@ template <typename R> void enqueue_window(dem_ctx* c, int64_t t, int64_t t1, int
     }
   };
   if (eager || c->prof || !c->use_graphs) {
-    body(c->prof != 0);
+    body(c->prof != 0, c->stream);
     return;
   }
   const int64_t key = ((int64_t)b0 << 40) | ((fluid ? t % d.couple_every : 0) << 20) | (t1 - t);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
+    // recorded on a stream of the library's own (the caller's may be the legacy
+    // default stream, which cannot record), replayed on the caller's stream
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
-    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess;
+    bool ok = true;
+    if (!c->cap_stream) ok = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
     if (ok) {
-      body(false);
-      ok = hipStreamEndCapture(s, &g) == hipSuccess && g != nullptr;
+      body(false, c->cap_stream);
+      ok = hipStreamEndCapture(c->cap_stream, &g) == hipSuccess && g != nullptr;
     }
     if (ok) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
     if (g) (void)hipGraphDestroy(g);
-    if (!ok) {   // recording failed: run this window eagerly and stop recording
+    if (!ok) {   // the runtime refused: clear its error, run eagerly, stop recording
+      (void)hipGetLastError();
       c->use_graphs = 0;
-      body(false);
+      body(false, c->stream);
       return;
     }
     it = c->graphs.emplace(key, ge).first;
   }
-  (void)hipGraphLaunch(it->second, s);
+  (void)hipGraphLaunch(it->second, c->stream);
 }
 
 // Steps are enqueued in windows without waiting for the device.  A step that
@@ -746,6 +746,7 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.abort_step, 1) == hipSuccess;
   ok &= dalloc_bytes(c, (void**)&c->d_dev, sizeof(DevState)) == hipSuccess;
   d.self = c->d_dev;
+  d.group = 8;
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nbk, n + 1), d.ndual + 2);
   d.scan_tmp_n = scan_n / 256 + 4096;
   ok &= dalloc(c, &d.scan_tmp, d.scan_tmp_n) == hipSuccess;
@@ -1163,6 +1164,15 @@ dem_status dem_read_closure(dem_ctx* c, double* features, double* c_drag, double
   return DEM_OK;
 }
 
+dem_status dem_set_lanes(dem_ctx* c, int32_t lanes) {
+  if (!c || (lanes != 4 && lanes != 8 && lanes != 16)) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  c->d.group = lanes;
+  return DEM_OK;
+}
+
 dem_status dem_set_graphs(dem_ctx* c, int32_t enable) {
   if (!c) return DEM_E_INVAL;
   if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
@@ -1184,6 +1194,7 @@ void dem_destroy(dem_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->allocs)
     if (p) (void)hipFree(p);
   if (c->stage) (void)hipFree(c->stage);

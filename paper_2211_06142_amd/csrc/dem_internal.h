@@ -78,6 +78,7 @@ struct DevState {
   double dt;
   int couple_every;
   int rolling;                     // any sample with mu_roll > 0
+  int group;                       // lanes per particle of the step kernel (4, 8, 16)
   int cur;                         // buffer holding the current particle state and history
   // double-buffered particle state
   double4 *xr[2], *vel[2];

@@ -85,12 +85,11 @@ template <typename R> void launch_prologue(DevState& d, StepArgs a, hipStream_t 
 template void launch_prologue<double>(DevState&, StepArgs, hipStream_t);
 template void launch_prologue<float>(DevState&, StepArgs, hipStream_t);
 
-// Lanes per particle: a group of kGroup lanes shares one particle's row; lane
-// s evaluates entries s, s + kGroup, ... and the group sums its partial forces
+// Lanes per particle: a group of G lanes (4, 8 or 16, chosen per context)
+// shares one particle's row; lane s evaluates entries s, s + G, ... and the
+// group sums its partial forces
 // with a fixed xor butterfly (every lane ends with the bit-identical total).
-constexpr int kGroup = 8;
-
-template <typename R>
+template <typename R, int kGroup>
 __device__ inline R group_sum(R v) {
 #pragma unroll
   for (int off = kGroup / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kGroup);
@@ -101,7 +100,7 @@ __device__ inline R group_sum(R v) {
 // recorded abort step (no rebuild: a large value) is written only by an
 // earlier launch or by the launch that finds it due for the NEXT step, so every
 // block of one launch takes the same decision.
-template <typename R>
+template <typename R, int kGroup>
 __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, StepArgs a) {
   const DevState& d = *dp;
   if (*d.abort_step <= a.step) return;
@@ -200,8 +199,8 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    F[k] = group_sum<R>(F[k]);
-    T[k] = group_sum<R>(T[k]);
+    F[k] = group_sum<R, kGroup>(F[k]);
+    T[k] = group_sum<R, kGroup>(T[k]);
   }
   if (sub != 0) return;
   F[0] += (R)(m * c.g[0]);
@@ -244,7 +243,12 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
 }
 
 template <typename R> void launch_step(DevState& d, StepArgs a, hipStream_t s) {
-  hipLaunchKernelGGL(k_step<R>, dim3(nblk(d.n * kGroup)), dim3(kBlock), 0, s, d.self, a);
+  if (d.group == 4)
+    hipLaunchKernelGGL((k_step<R, 4>), dim3(nblk(d.n * 4)), dim3(kBlock), 0, s, d.self, a);
+  else if (d.group == 16)
+    hipLaunchKernelGGL((k_step<R, 16>), dim3(nblk(d.n * 16)), dim3(kBlock), 0, s, d.self, a);
+  else
+    hipLaunchKernelGGL((k_step<R, 8>), dim3(nblk(d.n * 8)), dim3(kBlock), 0, s, d.self, a);
 }
 template void launch_step<double>(DevState&, StepArgs, hipStream_t);
 template void launch_step<float>(DevState&, StepArgs, hipStream_t);

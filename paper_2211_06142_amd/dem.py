@@ -30,7 +30,7 @@ EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "de
                   "dem_read_aggregates", "dem_info", "dem_request_rebuild", "dem_destroy", "dem_status_str",
                   "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile",
                   "dem_read_fault", "dem_mlp_create", "dem_mlp_destroy", "dem_mlp_set_params", "dem_mlp_get_params",
-                  "dem_mlp_forward", "dem_mlp_grad", "dem_mlp_train_step", "dem_set_closure", "dem_read_closure", "dem_set_graphs"])
+                  "dem_mlp_forward", "dem_mlp_grad", "dem_mlp_train_step", "dem_set_closure", "dem_read_closure", "dem_set_graphs", "dem_set_lanes"])
 MLP_NPARAMS = 8898
 
 
@@ -139,6 +139,8 @@ def lib():
         L.dem_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
         L.dem_mlp_train_step.restype = i32
         L.dem_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp]
+        L.dem_set_lanes.restype = i32
+        L.dem_set_lanes.argtypes = [vp, i32]
         L.dem_set_graphs.restype = i32
         L.dem_set_graphs.argtypes = [vp, i32]
         L.dem_set_closure.restype = i32
@@ -557,6 +559,9 @@ class Simulation:
 
     def request_rebuild(self):
         _check(dem_request_rebuild(self.ctx), "dem_request_rebuild")
+
+    def set_lanes(self, lanes):
+        _check(lib().dem_set_lanes(self.ctx, int(lanes)), "dem_set_lanes")
 
     def set_graphs(self, enable):
         _check(lib().dem_set_graphs(self.ctx, 1 if enable else 0), "dem_set_graphs")

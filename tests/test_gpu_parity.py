@@ -146,6 +146,23 @@ def test_c0_fp64_steps(nsteps):
     assert gs["n_contacts"] == sc["n_contacts"]
 
 
+@pytest.mark.parametrize("lanes", [4, 16])
+def test_c0_fp64_lanes_per_particle(lanes):
+    """the step kernel's lane-group size is a tuning knob: any setting matches
+    the oracle to rounding"""
+    w = c0_sub()
+    g = gpu_for(w, "fp64")
+    g.set_lanes(lanes)
+    o = oracle_for(w, bond_at_init=True)
+    g.step(10)
+    o.step(10)
+    gs, os_ = g.state(), o.state()
+    assert scaled_err(gs["F"], os_["F"], os_["fscale"]) < 1e-12
+    assert scaled_err(gs["T"], os_["T"], os_["tscale"]) < 1e-12
+    with pytest.raises(dem.DemError):
+        g.set_lanes(5)
+
+
 def test_c0_fluid_cells_fp64():
     w = c0_sub()
     g = gpu_for(w, "fp64")
