@@ -23,8 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SKIN_FACTOR = 0.2   # neighbour skin / smallest radius (the library default)
-LANES = 8           # lanes per particle of the step kernel
+SKIN_FACTOR = 0.4   # neighbour skin / smallest radius (the library default)
+LANES = 4           # lanes per particle of the step kernel (the library default)
 
 
 def source_hash():

@@ -106,7 +106,7 @@ typedef struct {
   dem_grid grid;            /* fluid grid of this sample                            */
   double g[3];              /* gravity                                              */
   double dt;                /* DEM time step (same for all samples)                 */
-  double skin;              /* neighbour-list skin; <= 0: 0.1 x smallest diameter   */
+  double skin;              /* neighbour-list skin; <= 0: 0.2 x smallest diameter   */
   double dt_rayleigh_max_frac; /* > 0: reject dt above this fraction of eq 37       */
   int32_t outlet_kind;      /* DEM_OUTLET_*                                         */
   int32_t n_walls;          /* <= DEM_MAX_WALLS                                     */
@@ -215,8 +215,8 @@ dem_status dem_request_rebuild(dem_ctx* ctx);
  * runtime refuses it. */
 dem_status dem_set_graphs(dem_ctx* ctx, int32_t enable);
 
-/* Lanes of the step kernel that share one particle's neighbour row: 4, 8
- * (default) or 16; anything else is DEM_E_INVAL.  A tuning knob: forces are
+/* Lanes of the step kernel that share one particle's neighbour row: 1, 2, 4
+ * (default), 8 or 16; anything else is DEM_E_INVAL.  A tuning knob: forces are
  * summed in a fixed tree within the group, so results differ between settings
  * by rounding only, and are reproducible for each. */
 dem_status dem_set_lanes(dem_ctx* ctx, int32_t lanes);

@@ -81,6 +81,8 @@ struct dem_ctx {
   int failed = 0;        // a latched device fault
   int window = 32;       // steps enqueued between host checks
   int* h_flags = nullptr;  // pinned: abort, abort_step, status
+  int32_t* h_tot = nullptr;   // pinned: rebuild totals
+  double* agg_buf = nullptr;  // aggregate outputs and slice partials
   std::vector<void*> allocs;
   // kernel-class timing
   int prof = 0;
@@ -214,7 +216,7 @@ void derive(const dem_params& p, const double* x, const double* r, const uint8_t
   }
   if (nal == 0) { for (int k = 0; k < 3; ++k) { bl[k] = 0.0; bh[k] = 0.0; } }
   if (rmax == 0.0) { rmin = rmax = 1e-6; }
-  c.skin = p.skin > 0.0 ? p.skin : 0.2 * rmin;
+  c.skin = p.skin > 0.0 ? p.skin : 0.4 * rmin;   // tuned: fewer rebuilds, rows barely longer
   // largest pull-off separation |delta_C| = (3/16)^(1/3) X (Table 1), with the
   // surface energy bounded by twice its value (closure factors are <= 2)
   double gmax = 2.0 * c.gamma;
@@ -362,12 +364,10 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   launch_wall_count(d, s);
   HIPCHK(hipMemsetAsync(d.wcnt + d.n, 0, sizeof(int32_t), s));
   scan_exclusive(d.wcnt, d.wrow, d.n + 1, d.scan_tmp, s);
-  int32_t tot[4];
-  HIPCHK(hipMemcpyAsync(&tot[0], d.nrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&tot[1], d.hrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&tot[2], d.wrow + d.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&tot[3], d.novf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  launch_totals(d, s);   // entries, slots, wall entries, overflow rows: one copy
+  HIPCHK(hipMemcpyAsync(c->h_tot, d.totals, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  const int32_t* tot = c->h_tot;
   NbrSet& ns = c->ns[c->live];
   WallSet& ws = c->ws[c->live];
   if (grow_nbr(c, ns, tot[0], tot[1]) != hipSuccess) return DEM_E_NOMEM;
@@ -388,9 +388,8 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
 }
 
 dem_status read_flags(dem_ctx* c) {
-  HIPCHK(hipMemcpyAsync(c->h_flags, c->d.abort, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(c->h_flags + 1, c->d.abort_step, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(c->h_flags + 2, c->d.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  // abort, abort_step and status are adjacent: one copy
+  HIPCHK(hipMemcpyAsync(c->h_flags, c->d.abort, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return DEM_OK;
 }
@@ -742,16 +741,19 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.dfill, d.ndual + 2) == hipSuccess;
   ok &= dalloc(c, &d.sc, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.broken, n_samples) == hipSuccess;
-  ok &= dalloc(c, &d.status, 1) == hipSuccess && dalloc(c, &d.abort, 1) == hipSuccess;
-  ok &= dalloc(c, &d.abort_step, 1) == hipSuccess;
+  ok &= dalloc(c, &d.abort, 4) == hipSuccess;   // abort, abort_step, status: adjacent
+  d.abort_step = d.abort + 1;
+  d.status = d.abort + 2;
+  ok &= dalloc(c, &d.totals, 4) == hipSuccess;
   ok &= dalloc_bytes(c, (void**)&c->d_dev, sizeof(DevState)) == hipSuccess;
   d.self = c->d_dev;
-  d.group = 8;
+  d.group = 4;   // tuned on the 200 000-sphere cylinder (4 beat 8 and 16 at every skin)
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nbk, n + 1), d.ndual + 2);
   d.scan_tmp_n = scan_n / 256 + 4096;
   ok &= dalloc(c, &d.scan_tmp, d.scan_tmp_n) == hipSuccess;
   if (!ok) return fail(DEM_E_NOMEM);
   if (hipHostMalloc((void**)&c->h_flags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(DEM_E_NOMEM);
+  if (hipHostMalloc((void**)&c->h_tot, 4 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) return fail(DEM_E_NOMEM);
   if (dalloc(c, &c->d_offsets, n_samples + 1) != hipSuccess) return fail(DEM_E_NOMEM);
 
   // upload in the caller's order into buffer 0
@@ -912,13 +914,16 @@ dem_status dem_map_fluid(dem_ctx* c, const double* u_cell, const double* gradp_c
 static dem_status aggregates(dem_ctx* c, std::vector<double>& pm, std::vector<double>& ke,
                              std::vector<long long>& nc, std::vector<long long>& na, std::vector<unsigned long long>& br) {
   int ns = c->d.nsamples;
-  double *dpm, *dke;
-  long long *dnc, *dna;
-  if (hipMalloc((void**)&dpm, sizeof(double) * ns * 2 + sizeof(long long) * ns * 2) != hipSuccess) return DEM_E_NOMEM;
-  dke = dpm + ns;
-  dnc = (long long*)(dke + ns);
-  dna = dnc + ns;
-  launch_aggregate_impl(c->d, c->d_offsets, dpm, dke, dnc, dna, nullptr, c->fp64, c->stream);
+  if (!c->agg_buf) {   // outputs (4 per sample) and the per-slice partials, kept for later calls
+    int64_t bytes = sizeof(double) * (4 * (int64_t)ns + aggregate_scratch_doubles(ns));
+    if (dalloc_bytes(c, (void**)&c->agg_buf, bytes) != hipSuccess) return DEM_E_NOMEM;
+  }
+  double* dpm = c->agg_buf;
+  double* dke = dpm + ns;
+  long long* dnc = (long long*)(dke + ns);
+  long long* dna = dnc + ns;
+  double* part = (double*)(dna + ns);
+  launch_aggregate_impl(c->d, c->d_offsets, dpm, dke, dnc, dna, part, c->fp64, c->stream);
   pm.resize(ns); ke.resize(ns); nc.resize(ns); na.resize(ns); br.resize(ns);
   bool ok = hipStreamSynchronize(c->stream) == hipSuccess;
   ok &= hipMemcpy(pm.data(), dpm, sizeof(double) * ns, hipMemcpyDeviceToHost) == hipSuccess;
@@ -926,7 +931,6 @@ static dem_status aggregates(dem_ctx* c, std::vector<double>& pm, std::vector<do
   ok &= hipMemcpy(nc.data(), dnc, sizeof(long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
   ok &= hipMemcpy(na.data(), dna, sizeof(long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
   ok &= hipMemcpy(br.data(), c->d.broken, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
-  (void)hipFree(dpm);
   for (int s = 0; s < ns; ++s) pm[s] -= c->dead_mass0[s];
   return ok ? DEM_OK : DEM_E_DEVICE;
 }
@@ -1165,7 +1169,7 @@ dem_status dem_read_closure(dem_ctx* c, double* features, double* c_drag, double
 }
 
 dem_status dem_set_lanes(dem_ctx* c, int32_t lanes) {
-  if (!c || (lanes != 4 && lanes != 8 && lanes != 16)) return DEM_E_INVAL;
+  if (!c || (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)) return DEM_E_INVAL;
   if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
@@ -1200,6 +1204,7 @@ void dem_destroy(dem_ctx* c) {
   if (c->stage) (void)hipFree(c->stage);
   if (c->stage_alive) (void)hipFree(c->stage_alive);
   if (c->h_flags) (void)hipHostFree(c->h_flags);
+  if (c->h_tot) (void)hipHostFree(c->h_tot);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }

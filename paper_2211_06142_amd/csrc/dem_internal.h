@@ -145,6 +145,7 @@ struct DevState {
   int* status;
   int* abort;                      // set when a rebuild is due before the next step
   int* abort_step;
+  int32_t* totals;                 // rebuild totals gathered for one copy
   int32_t* scan_tmp;
   int64_t scan_tmp_n;
 };
@@ -165,6 +166,7 @@ void launch_bucket_sort(const uint32_t* key, int64_t n, int64_t nb, const int32_
 void launch_bin_keys(DevState& d, hipStream_t s);
 template <typename R> void launch_permute(DevState& d, hipStream_t s);
 void launch_nbr_search(DevState& d, hipStream_t s);
+void launch_totals(DevState& d, hipStream_t s);
 void launch_nbr_fill(DevState& d, int novf, hipStream_t s);
 void launch_wall_count(DevState& d, hipStream_t s);
 void launch_wall_fill(DevState& d, hipStream_t s);
@@ -184,6 +186,7 @@ hipStream_t mlp_stream(const dem_mlp* n);
 // read-back
 template <typename R> void launch_unpermute(DevState& d, double* x, double* v, double* w, double* F,
                                             double* T, uint8_t* alive, hipStream_t s);
+int64_t aggregate_scratch_doubles(int nsamples);
 void launch_aggregate_impl(DevState& d, const int64_t* soff, double* produced, double* kinetic,
                            long long* contacts, long long* nalive, double* partial, int fp64, hipStream_t s);
 

@@ -29,50 +29,69 @@ void launch_unpermute(DevState& d, double* x, double* v, double* w, double* F, d
 template void launch_unpermute<double>(DevState&, double*, double*, double*, double*, double*, uint8_t*, hipStream_t);
 template void launch_unpermute<float>(DevState&, double*, double*, double*, double*, double*, uint8_t*, hipStream_t);
 
-// one 1024-thread block per sample
+// Aggregates in two fixed-order passes: kAggChunks blocks per sample each
+// reduce one contiguous slice of the sample's particles and half-pair slots
+// (tree in LDS), then one thread per sample sums its slices in order.
+constexpr int kAggChunks = 64;
+
 template <typename R>
-__global__ __launch_bounds__(1024) void k_aggregate(DevState d, const int64_t* soff, double* produced,
-                                                    double* kinetic, long long* contacts, long long* nalive) {
-  __shared__ double sm[1024], sk[1024];
-  __shared__ long long sc_[1024], sa[1024];
-  const int s = blockIdx.x;
+__global__ __launch_bounds__(256) void k_aggregate_part(DevState d, const int64_t* soff, double* part) {
+  __shared__ double sh[4][256];
+  const int s = blockIdx.x / kAggChunks, ch = blockIdx.x % kAggChunks;
   const int t = threadIdx.x;
   const int b = d.cur;
   const SampleConst& c = d.sc[s];
-  double pm = 0.0, ke = 0.0;
-  long long na = 0, nc = 0;
-  for (int64_t k = soff[s] + t; k < soff[s + 1]; k += 1024) {
+  const int64_t a0 = soff[s], a1 = soff[s + 1];
+  const int64_t k0 = a0 + (a1 - a0) * ch / kAggChunks, k1 = a0 + (a1 - a0) * (ch + 1) / kAggChunks;
+  double pm = 0.0, ke = 0.0, na = 0.0, nc = 0.0;
+  for (int64_t k = k0 + t; k < k1; k += 256) {
     double4 p = d.xr[b][k], v = d.vel[b][k];
     double m = c.rho * (4.0 / 3.0) * M_PI * p.w * p.w * p.w;
     if (!d.alive[b][k]) { pm += m; continue; }
-    ++na;
+    na += 1.0;
     R4<R> w = ((const R4<R>*)d.omg[b])[k];
     double I = 0.4 * m * p.w * p.w;
     double wx = w.x, wy = w.y, wz = w.z;
     ke += 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z) + 0.5 * I * ((wx * wx + wy * wy) + wz * wz);
   }
-  const int32_t p0 = d.hrow[soff[s]], p1 = d.hrow[soff[s + 1]];
-  for (int32_t p = p0 + t; p < p1; p += 1024) {
-    if ((d.pfl[b][p] & 3) && d.alive[b][d.sown[p]] && d.alive[b][d.spart[p]]) ++nc;
-  }
-  sm[t] = pm; sk[t] = ke; sc_[t] = nc; sa[t] = na;
+  const int64_t p0 = d.hrow[a0], p1 = d.hrow[a1];
+  const int64_t q0 = p0 + (p1 - p0) * ch / kAggChunks, q1 = p0 + (p1 - p0) * (ch + 1) / kAggChunks;
+  for (int64_t p = q0 + t; p < q1; p += 256)
+    if ((d.pfl[b][p] & 3) && d.alive[b][d.sown[p]] && d.alive[b][d.spart[p]]) nc += 1.0;
+  sh[0][t] = pm; sh[1][t] = ke; sh[2][t] = nc; sh[3][t] = na;
   __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (t < off) { sm[t] += sm[t + off]; sk[t] += sk[t + off]; sc_[t] += sc_[t + off]; sa[t] += sa[t + off]; }
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off)
+      for (int q = 0; q < 4; ++q) sh[q][t] += sh[q][t + off];
     __syncthreads();
   }
-  if (t == 0) { produced[s] = sm[0]; kinetic[s] = sk[0]; contacts[s] = sc_[0]; nalive[s] = sa[0]; }
+  if (t < 4) part[(int64_t)blockIdx.x * 4 + t] = sh[t][0];
 }
+
+__global__ void k_aggregate_final(const double* part, int nsamples, double* produced, double* kinetic,
+                                  long long* contacts, long long* nalive) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsamples) return;
+  double a[4] = {0, 0, 0, 0};
+  for (int ch = 0; ch < kAggChunks; ++ch)
+    for (int q = 0; q < 4; ++q) a[q] += part[((int64_t)s * kAggChunks + ch) * 4 + q];
+  produced[s] = a[0];
+  kinetic[s] = a[1];
+  contacts[s] = (long long)a[2];
+  nalive[s] = (long long)a[3];
+}
+
+int64_t aggregate_scratch_doubles(int nsamples) { return (int64_t)nsamples * kAggChunks * 4; }
 
 void launch_aggregate_impl(DevState& d, const int64_t* soff, double* produced, double* kinetic, long long* contacts,
                            long long* nalive, double* partial, int fp64, hipStream_t s) {
-  (void)partial;
+  const unsigned nb = (unsigned)(d.nsamples * kAggChunks);
   if (fp64)
-    hipLaunchKernelGGL(k_aggregate<double>, dim3(d.nsamples), dim3(1024), 0, s, d, soff, produced, kinetic,
-                       contacts, nalive);
+    hipLaunchKernelGGL(k_aggregate_part<double>, dim3(nb), dim3(256), 0, s, d, soff, partial);
   else
-    hipLaunchKernelGGL(k_aggregate<float>, dim3(d.nsamples), dim3(1024), 0, s, d, soff, produced, kinetic,
-                       contacts, nalive);
+    hipLaunchKernelGGL(k_aggregate_part<float>, dim3(nb), dim3(256), 0, s, d, soff, partial);
+  hipLaunchKernelGGL(k_aggregate_final, dim3(nblk(d.nsamples)), dim3(kBlock), 0, s, partial, d.nsamples, produced,
+                     kinetic, contacts, nalive);
 }
 
 }  // namespace dem

@@ -118,25 +118,23 @@ __device__ inline int32_t cand_index(const int32_t* srs, const int32_t* srl, int
   return j;
 }
 
-// row i straight from global memory (wavefront-wide): counts, and the row in
-// its scratch row as far as it fits
-__device__ inline void search_row_global(DevState& d, const double4* X, int32_t i, const int32_t* srs,
-                                         const int32_t* srl, int total, double margin, int lane, int& written,
-                                         int& owned) {
+// row i straight from global memory (wavefront-wide), cell by cell in
+// candidate order: counts, and the row in its scratch row as far as it fits
+__device__ inline void search_row_global(const DevState& d, const double4* X, int32_t i, const int32_t* srs,
+                                         const int32_t* srl, double margin, int lane, int& written, int& owned) {
   const double4 pi = X[i];
-  for (int base = 0; base < total; base += 64) {
-    const int t = base + lane;
-    bool pred = false;
-    int32_t j = -1;
-    if (t < total) {
-      j = cand_index(srs, srl, t);
-      pred = j != i && is_candidate(pi, X[j], margin);
+  for (int k = 0; k < 27; ++k) {
+    const int32_t c0 = srs[k], len = srl[k];
+    for (int base = 0; base < len; base += 64) {
+      const int t = base + lane;
+      const int32_t j = c0 + t;
+      const bool pred = t < len && j != i && is_candidate(pi, X[j], margin);
+      const unsigned long long m = __ballot(pred);
+      const int pos = written + __popcll(m & ((1ull << lane) - 1ull));
+      if (pred && pos < kRowMax) d.scr[(int64_t)i * kRowMax + pos] = j;
+      written += __popcll(m);
+      owned += __popcll(__ballot(pred && j > i));
     }
-    const unsigned long long m = __ballot(pred);
-    const int pos = written + __popcll(m & ((1ull << lane) - 1ull));
-    if (pred && pos < kRowMax) d.scr[(int64_t)i * kRowMax + pos] = j;
-    written += __popcll(m);
-    owned += __popcll(__ballot(pred && j > i));
   }
 }
 
@@ -177,7 +175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     // crowded neighbourhood: count every home row from global memory
     for (int32_t i = h0 + wv; i < h1; i += 4) {
       int written = 0, owned = 0;
-      search_row_global(d, X, i, srs, srl, total, margin, lane, written, owned);
+      search_row_global(d, X, i, srs, srl, margin, lane, written, owned);
       if (lane == 0) {
         d.ncnt[i] = written;
         d.ocnt[i] = owned;
@@ -257,7 +255,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
       written = __popcll(m);
       owned = __popcll(__ballot(pred && j > i));
     } else {
-      search_row_global(d, X, i, srs, srl, total, margin, lane, written, owned);
+      search_row_global(d, X, i, srs, srl, margin, lane, written, owned);
     }
     if (lane == 0) {
       d.ncnt[i] = written;
@@ -266,6 +264,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     }
   }
 }
+
+__global__ void k_totals(DevState d) {
+  if (threadIdx.x == 0) {
+    d.totals[0] = d.nrow[d.n];
+    d.totals[1] = d.hrow[d.n];
+    d.totals[2] = d.wrow[d.n];
+    d.totals[3] = *d.novf;
+  }
+}
+void launch_totals(DevState& d, hipStream_t s) { hipLaunchKernelGGL(k_totals, dim3(1), dim3(64), 0, s, d); }
 
 void launch_nbr_search(DevState& d, hipStream_t s) {
   hipLaunchKernelGGL(k_nbr_search, dim3((unsigned)d.nbins_total), dim3(256), 0, s, d);
@@ -285,31 +293,28 @@ __global__ __launch_bounds__(64) void k_nbr_fill_overflow(DevState d) {
   const int lane = threadIdx.x;
   if (lane < 27) cell_range(d, c, cx, cy, cz, lane, srs[lane], srl[lane]);
   __syncthreads();
-  int total = 0;
-  for (int k = 0; k < 27; ++k) total += srl[k];
   const int32_t row = d.nrow[i], hbase = d.hrow[i];
   const int pre_n = d.ncnt[i] - d.ocnt[i];
   int written = 0;
-  for (int base = 0; base < total; base += 64) {
-    const int t = base + lane;
-    bool pred = false;
-    int32_t j = -1;
-    if (t < total) {
-      j = cand_index(srs, srl, t);
-      pred = j != i && is_candidate(pi, X[j], c.margin);
-    }
-    const unsigned long long m = __ballot(pred);
-    if (pred) {
-      const int pos = written + __popcll(m & ((1ull << lane) - 1ull));
-      d.nbr[row + pos] = j;
-      if (j > i) {
-        const int slot = hbase + (pos - pre_n);
-        d.nslot[row + pos] = slot;
-        d.sown[slot] = i;
-        d.spart[slot] = j;
+  for (int k = 0; k < 27; ++k) {
+    const int32_t c0 = srs[k], len = srl[k];
+    for (int base = 0; base < len; base += 64) {
+      const int t = base + lane;
+      const int32_t j = c0 + t;
+      const bool pred = t < len && j != i && is_candidate(pi, X[j], c.margin);
+      const unsigned long long m = __ballot(pred);
+      if (pred) {
+        const int pos = written + __popcll(m & ((1ull << lane) - 1ull));
+        d.nbr[row + pos] = j;
+        if (j > i) {
+          const int slot = hbase + (pos - pre_n);
+          d.nslot[row + pos] = slot;
+          d.sown[slot] = i;
+          d.spart[slot] = j;
+        }
       }
+      written += __popcll(m);
     }
-    written += __popcll(m);
   }
 }
 
@@ -357,14 +362,13 @@ __global__ __launch_bounds__(256) void k_nbr_copy(DevState d) {
   }
 }
 
-// mirror entries of the overflow rows (after every owner entry is final)
-__global__ void k_nbr_mirror_overflow(DevState d, int novf) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= novf) return;
-  const int32_t i = d.ovf[q];
+// mirror entries of the overflow rows (after every owner entry is final):
+// one wavefront per row, one binary search per lane
+__global__ __launch_bounds__(64) void k_nbr_mirror_overflow(DevState d) {
+  const int32_t i = d.ovf[blockIdx.x];
   const int32_t r0 = d.nrow[i];
   const int32_t nmir = d.ncnt[i] - d.ocnt[i];
-  for (int32_t e = r0; e < r0 + nmir; ++e) {
+  for (int32_t e = r0 + (int32_t)threadIdx.x; e < r0 + nmir; e += 64) {
     const int32_t j = d.nbr[e];
     int32_t lo = d.nrow[j], hi = d.nrow[j + 1];
     while (lo < hi) {
@@ -378,7 +382,7 @@ __global__ void k_nbr_mirror_overflow(DevState d, int novf) {
 void launch_nbr_fill(DevState& d, int novf, hipStream_t s) {
   if (novf > 0) hipLaunchKernelGGL(k_nbr_fill_overflow, dim3(novf), dim3(64), 0, s, d);
   hipLaunchKernelGGL(k_nbr_copy, dim3(nblk(d.n * 8)), dim3(kBlock), 0, s, d);
-  if (novf > 0) hipLaunchKernelGGL(k_nbr_mirror_overflow, dim3(nblk(novf)), dim3(kBlock), 0, s, d, novf);
+  if (novf > 0) hipLaunchKernelGGL(k_nbr_mirror_overflow, dim3(novf), dim3(64), 0, s, d);
 }
 
 // ---------------------------------------------------------------------------

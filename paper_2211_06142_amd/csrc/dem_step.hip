@@ -85,7 +85,7 @@ template <typename R> void launch_prologue(DevState& d, StepArgs a, hipStream_t 
 template void launch_prologue<double>(DevState&, StepArgs, hipStream_t);
 template void launch_prologue<float>(DevState&, StepArgs, hipStream_t);
 
-// Lanes per particle: a group of G lanes (4, 8 or 16, chosen per context)
+// Lanes per particle: a group of G lanes (1, 2, 4, 8 or 16, chosen per context)
 // shares one particle's row; lane s evaluates entries s, s + G, ... and the
 // group sums its partial forces
 // with a fixed xor butterfly (every lane ends with the bit-identical total).
@@ -243,7 +243,11 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
 }
 
 template <typename R> void launch_step(DevState& d, StepArgs a, hipStream_t s) {
-  if (d.group == 4)
+  if (d.group == 1)
+    hipLaunchKernelGGL((k_step<R, 1>), dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, a);
+  else if (d.group == 2)
+    hipLaunchKernelGGL((k_step<R, 2>), dim3(nblk(d.n * 2)), dim3(kBlock), 0, s, d.self, a);
+  else if (d.group == 4)
     hipLaunchKernelGGL((k_step<R, 4>), dim3(nblk(d.n * 4)), dim3(kBlock), 0, s, d.self, a);
   else if (d.group == 16)
     hipLaunchKernelGGL((k_step<R, 16>), dim3(nblk(d.n * 16)), dim3(kBlock), 0, s, d.self, a);

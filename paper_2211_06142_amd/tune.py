@@ -24,7 +24,7 @@ def _time_steps(sim, steps):
     return e0.elapsed_time(e1)
 
 
-def tune(make_sim, skins, lanes=(4, 8, 16), warmup=40, steps=200, log=None):
+def tune(make_sim, skins, lanes=(1, 2, 4, 8), warmup=40, steps=200, log=None):
     """make_sim(skin) -> a fresh dem.Simulation with that skin (metres).
     Returns (best, table): best = dict(skin, lanes, ms_per_step), table = all
     trials as (skin, lanes, ms_per_step, rebuilds)."""
