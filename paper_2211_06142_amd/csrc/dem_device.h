@@ -33,6 +33,17 @@ template <typename R> __device__ inline R fsqrt_(R x);
 template <> __device__ inline double fsqrt_<double>(double x) { return sqrt(x); }
 template <> __device__ inline float fsqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Workgroups are dealt to the 8 XCDs of the chip in turn, each with its own L2.
+// Remapping gives every XCD one contiguous run of logical blocks, so blocks that
+// gather each other's (spatially sorted) particles share an L2.  A bijection on
+// [0, nb) for any nb.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  constexpr int kXcd = 8;
+  const int64_t q = nb / kXcd, r = nb % kXcd;
+  const int64_t x = b % kXcd, k = b / kXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
 __device__ inline int bin_coord(double x, double lo, double h, int n) {
   double q = floor((x - lo) / h);
   if (!(q >= 0.0)) return 0;   // also a NaN coordinate

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   const DevState& d = *dp;
   if (*d.abort_step <= a.step) return;
   const int sub = threadIdx.x & (kGroup - 1);
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+  const int64_t i = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / kGroup;
   if (i >= d.n) return;   // whole group
   const int in = a.in, out = a.out;
   const double4* X = d.xr[in];
