@@ -33,6 +33,27 @@ template <typename R> __device__ inline R fsqrt_(R x);
 template <> __device__ inline double fsqrt_<double>(double x) { return sqrt(x); }
 template <> __device__ inline float fsqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Global-address-space views of the state arrays.  The step-window kernels
+// read the state struct through a pointer, so the compiler cannot tell where
+// the array pointers inside point; without these views every access is a flat
+// access with a full 64-bit address per lane.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ inline gptr<T> G(T* p) { return (gptr<T>)p; }
+// Loads and stores of the HIP vector types through such views go through the
+// compiler's own vector types (whole-vector accesses, no constructors).
+typedef double gd4 __attribute__((ext_vector_type(4)));
+typedef float gf4 __attribute__((ext_vector_type(4)));
+__device__ inline double4 gld(gptr<const double4> p) {
+  const gd4 t = *(gptr<const gd4>)p;
+  return make_double4(t.x, t.y, t.z, t.w);
+}
+__device__ inline float4 gld(gptr<const float4> p) {
+  const gf4 t = *(gptr<const gf4>)p;
+  return make_float4(t.x, t.y, t.z, t.w);
+}
+__device__ inline void gst(gptr<double4> p, const double4& v) { *(gptr<gd4>)p = gd4{v.x, v.y, v.z, v.w}; }
+__device__ inline void gst(gptr<float4> p, const float4& v) { *(gptr<gf4>)p = gf4{v.x, v.y, v.z, v.w}; }
+
 // Workgroups are dealt to the 8 XCDs of the chip in turn, each with its own L2.
 // Remapping gives every XCD one contiguous run of logical blocks, so blocks that
 // gather each other's (spatially sorted) particles share an L2.  A bijection on

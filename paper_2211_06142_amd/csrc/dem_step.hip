@@ -26,22 +26,22 @@ __device__ inline void finish_drift(const DevState& d, const SampleConst& c, int
     atomicOr(d.status, (int)kStTooFast);
     atomicOr(d.abort, 1);
   }
-  d.xr[out][i] = p;
-  d.vel[out][i] = v;
-  ((R4<R>*)d.omg[out])[i] = w;
+  gst(G(d.xr[out]) + i, p);
+  gst(G(d.vel[out]) + i, v);
+  gst(G((R4<R>*)d.omg[out]) + i, w);
   uint8_t alive = 1;
   if (c.outlet_kind == DEM_OUTLET_CAVITY) {
     double ex = p.x - c.outlet[0], ey = p.y - c.outlet[1];
     double rc = c.outlet[2];
     if (ex * ex + ey * ey < rc * rc) {
       alive = 0;
-      ((R4<R>*)d.frc)[i] = mk4<R>(0, 0, 0, 0);
-      ((R4<R>*)d.trq)[i] = mk4<R>(0, 0, 0, 0);
+      gst(G((R4<R>*)d.frc) + i, mk4<R>(0, 0, 0, 0));
+      gst(G((R4<R>*)d.trq) + i, mk4<R>(0, 0, 0, 0));
     }
   }
-  d.alive[out][i] = alive;
+  G(d.alive[out])[i] = alive;
   if (alive) {
-    double4 q = d.xref[i];
+    double4 q = gld(G((const double4*)d.xref) + i);
     double ux = p.x - q.x, uy = p.y - q.y, uz = p.z - q.z;
     if ((ux * ux + uy * uy) + uz * uz > hs * hs) {
       atomicOr(d.abort, 1);
@@ -108,57 +108,60 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   const int64_t i = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / kGroup;
   if (i >= d.n) return;   // whole group
   const int in = a.in, out = a.out;
-  const double4* X = d.xr[in];
-  const double4* V = d.vel[in];
-  const R4<R>* W = (const R4<R>*)d.omg[in];
-  const uint8_t* AL = d.alive[in];
-  const double4 pi = X[i];
-  double4 v = V[i];
-  R4<R> w = W[i];
+  const auto X = G((const double4*)d.xr[in]);
+  const auto V = G((const double4*)d.vel[in]);
+  const auto W = G((const R4<R>*)d.omg[in]);
+  const auto AL = G((const uint8_t*)d.alive[in]);
+  const double4 pi = gld(X + i);
+  double4 v = gld(V + i);
+  R4<R> w = gld(W + i);
   if (!AL[i]) {           // whole group
     if (sub == 0) {
-      d.xr[out][i] = pi;
-      d.vel[out][i] = v;
-      ((R4<R>*)d.omg[out])[i] = w;
-      d.alive[out][i] = 0;
+      gst(G(d.xr[out]) + i, pi);
+      gst(G(d.vel[out]) + i, v);
+      gst(G((R4<R>*)d.omg[out]) + i, w);
+      G(d.alive[out])[i] = 0;
     }
     return;
   }
-  const int s = d.sample[i];
+  const int s = G((const int32_t*)d.sample)[i];
   const SampleConst& c = d.sc[s];
-  const R4<R>* Hin = (const R4<R>*)d.hdt[in];
-  R4<R>* Hout = (R4<R>*)d.hdt[out];
-  const uint8_t* Fin = d.pfl[in];
-  uint8_t* Fout = d.pfl[out];
+  const auto Hin = G((const R4<R>*)d.hdt[in]);
+  const auto Hout = G((R4<R>*)d.hdt[out]);
+  const auto Fin = G((const uint8_t*)d.pfl[in]);
+  const auto Fout = G((uint8_t*)d.pfl[out]);
+  const auto NBR = G((const int32_t*)d.nbr);
+  const auto NSL = G((const int32_t*)d.nslot);
+  const auto CC = G((const double*)d.ccoh);
   const bool rolling = d.rolling != 0;
   const R r = (R)pi.w;
   R F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  const double ci = d.ccoh ? d.ccoh[i] : 1.0;
-  const int32_t e1 = d.nrow[i + 1];
-  for (int32_t e = d.nrow[i] + sub; e < e1; e += kGroup) {
-    const int32_t j = d.nbr[e];
-    const int32_t p = d.nslot[e];
+  const double ci = d.ccoh ? CC[i] : 1.0;
+  const int32_t e1 = G((const int32_t*)d.nrow)[i + 1];
+  for (int32_t e = G((const int32_t*)d.nrow)[i] + sub; e < e1; e += kGroup) {
+    const int32_t j = NBR[e];
+    const int32_t p = NSL[e];
     const bool own = j > (int32_t)i;
     if (!AL[j]) {
       if (own) {
-        Hout[p] = mk4<R>(0, 0, 0, 0);
+        gst(Hout + p, mk4<R>(0, 0, 0, 0));
         Fout[p] = 0;
       }
       continue;
     }
-    const double4 pj = X[j];
-    const double4 vj = V[j];
-    const R4<R> wj = W[j];
+    const double4 pj = gld(X + j);
+    const double4 vj = gld(V + j);
+    const R4<R> wj = gld(W + j);
     double gam = c.gamma;
-    if (d.ccoh) gam = c.gamma * sqrt(ci * d.ccoh[j]);
+    if (d.ccoh) gam = c.gamma * sqrt(ci * CC[j]);
     PairOut<R> po;
     // canonical orientation: the owner (lower index) is body A
     const double4 PA = own ? pi : pj, PB = own ? pj : pi;
     const double4 VA = own ? v : vj, VB = own ? vj : v;
     const R4<R> WA = own ? w : wj, WB = own ? wj : w;
-    pair_eval<R>(c, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, Hin[p], Fin[p], po);
+    pair_eval<R>(c, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, gld(Hin + p), Fin[p], po);
     if (own) {
-      Hout[p] = po.h;
+      gst(Hout + p, po.h);
       Fout[p] = po.fl;
       if (po.broke) atomicAdd(&d.broken[s], 1ull);
     }
@@ -171,14 +174,16 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   }
   // walls: Hertz with R* = r and m* = m (rigid, static); entries private to i
   const double m = c.rho * (4.0 / 3.0) * M_PI * pi.w * pi.w * pi.w;
-  const int32_t w1 = d.wrow[i + 1];
-  for (int32_t e = d.wrow[i] + sub; e < w1; e += kGroup) {
-    R4<R> h4 = ((const R4<R>*)d.wdt)[e];
+  const auto WDT = G((R4<R>*)d.wdt);
+  const auto WFL = G((uint8_t*)d.wfl);
+  const int32_t w1 = G((const int32_t*)d.wrow)[i + 1];
+  for (int32_t e = G((const int32_t*)d.wrow)[i] + sub; e < w1; e += kGroup) {
+    R4<R> h4 = gld((gptr<const R4<R>>)(WDT + e));
     double sd, nw[3];
-    const Wall& wl = c.walls[d.wid[e]];
+    const Wall& wl = c.walls[G((const int32_t*)d.wid)[e]];
     if (!wall_geom(wl, pi.x, pi.y, pi.z, sd, nw) || !(sd < pi.w)) {
-      ((R4<R>*)d.wdt)[e] = mk4<R>(0, 0, 0, 0);
-      d.wfl[e] = 0;
+      gst(WDT + e, mk4<R>(0, 0, 0, 0));
+      WFL[e] = 0;
       continue;
     }
     const R delta = (R)(pi.w - sd);
@@ -194,8 +199,8 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
     T[0] += r * o.c[0] + o.Tr[0];
     T[1] += r * o.c[1] + o.Tr[1];
     T[2] += r * o.c[2] + o.Tr[2];
-    ((R4<R>*)d.wdt)[e] = mk4<R>(h[0], h[1], h[2], (R)0);
-    d.wfl[e] = 2;
+    gst(WDT + e, mk4<R>(h[0], h[1], h[2], (R)0));
+    WFL[e] = 2;
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   F[1] += (R)(m * c.g[1]);
   F[2] += (R)(m * c.g[2]);
   if (c.fluid_on) {
-    const R4<R> fd = ((const R4<R>*)d.fdr)[i];
+    const R4<R> fd = gld(G((const R4<R>*)d.fdr) + i);
     F[0] += fd.x; F[1] += fd.y; F[2] += fd.z;
   }
   if (!isfinite(F[0] + F[1] + F[2] + T[0] + T[1] + T[2])) {
@@ -224,12 +229,12 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   w.y += hdtR * T[1] * w.w;
   w.z += hdtR * T[2] * w.w;
   if (a.final_step) {
-    d.xr[out][i] = pi;
-    d.vel[out][i] = v;
-    ((R4<R>*)d.omg[out])[i] = w;
-    d.alive[out][i] = 1;
-    ((R4<R>*)d.frc)[i] = mk4<R>(F[0], F[1], F[2], (R)0);
-    ((R4<R>*)d.trq)[i] = mk4<R>(T[0], T[1], T[2], (R)0);
+    gst(G(d.xr[out]) + i, pi);
+    gst(G(d.vel[out]) + i, v);
+    gst(G((R4<R>*)d.omg[out]) + i, w);
+    G(d.alive[out])[i] = 1;
+    gst(G((R4<R>*)d.frc) + i, mk4<R>(F[0], F[1], F[2], (R)0));
+    gst(G((R4<R>*)d.trq) + i, mk4<R>(T[0], T[1], T[2], (R)0));
     return;
   }
   // first half kick and drift of the next step
