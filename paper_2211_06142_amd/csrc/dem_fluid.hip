@@ -66,32 +66,30 @@ __device__ inline double corner_w(const double4& fr, int kx, int ky, int kz) {
 // corner partials of every bucket: kind 0 volume (8 per bucket), kind 1 drag (24 per bucket)
 template <int kKind>
 __global__ void k_fluid_partials(const DevState* __restrict__ dp) {
+  // one thread per (bucket, output): 8 corner volumes, or 8 corners x 3 drag
+  // components; each output sums the bucket's members in bucket order
   const DevState& d = *dp;
   if (*d.abort) return;
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= d.ndual) return;
-  double acc[kKind == 0 ? 8 : 24];
-#pragma unroll
-  for (int k = 0; k < (kKind == 0 ? 8 : 24); ++k) acc[k] = 0.0;
+  constexpr int m = kKind == 0 ? 8 : 24;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.ndual * m) return;
+  const int64_t b = t / m;
+  const int k = (int)(t - b * m);
+  const int corner = kKind == 0 ? k : k / 3, comp = kKind == 0 ? 0 : k % 3;
+  const int cx = corner & 1, cy = (corner >> 1) & 1, cz = corner >> 2;
+  double acc = 0.0;
   for (int32_t q = d.doff[b]; q < d.doff[b + 1]; ++q) {
     const int32_t i = d.dmem[q];
     const double4 fr = d.dfr[i];
-    double4 fp = make_double4(0, 0, 0, 0);
-    if (kKind == 1) fp = d.fpart[i];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double w = corner_w(fr, k & 1, (k >> 1) & 1, k >> 2);
-      if (kKind == 0) {
-        acc[k] += w * fr.w;
-      } else {
-        acc[3 * k] += w * fp.x;
-        acc[3 * k + 1] += w * fp.y;
-        acc[3 * k + 2] += w * fp.z;
-      }
+    const double w = corner_w(fr, cx, cy, cz);
+    if (kKind == 0) {
+      acc += w * fr.w;
+    } else {
+      const double4 fp = d.fpart[i];
+      acc += w * (comp == 0 ? fp.x : comp == 1 ? fp.y : fp.z);
     }
   }
-  const int m = kKind == 0 ? 8 : 24;
-  for (int k = 0; k < m; ++k) d.dpart[m * b + k] = acc[k];
+  d.dpart[t] = acc;
 }
 
 // per fluid cell: fixed-order sum of the corner partials of the adjacent buckets
@@ -270,14 +268,14 @@ template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
   hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
   launch_bucket_sort((const uint32_t*)d.dkey, d.n, d.ndual, nullptr, d.dcnt, d.doff, d.dfill, d.dmem_tmp,
                      d.dmem, d.scan_tmp, d.dual_sink, d.abort, s);
-  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d.self);
+  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
   if (d.closure_on) {
     hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
     launch_closure_infer(d, s);
   }
   hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
-  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual)), dim3(kBlock), 0, s, d.self);
+  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual * 24)), dim3(kBlock), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
 }
 template void launch_fluid<double>(DevState&, int, hipStream_t);
