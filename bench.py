@@ -101,6 +101,67 @@ def cpu_baseline(w, budget_s=15.0):
                       % (w["name"], len(w["r"]), steps, w["fluid"]["couple_every"], el, t_init)}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+MLP_FLOP_FWD = 2 * (6 * 64 + 64 * 64 + 64 * 64 + 64 * 2)     # per sample
+
+
+def time_events(torch, stream, fn, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def closure_block(w, torch):
+    """Network forward and training-step throughput (BF16 MFMA, FP32
+    accumulation) at a batch of the workload's particle count, and the cost
+    of the closure inside the coupling (features + inference for every
+    particle), from instrumented coupling evaluations with and without it."""
+    from paper_2211_06142_amd import dem
+    n = len(w["r"])
+    rng = np.random.default_rng(7)
+    p0 = (rng.normal(0, 0.1, dem.MLP_NPARAMS)).astype(np.float32)
+    net = dem.Mlp(p0)
+    x = torch.as_tensor(rng.normal(size=(n, 6)).astype(np.float32), device="cuda")
+    t = torch.as_tensor(rng.normal(0, 0.3, size=(n, 2)).astype(np.float32), device="cuda")
+    y = torch.zeros((n, 2), dtype=torch.float32, device="cuda")
+    stream = net.stream
+    fwd = lambda: dem.dem_mlp_forward(net.h, x.data_ptr(), y.data_ptr(), n)
+    fwd()
+    ms_f = time_events(torch, stream, fwd, 50)
+    trn = lambda: dem.dem_mlp_train_step(net.h, x.data_ptr(), t.data_ptr(), n, 1e-4)
+    trn()
+    ms_t = time_events(torch, stream, trn, 10)
+    flop_f = MLP_FLOP_FWD * n
+    out = {"batch": n, "forward_us": ms_f * 1e3, "forward_tflops": flop_f / (ms_f * 1e-3) / 1e12,
+           "train_step_us": ms_t * 1e3, "train_tflops": 3 * flop_f / (ms_t * 1e-3) / 1e12,
+           "mfma_peak_tflops": MFMA_BF16_PEAK_TFLOPS}
+    # closure inside the coupling: instrumented coupling class with and without
+    norm = np.array([0.6, 0.05, 2.0, 1.0, 0.01, 4.0, 0.2, 0.05, 2.0, 1.0, 0.02, 3.0])
+    per = {}
+    for on in (False, True):
+        sim = build_sim([w], SKIN_FACTOR, LANES, 0)
+        if on:
+            sim.set_closure(net, norm)
+        sim.step(20)
+        sim.profile(1)
+        sim.step(200)
+        prof = sim.read_profile()
+        sim.profile(0)
+        per[on] = prof["fluid"][0] * 1e3 / max(prof["fluid"][1], 1)
+        sim.close()
+    out["coupling_us_without"] = per[False]
+    out["coupling_us_with"] = per[True]
+    out["closure_us_per_evaluation"] = per[True] - per[False]
+    net.close()
+    return out
+
+
 def build_sim(ws, skin_factor, lanes, graphs):
     from paper_2211_06142_amd import dem
     rmin = min(float(np.min(w["r"])) for w in ws)
@@ -131,6 +192,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=LANES, help="lanes per particle of the step kernel")
     ap.add_argument("--graphs", type=int, default=0, help="replay recorded step windows (timing off)")
     ap.add_argument("--tune", action="store_true", help="autotune skin and lanes before the timed run")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure measurement (network "
+                    "throughput on the matrix cores, cost inside the coupling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU sharding of the DEM step is a "
@@ -216,7 +279,8 @@ def main():
         desc = ("%s: %d polydisperse spheres (lognormal d, median 0.15 mm), hollow cylinder R 12 mm / cavity "
                 "2 mm, 48x48x24 fluid grid, radial Darcy inflow, dt 1e-7 s, coupling every %d steps"
                 % (w["name"], len(w["r"]), w["fluid"]["couple_every"]))
-        metric = "particle-steps/s at 200k particles, 1 GPU"
+        metric = ("particle-steps/s at 200k particles, 1 GPU" if args.workload == "c1"
+                  else "particle-steps/s at %d particles, 1 GPU" % len(w["r"]))
     out = {
         "metric": metric,
         "value": value,
@@ -241,6 +305,8 @@ def main():
     }
     if tuned:
         out["config"]["tuned"] = tuned
+    if not args.no_closure and len(ws) == 1:
+        out["closure"] = closure_block(w, torch)
     sim.close()
     if not args.no_cpu and args.workload != "c3":
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
