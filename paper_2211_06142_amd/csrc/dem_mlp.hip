@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const short* wb, const floa
 
 // forward of a training batch: records activations, the output gradient of
 // L = mean (y - t)^2 and the squared error per sample
-__global__ __launch_bounds__(256) void k_mlp_forward_train(const short* wb, const float* pf, const float* x,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_forward_train(const short* wb, const float* pf, const float* x,
                                                            const float* tgt, int64_t B, MlpTrainBuf tb) {
   const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
   const int64_t nt = (B + 15) / 16;
@@ -236,62 +236,85 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const short* wb, int64_t B
   }
 }
 
-// Weight and bias gradients of one chunk of samples: dW[k][m] = sum_s H[s][k] G[s][m]
-// as MFMA products with the samples as the contraction; a bias gradient uses
-// an all-ones A operand.  Jobs: (layer, input tile or bias, output tile).
-struct GradJob {
-  int layer, kt, mt;   // kt = -1: bias
-};
-__device__ inline GradJob grad_job(int j) {
-  // layer 0: 1 x 4 weight tiles + 4 bias; layers 1, 2: 16 + 4; layer 3: 4 + 1
-  if (j < 8) return j < 4 ? GradJob{0, 0, j} : GradJob{0, -1, j - 4};
-  j -= 8;
-  if (j < 40) {
-    int l = 1 + j / 20, u = j % 20;
-    return u < 16 ? GradJob{l, u / 4, u % 4} : GradJob{l, -1, u - 16};
-  }
-  j -= 40;
-  return j < 4 ? GradJob{3, j, 0} : GradJob{3, -1, 0};
-}
-constexpr int kGradJobs = 53;
+// Weight and bias gradients of one chunk of samples for one layer:
+// dW[k][m] = sum_s H[s][k] G[s][m] as MFMA products with the samples as the
+// contraction, a bias gradient with an all-ones A operand.  The block stages
+// 64-sample tiles of H and G in LDS with coalesced loads; each wavefront keeps
+// the accumulators of its output tiles (at most 5) in registers.
+constexpr int kSub = 64;   // samples per LDS tile
 
 __global__ __launch_bounds__(256) void k_mlp_wgrad(int64_t B, MlpTrainBuf tb, float* part) {
+  __shared__ short Hs[kSub][64];
+  __shared__ short Gs[kSub][64];
   const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15, wv = threadIdx.x >> 6;
-  const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+  const int chunk = blockIdx.x >> 2, layer = blockIdx.x & 3;
+  const int64_t c0 = (int64_t)chunk * kChunk;
   const int64_t c1 = c0 + kChunk < B ? c0 + kChunk : B;
-  float* out = part + (int64_t)blockIdx.x * kNParams;
-  for (int j = wv; j < kGradJobs; j += 4) {
-    const GradJob jb = grad_job(j);
-    const int K = jb.layer == 0 ? 6 : 64, M = jb.layer == 3 ? 2 : 64;
-    const int ldh = jb.layer == 0 ? 16 : 64;
-    const short* H = jb.layer == 0 ? tb.h0 : tb.h[jb.layer - 1];
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t s0 = c0; s0 < c1; s0 += 16) {
-      bf16x4 a, b;
+  const int K = layer == 0 ? 6 : 64, M = layer == 3 ? 2 : 64;
+  const int KT = layer == 0 ? 1 : 4, MT = layer == 3 ? 1 : 4;       // input and output tiles
+  const int njobs = KT * MT + MT;                                   // weight tiles, then bias tiles
+  const int ldh = layer == 0 ? 16 : 64;
+  const short* H = layer == 0 ? tb.h0 : tb.h[layer - 1];
+  f32x4 acc[5];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t s = s0 + 4 * q + i;
-        const bool ok = s < c1;
-        const int k = 16 * (jb.kt < 0 ? 0 : jb.kt) + r;
-        a[i] = jb.kt < 0 ? (short)0x3F80 : ((ok && k < K) ? H[s * ldh + k] : (short)0);   // 0x3F80 = 1.0
-        const int m = 16 * jb.mt + r;
-        if (jb.layer == 3) b[i] = (ok && m < 2) ? f2bf(tb.g4[2 * s + m]) : (short)0;
-        else b[i] = ok ? tb.g[jb.layer][s * 64 + m] : (short)0;
+  for (int u = 0; u < 5; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t s0 = c0; s0 < c1; s0 += kSub) {
+    // stage: thread t loads 16 consecutive features of one sample row
+    {
+      const int row = threadIdx.x >> 2, part16 = (threadIdx.x & 3) * 16;
+      const int64_t s = s0 + row;
+      const bool ok = s < c1;
+      for (int k = 0; k < 16; ++k) {
+        const int col = part16 + k;
+        Hs[row][col] = (ok && col < ldh) ? H[s * ldh + col] : (short)0;
+        short g = 0;
+        if (ok) {
+          if (layer == 3) g = col < 2 ? f2bf(tb.g4[2 * s + col]) : (short)0;
+          else g = tb.g[layer][s * 64 + col];
+        }
+        Gs[row][col] = g;
       }
-      acc = mfma16(a, b, acc);
     }
-    // D[row][col]: row 4q + i of the tile, column r
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const int j = wv + 4 * u;
+      if (j >= njobs) break;
+      const bool bias = j >= KT * MT;
+      const int kt = bias ? 0 : j / MT, mt = bias ? j - KT * MT : j % MT;
+#pragma unroll
+      for (int t = 0; t < kSub / 16; ++t) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int sr = 16 * t + 4 * q + i;
+          a[i] = bias ? (short)0x3F80 : Hs[sr][16 * kt + r];   // 0x3F80 = 1.0
+          b[i] = Gs[sr][16 * mt + r];
+        }
+        acc[u] = mfma16(a, b, acc[u]);
+      }
+    }
+    __syncthreads();
+  }
+  // D[row][col]: row 4q + i of the tile, column r
+  float* out = part + (int64_t)chunk * kNParams;
+  const int offW = layer == 0 ? kW1 : layer == 1 ? kW2 : layer == 2 ? kW3 : kW4;
+  const int offB = layer == 0 ? kB1 : layer == 1 ? kB2 : layer == 2 ? kB3 : kB4;
+#pragma unroll
+  for (int u = 0; u < 5; ++u) {
+    const int j = wv + 4 * u;
+    if (j >= njobs) break;
+    const bool bias = j >= KT * MT;
+    const int kt = bias ? 0 : j / MT, mt = bias ? j - KT * MT : j % MT;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = 4 * q + i, m = 16 * jb.mt + r;
+      const int row = 4 * q + i, m = 16 * mt + r;
       if (m >= M) continue;
-      const int offW = jb.layer == 0 ? kW1 : jb.layer == 1 ? kW2 : jb.layer == 2 ? kW3 : kW4;
-      const int offB = jb.layer == 0 ? kB1 : jb.layer == 1 ? kB2 : jb.layer == 2 ? kB3 : kB4;
-      if (jb.kt < 0) {
-        if (row == 0) out[offB + m] = acc[i];
+      if (bias) {
+        if (row == 0) out[offB + m] = acc[u][i];
       } else {
-        const int k = 16 * jb.kt + row;
-        if (k < K) out[offW + k * M + m] = acc[i];
+        const int k = 16 * kt + row;
+        if (k < K) out[offW + k * M + m] = acc[u][i];
       }
     }
   }
@@ -317,8 +340,17 @@ __global__ void k_mlp_reduce_adam(const float* part, int nchunk, float* grad, fl
                                   short* wb, int do_adam, float lr, float bc1, float bc2) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= kNParams) return;
+  // chunk partials in order; eight loads in flight per round
   float g = 0.f;
-  for (int c = 0; c < nchunk; ++c) g += part[(int64_t)c * kNParams + k];
+  int c = 0;
+  for (; c + 8 <= nchunk; c += 8) {
+    float v8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v8[u] = part[(int64_t)(c + u) * kNParams + k];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g += v8[u];
+  }
+  for (; c < nchunk; ++c) g += part[(int64_t)c * kNParams + k];
   grad[k] = g;
   if (!do_adam) return;
   const float mk = 0.9f * m[k] + 0.1f * g;
@@ -447,7 +479,7 @@ dem_status train_pass(dem_mlp* n, const float* x, const float* t, int64_t B, int
   hipLaunchKernelGGL(k_mlp_forward_train, dim3(g), dim3(256), 0, s, n->wb, n->p, x, t, B, n->tb);
   hipLaunchKernelGGL(k_mlp_backward, dim3(g), dim3(256), 0, s, n->wb, B, n->tb);
   int nch = (int)((B + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nch), dim3(256), 0, s, B, n->tb, n->part);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(4 * nch), dim3(256), 0, s, B, n->tb, n->part);
   hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, n->tb.err, B, n->loss);
   float bc1 = 1.f, bc2 = 1.f;
   if (adam) {
