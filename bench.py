@@ -27,10 +27,15 @@ SKIN_FACTOR = 0.4   # neighbour skin / smallest radius (the library default)
 LANES = 4           # lanes per particle of the step kernel (the library default)
 
 
-def source_hash():
+KERNEL_SOURCES = {"step": ["dem_step.hip", "dem_device.h", "dem_internal.h"]}
+
+
+def source_hash(files=None):
+    """SHA-256 prefix of the kernel sources (a class's own files, or all)."""
+    d = os.path.join(ROOT, "paper_2211_06142_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2211_06142_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2211_06142_amd", "csrc", f), "rb") as fh:
+    for f in sorted(files if files else os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -70,7 +75,7 @@ def load_traffic(kernel, workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash(d.get("sources")):
         return None
     return d.get("traffic_bytes_per_launch")
 
