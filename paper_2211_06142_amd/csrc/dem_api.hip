@@ -177,6 +177,13 @@ void derive(const dem_params& p, const double* x, const double* r, const uint8_t
   c.mu_roll = p.mu_roll;
   c.rho = p.rho;
   c.k_lin = p.k_lin;
+  c.f_Es = (float)c.Es;
+  c.f_Gs = (float)c.Gs;
+  c.f_beta = (float)c.beta;
+  c.f_cdamp = (float)c.cdamp;
+  c.f_mu = (float)c.mu;
+  c.f_mu_roll = (float)c.mu_roll;
+  c.f_k_lin = (float)c.k_lin;
   c.kcg = p.k;
   c.k3 = p.k * p.k * p.k;
   c.normal_model = p.normal_model;

@@ -54,6 +54,23 @@ __device__ inline float4 gld(gptr<const float4> p) {
 __device__ inline void gst(gptr<double4> p, const double4& v) { *(gptr<gd4>)p = gd4{v.x, v.y, v.z, v.w}; }
 __device__ inline void gst(gptr<float4> p, const float4& v) { *(gptr<gf4>)p = gf4{v.x, v.y, v.z, v.w}; }
 
+// The per-sample constants do not change while a kernel runs.  Reading them
+// through the constant address space lets the compiler use scalar loads for a
+// wave-uniform sample and hoist the loads out of loops that store.
+template <typename T> using cptr = __attribute__((address_space(4))) const T*;
+__device__ inline const SampleConst& sample_const(const SampleConst* sc, int s) {
+  return *(const SampleConst*)((cptr<SampleConst>)sc + s);
+}
+
+// Lane `lane`'s value as a scalar that the optimiser cannot identify with the
+// per-lane value it was read from: inside `if (x == readlane(x, l))` it would
+// otherwise substitute the per-lane x back and lose the scalar registers.
+__device__ inline int opaque_readlane(int v, int lane) {
+  int r;
+  asm volatile("v_readlane_b32 %0, %1, %2" : "=s"(r) : "v"(v), "s"(lane));
+  return r;
+}
+
 // Workgroups are dealt to the 8 XCDs of the chip in turn, each with its own L2.
 // Remapping gives every XCD one contiguous run of logical blocks, so blocks that
 // gather each other's (spatially sorted) particles share an L2.  A bijection on
@@ -120,6 +137,19 @@ __device__ inline void jkr_bonded(R delta, R Rs, R gam, R jkrK, R& a, R& Fel) {
   a = fsqrt_<R>(X * Rs) * b * b;
 }
 
+// Contact-law constants of one sample in the arithmetic type of the forces.
+template <typename R> struct LawK {
+  R Es, Gs, beta, cdamp, mu, mu_roll, k_lin;
+  bool linear;
+};
+template <typename R> __device__ inline LawK<R> law_k(const SampleConst& c);
+template <> __device__ inline LawK<double> law_k<double>(const SampleConst& c) {
+  return {c.Es, c.Gs, c.beta, c.cdamp, c.mu, c.mu_roll, c.k_lin, c.normal_model == DEM_NORMAL_LINEAR};
+}
+template <> __device__ inline LawK<float> law_k<float>(const SampleConst& c) {
+  return {c.f_Es, c.f_Gs, c.f_beta, c.f_cdamp, c.f_mu, c.f_mu_roll, c.f_k_lin, c.normal_model == DEM_NORMAL_LINEAR};
+}
+
 template <typename R> struct LawOut {
   R F[3], c[3], Tr[3];
 };
@@ -130,30 +160,30 @@ template <typename R> struct LawOut {
 // tangential elongation (in/out).  Output: force on the body, n x F_t (the
 // torque on each body is its radius times this), rolling torque on the body.
 template <typename R>
-__device__ inline void contact_law(const SampleConst& c, int bonded, R delta, R Rs, R ms, R gam, R jkrK,
+__device__ inline void contact_law(const LawK<R>& c, int bonded, R delta, R Rs, R ms, R gam, R jkrK,
                                    const R n[3], const R vrel[3], const R wrel[3], R hdt[3], R dt,
                                    bool rolling, LawOut<R>& o) {
   R a, Fel, kn, kt, etan, etat, L;
-  if (c.normal_model == DEM_NORMAL_LINEAR) {
-    kn = (R)c.k_lin;
+  if (c.linear) {
+    kn = c.k_lin;
     Fel = kn * delta;
     kt = ((R)2 / (R)7) * kn;
-    etan = (R)2 * (R)c.beta * fsqrt_<R>(kn * ms);
-    etat = (R)2 * (R)c.beta * fsqrt_<R>(kt * ms);
-    L = (R)c.mu * Fel;
+    etan = (R)2 * c.beta * fsqrt_<R>(kn * ms);
+    etat = (R)2 * c.beta * fsqrt_<R>(kt * ms);
+    L = c.mu * Fel;
   } else {
     if (bonded && gam > (R)0) {
       jkr_bonded<R>(delta, Rs, gam, jkrK, a, Fel);
-      L = (R)c.mu * (Fel + (R)2 * ((R)3 * (R)3.14159265358979323846 * gam * Rs));
+      L = c.mu * (Fel + (R)2 * ((R)3 * (R)3.14159265358979323846 * gam * Rs));
     } else {
       a = fsqrt_<R>(Rs * (delta > (R)0 ? delta : (R)0));
-      Fel = (R)4 * (R)c.Es * a * a * a * frcp_<R>((R)3 * Rs);
-      L = (R)c.mu * Fel;
+      Fel = (R)4 * c.Es * a * a * a * frcp_<R>((R)3 * Rs);
+      L = c.mu * Fel;
     }
-    kn = (R)2 * (R)c.Es * a;
-    kt = (R)8 * (R)c.Gs * a;
-    etan = (R)c.cdamp * fsqrt_<R>(kn * ms);
-    etat = (R)c.cdamp * fsqrt_<R>(kt * ms);
+    kn = (R)2 * c.Es * a;
+    kt = (R)8 * c.Gs * a;
+    etan = c.cdamp * fsqrt_<R>(kn * ms);
+    etat = c.cdamp * fsqrt_<R>(kt * ms);
   }
   R vn = (vrel[0] * n[0] + vrel[1] * n[1]) + vrel[2] * n[2];
   R vt[3] = {vrel[0] - vn * n[0], vrel[1] - vn * n[1], vrel[2] - vn * n[2]};
@@ -191,12 +221,12 @@ __device__ inline void contact_law(const SampleConst& c, int bonded, R delta, R 
   o.c[1] = n[2] * Ft[0] - n[0] * Ft[2];
   o.c[2] = n[0] * Ft[1] - n[1] * Ft[0];
   o.Tr[0] = o.Tr[1] = o.Tr[2] = (R)0;
-  if (rolling && c.mu_roll > 0.0) {
+  if (rolling && c.mu_roll > (R)0) {
     R wn = (wrel[0] * n[0] + wrel[1] * n[1]) + wrel[2] * n[2];
     R wr[3] = {wrel[0] - wn * n[0], wrel[1] - wn * n[1], wrel[2] - wn * n[2]};
     R wm = fsqrt_<R>((wr[0] * wr[0] + wr[1] * wr[1]) + wr[2] * wr[2]);
     if (wm > (R)0) {
-      R tm = (R)c.mu_roll * Rs * (Fel < (R)0 ? -Fel : Fel) * frcp_<R>(wm);
+      R tm = c.mu_roll * Rs * (Fel < (R)0 ? -Fel : Fel) * frcp_<R>(wm);
       o.Tr[0] = -tm * wr[0]; o.Tr[1] = -tm * wr[1]; o.Tr[2] = -tm * wr[2];
     }
   }
@@ -224,7 +254,7 @@ template <typename R> struct PairOut {
 };
 
 template <typename R>
-__device__ inline void pair_eval(const SampleConst& c, double dt, bool rolling, const double4& A, const double4& B,
+__device__ inline void pair_eval(const LawK<R>& c, double Es, double dt, bool rolling, const double4& A, const double4& B,
                                  const double4& VA, const double4& VB, const R4<R>& WA, const R4<R>& WB,
                                  double gam, R4<R> h4, uint8_t fl, PairOut<R>& out) {
   out.active = false;
@@ -234,7 +264,7 @@ __device__ inline void pair_eval(const SampleConst& c, double dt, bool rolling, 
   const double cs = A.w + B.w;
   const bool touching = d2 < cs * cs;
   const int bonded = fl & 1;
-  if (bonded && !touching && !bond_holds_apart(d2, cs, A.w * B.w / (A.w + B.w), gam, c.Es)) {
+  if (bonded && !touching && !bond_holds_apart(d2, cs, A.w * B.w / (A.w + B.w), gam, Es)) {
     out.broke = true;
     out.h = mk4<R>(0, 0, 0, 0);
     out.fl = 0;
@@ -273,7 +303,7 @@ __device__ inline void pair_eval(const SampleConst& c, double dt, bool rolling, 
   }
   R h[3] = {h4.x, h4.y, h4.z};
   const R gR = (R)gam;
-  const R jkrK = (R)3.14159265358979323846 * (R)3.14159265358979323846 * gR * gR * frcp_<R>((R)c.Es * (R)c.Es);
+  const R jkrK = (R)3.14159265358979323846 * (R)3.14159265358979323846 * gR * gR * frcp_<R>(c.Es * c.Es);
   contact_law<R>(c, bonded, delta, Rs, ms, gR, jkrK, n, vrel, wrel, h, (R)dt, rolling, out.o);
   out.h = mk4<R>(h[0], h[1], h[2], (R)0);
   out.fl = (uint8_t)(bonded | (touching ? 2 : 0));

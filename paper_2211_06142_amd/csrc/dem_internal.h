@@ -47,6 +47,8 @@ struct SampleConst {
   double Es, Gs, beta, cdamp;     // E*, G*, damping ratio, 2 sqrt(5/6) beta
   double gamma, mu, mu_roll, rho, k_lin;
   double kcg, k3;                 // drag rule f = k^3 f(d / k)
+  // the contact constants rounded to FP32 (the mixed-precision force path)
+  float f_Es, f_Gs, f_beta, f_cdamp, f_mu, f_mu_roll, f_k_lin;
   int normal_model;
   int fluid_on, voidfrac, u_superficial;
   double rho_f, mu_f, n_min;

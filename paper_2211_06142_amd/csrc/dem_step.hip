@@ -100,14 +100,13 @@ __device__ inline R group_sum(R v) {
 // recorded abort step (no rebuild: a large value) is written only by an
 // earlier launch or by the launch that finds it due for the NEXT step, so every
 // block of one launch takes the same decision.
+// Everything of one live particle after its own state has been read; `s` is
+// its sample, uniform over the wave.
 template <typename R, int kGroup>
-__global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, StepArgs a) {
-  const DevState& d = *dp;
-  if (*d.abort_step <= a.step) return;
-  const int sub = threadIdx.x & (kGroup - 1);
-  const int64_t i = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / kGroup;
-  if (i >= d.n) return;   // whole group
+__device__ __forceinline__ void particle_step(const DevState& d, const StepArgs& a, int64_t i, int sub, int s) {
   const int in = a.in, out = a.out;
+  const SampleConst& c = sample_const(d.sc, s);
+  const LawK<R> lk = law_k<R>(c);
   const auto X = G((const double4*)d.xr[in]);
   const auto V = G((const double4*)d.vel[in]);
   const auto W = G((const R4<R>*)d.omg[in]);
@@ -115,17 +114,6 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   const double4 pi = gld(X + i);
   double4 v = gld(V + i);
   R4<R> w = gld(W + i);
-  if (!AL[i]) {           // whole group
-    if (sub == 0) {
-      gst(G(d.xr[out]) + i, pi);
-      gst(G(d.vel[out]) + i, v);
-      gst(G((R4<R>*)d.omg[out]) + i, w);
-      G(d.alive[out])[i] = 0;
-    }
-    return;
-  }
-  const int s = G((const int32_t*)d.sample)[i];
-  const SampleConst& c = d.sc[s];
   const auto Hin = G((const R4<R>*)d.hdt[in]);
   const auto Hout = G((R4<R>*)d.hdt[out]);
   const auto Fin = G((const uint8_t*)d.pfl[in]);
@@ -159,7 +147,7 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
     const double4 PA = own ? pi : pj, PB = own ? pj : pi;
     const double4 VA = own ? v : vj, VB = own ? vj : v;
     const R4<R> WA = own ? w : wj, WB = own ? wj : w;
-    pair_eval<R>(c, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, gld(Hin + p), Fin[p], po);
+    pair_eval<R>(lk, c.Es, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, gld(Hin + p), Fin[p], po);
     if (own) {
       gst(Hout + p, po.h);
       Fout[p] = po.fl;
@@ -194,7 +182,7 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
     const R wrel[3] = {w.x, w.y, w.z};
     R h[3] = {h4.x, h4.y, h4.z};
     LawOut<R> o;
-    contact_law<R>(c, 0, delta, r, (R)m, (R)0, (R)0, n, vrel, wrel, h, (R)d.dt, true, o);
+    contact_law<R>(lk, 0, delta, r, (R)m, (R)0, (R)0, n, vrel, wrel, h, (R)d.dt, true, o);
     F[0] += o.F[0]; F[1] += o.F[1]; F[2] += o.F[2];
     T[0] += r * o.c[0] + o.Tr[0];
     T[1] += r * o.c[1] + o.Tr[1];
@@ -245,6 +233,41 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   w.y += hdtR * T[1] * w.w;
   w.z += hdtR * T[2] * w.w;
   finish_drift<R>(d, c, i, out, a.step + 1, pi, v, w);
+}
+
+template <typename R, int kGroup>
+__global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, StepArgs a) {
+  const DevState& d = *dp;
+  if (*d.abort_step <= a.step) return;
+  const int sub = threadIdx.x & (kGroup - 1);
+  const int64_t i = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / kGroup;
+  if (i >= d.n) return;   // whole group
+  const int in = a.in, out = a.out;
+  if (!G((const uint8_t*)d.alive[in])[i]) {   // whole group
+    if (sub == 0) {
+      gst(G(d.xr[out]) + i, gld(G((const double4*)d.xr[in]) + i));
+      gst(G(d.vel[out]) + i, gld(G((const double4*)d.vel[in]) + i));
+      gst(G((R4<R>*)d.omg[out]) + i, gld(G((const R4<R>*)d.omg[in]) + i));
+      G(d.alive[out])[i] = 0;
+    }
+    return;
+  }
+  // The lanes of a wave nearly always belong to one sample (an ensemble changes
+  // sample in few waves).  Each distinct sample of the wave is served in turn,
+  // so that the sample's constants are wave-uniform scalars.  The loop runs on
+  // a wave-uniform mask of the lanes still to serve, so every lane stays in it
+  // and runs its work under the branch of the iteration that serves its sample
+  // (a lane-wise `break` would let the compiler move the work past the loop,
+  // where all lanes have rejoined).  The lowest lane still to serve picks the
+  // sample; it is served, so the mask shrinks every iteration.
+  const int sl = G((const int32_t*)d.sample)[i];
+  uint64_t todo = __ballot(1);
+  while (todo) {
+    const int first = __builtin_ctzll(todo);
+    const bool mine = sl == __builtin_amdgcn_readlane(sl, first);
+    if (mine) particle_step<R, kGroup>(d, a, i, sub, opaque_readlane(sl, first));
+    todo &= ~__ballot(mine);
+  }
 }
 
 template <typename R> void launch_step(DevState& d, StepArgs a, hipStream_t s) {
