@@ -125,29 +125,45 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
   const R r = (R)pi.w;
   R F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   const double ci = d.ccoh ? CC[i] : 1.0;
+  const int32_t e0 = G((const int32_t*)d.nrow)[i] + sub;
   const int32_t e1 = G((const int32_t*)d.nrow)[i + 1];
-  for (int32_t e = G((const int32_t*)d.nrow)[i] + sub; e < e1; e += kGroup) {
-    const int32_t j = NBR[e];
-    const int32_t p = NSL[e];
+  // The next entry's partner and pair slot are fetched one iteration ahead, and
+  // all loads of an entry (the partner's state, the pair's history) are issued
+  // before any is used: one memory round trip per entry.
+  int32_t jn = 0, pn = 0;
+  if (e0 < e1) {
+    jn = NBR[e0];
+    pn = NSL[e0];
+  }
+  for (int32_t e = e0; e < e1; e += kGroup) {
+    const int32_t j = jn, p = pn;
+    if (e + kGroup < e1) {
+      jn = NBR[e + kGroup];
+      pn = NSL[e + kGroup];
+    }
+    const uint8_t alj = AL[j];
+    const double4 pj = gld(X + j);
+    const double4 vj = gld(V + j);
+    const R4<R> wj = gld(W + j);
+    const R4<R> hp = gld(Hin + p);
+    const uint8_t fp = Fin[p];
+    const double cj = d.ccoh ? CC[j] : 1.0;
     const bool own = j > (int32_t)i;
-    if (!AL[j]) {
+    if (!alj) {
       if (own) {
         gst(Hout + p, mk4<R>(0, 0, 0, 0));
         Fout[p] = 0;
       }
       continue;
     }
-    const double4 pj = gld(X + j);
-    const double4 vj = gld(V + j);
-    const R4<R> wj = gld(W + j);
     double gam = c.gamma;
-    if (d.ccoh) gam = c.gamma * sqrt(ci * CC[j]);
+    if (d.ccoh) gam = c.gamma * sqrt(ci * cj);
     PairOut<R> po;
     // canonical orientation: the owner (lower index) is body A
     const double4 PA = own ? pi : pj, PB = own ? pj : pi;
     const double4 VA = own ? v : vj, VB = own ? vj : v;
     const R4<R> WA = own ? w : wj, WB = own ? wj : w;
-    pair_eval<R>(lk, c.Es, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, gld(Hin + p), Fin[p], po);
+    pair_eval<R>(lk, c.Es, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, hp, fp, po);
     if (own) {
       gst(Hout + p, po.h);
       Fout[p] = po.fl;
