@@ -96,14 +96,38 @@ __device__ inline R group_sum(R v) {
   return v;
 }
 
-// A launch exits at entry when a rebuild is due at or before its step: the
-// recorded abort step (no rebuild: a large value) is written only by an
-// earlier launch or by the launch that finds it due for the NEXT step, so every
-// block of one launch takes the same decision.
-// Everything of one live particle after its own state has been read; `s` is
-// its sample, uniform over the wave.
+// Per-wave work queue of the step kernel, in LDS.  A round collects the live
+// entries (touching or bonded pairs with a live partner) of up to kKCap row
+// positions of every lane, at most kQCap of them, in (row position, lane)
+// order; the wave then evaluates them densely, each lane taking every
+// (number of lanes)-th entry, and finally each lane adds up its own entries in
+// row order, so the sum of every particle is formed as with one lane walking
+// its row.  An entry's contribution is its force (sign applied) and its
+// torque (r (n x F_t) + sign x rolling torque).
+constexpr int kQCap = 128;
+constexpr int kKCap = 32;
+template <typename R> struct WaveQueue {
+  int32_t j[kQCap], p[kQCap];
+  uint8_t li[kQCap];
+  R f[6][kQCap];
+  uint64_t ball[kKCap];   // lanes with a live entry at each row position of the round
+  int32_t base[kKCap];    // queue slot of the first of them
+};
+
+// LDS written by some lanes of a wave and read by others: keep the compiler
+// from moving the accesses across this point (the LDS executes the accesses
+// of one wave in order).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Everything of one live particle; `s` is its sample, uniform over the active
+// lanes, `lane` the lane in the wave and i0 the wave's first particle.
 template <typename R, int kGroup>
-__device__ __forceinline__ void particle_step(const DevState& d, const StepArgs& a, int64_t i, int sub, int s) {
+__device__ __forceinline__ void particle_step(const DevState& d, const StepArgs& a, int64_t i, int sub, int s,
+                                              int lane, int64_t i0, WaveQueue<R>& Q) {
   const int in = a.in, out = a.out;
   const SampleConst& c = sample_const(d.sc, s);
   const LawK<R> lk = law_k<R>(c);
@@ -111,9 +135,6 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
   const auto V = G((const double4*)d.vel[in]);
   const auto W = G((const R4<R>*)d.omg[in]);
   const auto AL = G((const uint8_t*)d.alive[in]);
-  const double4 pi = gld(X + i);
-  double4 v = gld(V + i);
-  R4<R> w = gld(W + i);
   const auto Hin = G((const R4<R>*)d.hdt[in]);
   const auto Hout = G((R4<R>*)d.hdt[out]);
   const auto Fin = G((const uint8_t*)d.pfl[in]);
@@ -122,60 +143,122 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
   const auto NSL = G((const int32_t*)d.nslot);
   const auto CC = G((const double*)d.ccoh);
   const bool rolling = d.rolling != 0;
-  const R r = (R)pi.w;
   R F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  const double ci = d.ccoh ? CC[i] : 1.0;
   const int32_t e0 = G((const int32_t*)d.nrow)[i] + sub;
   const int32_t e1 = G((const int32_t*)d.nrow)[i + 1];
-  // The next entry's partner and pair slot are fetched one iteration ahead, and
-  // all loads of an entry (the partner's state, the pair's history) are issued
-  // before any is used: one memory round trip per entry.
-  int32_t jn = 0, pn = 0;
-  if (e0 < e1) {
-    jn = NBR[e0];
-    pn = NSL[e0];
-  }
-  for (int32_t e = e0; e < e1; e += kGroup) {
-    const int32_t j = jn, p = pn;
-    if (e + kGroup < e1) {
-      jn = NBR[e + kGroup];
-      pn = NSL[e + kGroup];
+  const int nk = e0 < e1 ? (e1 - e0 + kGroup - 1) / kGroup : 0;   // row positions of this lane
+  const uint64_t below = (1ull << lane) - 1;
+  const uint64_t live = __ballot(1);
+  const bool leader = (live & below) == 0;
+  const int nact = __popcll(live), rank = __popcll(live & below);
+  const uint8_t li = (uint8_t)(lane / kGroup);
+  for (int k0 = 0; __ballot(k0 < nk);) {
+    // collect: a pair that is neither touching nor bonded, or whose partner
+    // is gone, gets its history cleared here (by its owner, the lower index)
+    // The partner and pair slot of the next row position are fetched one
+    // position ahead, and the tests below use every load unconditionally, so
+    // a row position costs one memory round trip.
+    int total = 0, kk = 0;
+    int32_t jn = 0, pn = 0;
+    if (k0 < nk) {
+      jn = NBR[e0 + k0 * kGroup];
+      pn = NSL[e0 + k0 * kGroup];
     }
-    const uint8_t alj = AL[j];
-    const double4 pj = gld(X + j);
-    const double4 vj = gld(V + j);
-    const R4<R> wj = gld(W + j);
-    const R4<R> hp = gld(Hin + p);
-    const uint8_t fp = Fin[p];
-    const double cj = d.ccoh ? CC[j] : 1.0;
-    const bool own = j > (int32_t)i;
-    if (!alj) {
-      if (own) {
-        gst(Hout + p, mk4<R>(0, 0, 0, 0));
-        Fout[p] = 0;
+    for (; kk < kKCap; ++kk) {
+      const int k = k0 + kk;
+      const bool has = k < nk;
+      if (!__ballot(has)) break;
+      const int32_t j = jn, p = pn;
+      if (k + 1 < nk) {
+        jn = NBR[e0 + (k + 1) * kGroup];
+        pn = NSL[e0 + (k + 1) * kGroup];
       }
-      continue;
+      bool act = false;
+      if (has) {
+        const double4 pi = gld(X + i);   // read again here: not held across the evaluation
+        const uint8_t alj = AL[j];
+        const double4 pj = gld(X + j);
+        const uint8_t fp = Fin[p];
+        const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        const double cs = pi.w + pj.w;
+        act = (alj != 0) & ((d2 < cs * cs) | ((fp & 1) != 0));
+        if (!act && j > (int32_t)i) {
+          gst(Hout + p, mk4<R>(0, 0, 0, 0));
+          Fout[p] = 0;
+        }
+      }
+      const uint64_t b = __ballot(act);
+      const int n = __popcll(b);
+      if (total + n > kQCap) break;   // this row position opens the next round
+      if (act) {
+        const int q = total + __popcll(b & below);
+        Q.j[q] = j;
+        Q.p[q] = p;
+        Q.li[q] = li;
+      }
+      if (leader) {
+        Q.ball[kk] = b;
+        Q.base[kk] = total;
+      }
+      total += n;
     }
-    double gam = c.gamma;
-    if (d.ccoh) gam = c.gamma * sqrt(ci * cj);
-    PairOut<R> po;
-    // canonical orientation: the owner (lower index) is body A
-    const double4 PA = own ? pi : pj, PB = own ? pj : pi;
-    const double4 VA = own ? v : vj, VB = own ? vj : v;
-    const R4<R> WA = own ? w : wj, WB = own ? wj : w;
-    pair_eval<R>(lk, c.Es, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, hp, fp, po);
-    if (own) {
-      gst(Hout + p, po.h);
-      Fout[p] = po.fl;
-      if (po.broke) atomicAdd(&d.broken[s], 1ull);
+    wave_lds_sync();
+    // evaluate, in the pair's canonical orientation (the owner, the lower
+    // index, is body A); only the owner writes the new history
+    for (int q = rank; q < total; q += nact) {
+      const int32_t j = Q.j[q], p = Q.p[q];
+      const int64_t ia = i0 + Q.li[q];
+      const double4 pa = gld(X + ia), pj = gld(X + j);
+      const double4 va = gld(V + ia), vj = gld(V + j);
+      const R4<R> wa = gld(W + ia), wj = gld(W + j);
+      const R4<R> hp = gld(Hin + p);
+      const uint8_t fp = Fin[p];
+      double gam = c.gamma;
+      if (d.ccoh) gam = c.gamma * sqrt(CC[ia] * CC[j]);
+      const bool own = j > (int32_t)ia;
+      PairOut<R> po;
+      const double4 PA = own ? pa : pj, PB = own ? pj : pa;
+      const double4 VA = own ? va : vj, VB = own ? vj : va;
+      const R4<R> WA = own ? wa : wj, WB = own ? wj : wa;
+      pair_eval<R>(lk, c.Es, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, hp, fp, po);
+      if (own) {
+        gst(Hout + p, po.h);
+        Fout[p] = po.fl;
+        if (po.broke) atomicAdd(&d.broken[s], 1ull);
+      }
+      // a broken bond contributes +0, which leaves the sums bit for bit as
+      // they are (they start at +0 and never become -0)
+      R cf[6] = {0, 0, 0, 0, 0, 0};
+      if (po.active) {
+        const R sg = own ? (R)1 : (R)-1, ra = (R)pa.w;
+        cf[0] = sg * po.o.F[0];
+        cf[1] = sg * po.o.F[1];
+        cf[2] = sg * po.o.F[2];
+        cf[3] = ra * po.o.c[0] + sg * po.o.Tr[0];
+        cf[4] = ra * po.o.c[1] + sg * po.o.Tr[1];
+        cf[5] = ra * po.o.c[2] + sg * po.o.Tr[2];
+      }
+#pragma unroll
+      for (int m = 0; m < 6; ++m) Q.f[m][q] = cf[m];
     }
-    if (!po.active) continue;
-    const R sg = own ? (R)1 : (R)-1;
-    F[0] += sg * po.o.F[0]; F[1] += sg * po.o.F[1]; F[2] += sg * po.o.F[2];
-    T[0] += r * po.o.c[0] + sg * po.o.Tr[0];
-    T[1] += r * po.o.c[1] + sg * po.o.Tr[1];
-    T[2] += r * po.o.c[2] + sg * po.o.Tr[2];
+    wave_lds_sync();
+    // add up, each lane its own entries in row order
+    for (int t = 0; t < kk; ++t) {
+      const uint64_t b = Q.ball[t];
+      if ((b >> lane) & 1) {
+        const int q = Q.base[t] + __popcll(b & below);
+        F[0] += Q.f[0][q]; F[1] += Q.f[1][q]; F[2] += Q.f[2][q];
+        T[0] += Q.f[3][q]; T[1] += Q.f[4][q]; T[2] += Q.f[5][q];
+      }
+    }
+    wave_lds_sync();
+    k0 += kk;
   }
+  const double4 pi = gld(X + i);
+  double4 v = gld(V + i);
+  R4<R> w = gld(W + i);
+  const R r = (R)pi.w;
   // walls: Hertz with R* = r and m* = m (rigid, static); entries private to i
   const double m = c.rho * (4.0 / 3.0) * M_PI * pi.w * pi.w * pi.w;
   const auto WDT = G((R4<R>*)d.wdt);
@@ -251,8 +334,13 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
   finish_drift<R>(d, c, i, out, a.step + 1, pi, v, w);
 }
 
+// A launch exits at entry when a rebuild is due at or before its step: the
+// recorded abort step (no rebuild: a large value) is written only by an
+// earlier launch or by the launch that finds it due for the NEXT step, so every
+// block of one launch takes the same decision.
 template <typename R, int kGroup>
 __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, StepArgs a) {
+  __shared__ WaveQueue<R> wq[kBlock / 64];
   const DevState& d = *dp;
   if (*d.abort_step <= a.step) return;
   const int sub = threadIdx.x & (kGroup - 1);
@@ -277,11 +365,14 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
   // where all lanes have rejoined).  The lowest lane still to serve picks the
   // sample; it is served, so the mask shrinks every iteration.
   const int sl = G((const int32_t*)d.sample)[i];
+  const int lane = threadIdx.x & 63;
   uint64_t todo = __ballot(1);
   while (todo) {
     const int first = __builtin_ctzll(todo);
     const bool mine = sl == __builtin_amdgcn_readlane(sl, first);
-    if (mine) particle_step<R, kGroup>(d, a, i, sub, opaque_readlane(sl, first));
+    if (mine)
+      particle_step<R, kGroup>(d, a, i, sub, opaque_readlane(sl, first), lane, i - lane / kGroup,
+                               wq[threadIdx.x >> 6]);
     todo &= ~__ballot(mine);
   }
 }
