@@ -74,6 +74,10 @@ __global__ void k_fluid_partials(const DevState* __restrict__ dp) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d.ndual * m) return;
   const int64_t b = t / m;
+  if (d.dual_sink[b]) {   // the skipped particles of a sample: no cell reads this bucket
+    d.dpart[t] = 0.0;
+    return;
+  }
   const int k = (int)(t - b * m);
   const int corner = kKind == 0 ? k : k / 3, comp = kKind == 0 ? 0 : k % 3;
   const int cx = corner & 1, cy = (corner >> 1) & 1, cz = corner >> 2;

@@ -60,10 +60,11 @@ void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hi
 // stable bucket sort: count, scan, scatter to arbitrary slots, then rank every
 // bucket's members by (tiebreak, index) -- one wavefront per bucket, members
 // staged in LDS when the bucket holds at most 64 of them.  Sink buckets (dead
-// particles, particles outside every fluid grid) keep the scatter order: their
-// order reaches no result, and a sink can hold a large share of all particles,
-// where the rank (quadratic in the bucket size) would not scale.  With a gate
-// flag set, the whole sort does nothing.
+// particles, particles outside every fluid grid) keep the scatter order,
+// written directly to the output: their order reaches no result, and a sink
+// can hold a large share of all particles, where the rank (quadratic in the
+// bucket size) would not scale.  With a gate flag set, the whole sort does
+// nothing.
 // ---------------------------------------------------------------------------
 __global__ void k_zero2(int32_t* a, int32_t* b, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -73,20 +74,50 @@ __global__ void k_zero2(int32_t* a, int32_t* b, int64_t n) {
   }
 }
 
-__global__ void k_bucket_count(const uint32_t* key, int64_t n, int32_t* cnt, const int* gate) {
-  if (gate && *gate) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&cnt[key[i]], 1);
+// Adds 1 to ctr[k] for every valid lane and returns the lane's slot (the
+// counter's value before its own addition).  The members of a sink bucket all
+// add to one counter, from every XCD of the chip: one contended address, whose
+// atomics serialise across the chip as the dead particles accumulate.  They
+// add per wave instead: one atomic per (wave, sink bucket), each lane taking
+// its rank among the wave's members of that bucket.
+__device__ inline int32_t bucket_add(int32_t* ctr, uint32_t k, bool valid, bool is_sink) {
+  const int lane = threadIdx.x & 63;
+  int32_t slot = 0;
+  if (valid && !is_sink) slot = atomicAdd(&ctr[k], 1);
+  const bool agg = valid && is_sink;
+  uint64_t pend = __ballot(agg);
+  while (pend) {                       // wave-uniform: one pass per distinct sink bucket
+    const int leader = __builtin_ctzll(pend);
+    const uint32_t kl = (uint32_t)__shfl((int)k, leader);
+    const uint64_t peers = __ballot(agg && k == kl) & pend;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[kl], __popcll(peers));
+    base = __shfl(base, leader);
+    if ((peers >> lane) & 1) slot = base + __popcll(peers & ((1ull << lane) - 1ull));
+    pend &= ~peers;
+  }
+  return slot;
 }
 
-__global__ void k_bucket_scatter(const uint32_t* key, int64_t n, const int32_t* off, int32_t* fill,
-                                 int32_t* order, const int* gate) {
+__global__ void k_bucket_count(const uint32_t* key, int64_t n, int32_t* cnt, const uint8_t* sink, const int* gate) {
   if (gate && *gate) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t k = key[i];
-  int32_t slot = atomicAdd(&fill[k], 1);
-  order[off[k] + slot] = (int32_t)i;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  const uint32_t k = valid ? key[i] : 0u;
+  bucket_add(cnt, k, valid, valid && sink && sink[k]);
+}
+
+// Members of a sink bucket go straight to their final array (their order
+// reaches no result); the others to the staging array that the rank reorders.
+__global__ void k_bucket_scatter(const uint32_t* key, int64_t n, const int32_t* off, int32_t* fill,
+                                 int32_t* order, int32_t* final_order, const uint8_t* sink, const int* gate) {
+  if (gate && *gate) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  const uint32_t k = valid ? key[i] : 0u;
+  const bool is_sink = valid && sink && sink[k];
+  const int32_t slot = bucket_add(fill, k, valid, is_sink);
+  if (valid) (is_sink ? final_order : order)[off[k] + slot] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t nb, const int32_t* src,
@@ -110,10 +141,7 @@ __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t
   }
   __syncthreads();
   if (b >= nb || k == 0) return;
-  if (sink && sink[b]) {
-    for (int32_t t = lane; t < k; t += 64) dst[lo + t] = src[lo + t];
-    return;
-  }
+  if (sink && sink[b]) return;   // written by the scatter
   if (small) {
     if (lane < k) {
       int32_t v = sm[w][lane], kv = sk[w][lane], rank = 0;
@@ -143,10 +171,11 @@ void launch_bucket_sort(const uint32_t* key, int64_t n, int64_t nb, const int32_
                         int32_t* scan_tmp, const uint8_t* sink, const int* gate, hipStream_t s) {
   // cleared by a kernel, not a memset: the sort is also recorded into graphs
   hipLaunchKernelGGL(k_zero2, dim3(nblk(nb + 1)), dim3(kBlock), 0, s, cnt, fill, nb + 1);
-  if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt, gate);
+  if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt, sink, gate);
   scan_exclusive(cnt, off, nb + 1, scan_tmp, s);
   if (n > 0)
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, off, fill, order_tmp, gate);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, off, fill, order_tmp,
+                       out_order, sink, gate);
   hipLaunchKernelGGL(k_bucket_rank, dim3(nblk(nb, 4)), dim3(256), 0, s, off, nb, order_tmp, tiebreak, out_order,
                      sink, gate);
 }
