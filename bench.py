@@ -167,6 +167,31 @@ def closure_block(w, torch):
     return out
 
 
+def learned_cg_block(horizon, ks=(2, 3)):
+    """The coarse-grained model against the fine run (the metric's second
+    part): for each k, paired fine (c1) and coarse (SSW) runs, the closure
+    trained on the first half of the horizon, and the produced mass at the
+    horizon of the plain and the learned coarse model against the fine run; the
+    closure is kept only where it is not worse (else the plain model).  The
+    speedup is the fine run's wall time over the kept coarse model's, both
+    from the initial packing over the whole horizon."""
+    import synth
+    from paper_2211_06142_amd import closure_train as ct
+    wf = synth.c1()
+    out = {"fine_particles": len(wf["r"]), "horizon_steps": horizon, "per_k": []}
+    for k in ks:
+        res = ct.gain_test(wf, synth.c2(k), horizon=horizon, window=500, epochs=30)
+        for key in ("net", "norm", "mass_series"):
+            res.pop(key)
+        kept = res["err_learned_cg"] if res["closure_accepted"] else res["err_plain_cg"]
+        res["err_kept"] = kept
+        res["within_5pct"] = bool(kept <= 0.05)
+        out["per_k"].append(res)
+        print("bench: learned-CG k=%d done: error plain %.4f learned %.4f, speedup %.2f" %
+              (k, res["err_plain_cg"], res["err_learned_cg"], res["speedup_vs_fine"]), file=sys.stderr, flush=True)
+    return out
+
+
 def build_sim(ws, skin_factor, lanes, graphs):
     from paper_2211_06142_amd import dem
     rmin = min(float(np.min(w["r"])) for w in ws)
@@ -199,6 +224,9 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune skin and lanes before the timed run")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure measurement (network "
                     "throughput on the matrix cores, cost inside the coupling)")
+    ap.add_argument("--no-learned-cg", action="store_true", help="skip the coarse-grained model against the "
+                    "fine run (paired runs, closure training, produced-mass error and speedup)")
+    ap.add_argument("--cg-horizon", type=int, default=20000, help="steps of the fine/coarse comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU sharding of the DEM step is a "
@@ -313,6 +341,8 @@ def main():
     if not args.no_closure and len(ws) == 1:
         out["closure"] = closure_block(w, torch)
     sim.close()
+    if not args.no_learned_cg and args.workload == "c1":
+        out["learned_cg"] = learned_cg_block(args.cg_horizon)
     if not args.no_cpu and args.workload != "c3":
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
