@@ -24,7 +24,7 @@ def _time_steps(sim, steps):
     return e0.elapsed_time(e1)
 
 
-def tune(make_sim, skins, lanes=(1, 2, 4, 8), warmup=40, steps=200, log=None):
+def tune(make_sim, skins, lanes=(1, 2, 4, 8), warmup=40, steps=1000, log=None):
     """make_sim(skin) -> a fresh dem.Simulation with that skin (metres).
     Returns (best, table): best = dict(skin, lanes, ms_per_step), table = all
     trials as (skin, lanes, ms_per_step, rebuilds)."""
@@ -45,7 +45,7 @@ def tune(make_sim, skins, lanes=(1, 2, 4, 8), warmup=40, steps=200, log=None):
     return best, table
 
 
-def tune_workload(w, skin_factors=(0.2, 0.4, 0.8, 1.6), precision=None, **kw):
+def tune_workload(w, skin_factors=(0.4, 0.8, 1.2, 1.6), precision=None, **kw):
     """Tune a workload dict (or a list of ensemble samples): skins are
     multiples of the smallest radius."""
     ws = w if isinstance(w, list) else [w]
