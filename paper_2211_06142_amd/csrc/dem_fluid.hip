@@ -65,35 +65,40 @@ __device__ inline double corner_w(const double4& fr, int kx, int ky, int kz) {
 
 // corner partials of every bucket: kind 0 volume (8 per bucket), kind 1 drag (24 per bucket)
 template <int kKind>
-__global__ void k_fluid_partials(const DevState* __restrict__ dp) {
-  // one thread per (bucket, output): 8 corner volumes, or 8 corners x 3 drag
-  // components; each output sums the bucket's members in bucket order
+__global__ __launch_bounds__(64) void k_fluid_partials(const DevState* __restrict__ dp) {
+  // one thread per bucket, all its outputs (8 corner volumes, or 8 corners x 3
+  // drag components): each member is read once, and every output sums the
+  // bucket's members in bucket order
   const DevState& d = *dp;
   if (*d.abort) return;
   constexpr int m = kKind == 0 ? 8 : 24;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= d.ndual * m) return;
-  const int64_t b = t / m;
-  if (d.dual_sink[b]) {   // the skipped particles of a sample: no cell reads this bucket
-    d.dpart[t] = 0.0;
-    return;
-  }
-  const int k = (int)(t - b * m);
-  const int corner = kKind == 0 ? k : k / 3, comp = kKind == 0 ? 0 : k % 3;
-  const int cx = corner & 1, cy = (corner >> 1) & 1, cz = corner >> 2;
-  double acc = 0.0;
-  for (int32_t q = d.doff[b]; q < d.doff[b + 1]; ++q) {
-    const int32_t i = d.dmem[q];
-    const double4 fr = d.dfr[i];
-    const double w = corner_w(fr, cx, cy, cz);
-    if (kKind == 0) {
-      acc += w * fr.w;
-    } else {
-      const double4 fp = d.fpart[i];
-      acc += w * (comp == 0 ? fp.x : comp == 1 ? fp.y : fp.z);
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= d.ndual) return;
+  double acc[m];
+#pragma unroll
+  for (int k = 0; k < m; ++k) acc[k] = 0.0;
+  // the skipped particles of a sample sit in its sink bucket, which no cell reads
+  if (!d.dual_sink[b]) {
+    for (int32_t q = d.doff[b]; q < d.doff[b + 1]; ++q) {
+      const int32_t i = d.dmem[q];
+      const double4 fr = d.dfr[i];
+      double4 fp = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (kKind == 1) fp = d.fpart[i];
+#pragma unroll
+      for (int corner = 0; corner < 8; ++corner) {
+        const double w = corner_w(fr, corner & 1, (corner >> 1) & 1, corner >> 2);
+        if (kKind == 0) {
+          acc[corner] += w * fr.w;
+        } else {
+          acc[3 * corner] += w * fp.x;
+          acc[3 * corner + 1] += w * fp.y;
+          acc[3 * corner + 2] += w * fp.z;
+        }
+      }
     }
   }
-  d.dpart[t] = acc;
+#pragma unroll
+  for (int k = 0; k < m; ++k) d.dpart[m * b + k] = acc[k];
 }
 
 // per fluid cell: fixed-order sum of the corner partials of the adjacent buckets
@@ -272,14 +277,14 @@ template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
   hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
   launch_bucket_sort((const uint32_t*)d.dkey, d.n, d.ndual, nullptr, d.dcnt, d.doff, d.dfill, d.dmem_tmp,
                      d.dmem, d.scan_tmp, d.dual_sink, d.abort, s);
-  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
+  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual, 64)), dim3(64), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
   if (d.closure_on) {
     hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
     launch_closure_infer(d, s);
   }
   hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
-  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual * 24)), dim3(kBlock), 0, s, d.self);
+  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual, 64)), dim3(64), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
 }
 template void launch_fluid<double>(DevState&, int, hipStream_t);
