@@ -87,16 +87,20 @@ def test_contact_sets_random_polydisperse(seed):
     np.testing.assert_array_equal(g.pairs(which=2)["pairs"], oracle.pairs(x, r, extra=margin))
 
 
-def test_long_rows_and_crowded_cells():
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_long_rows_and_crowded_cells(lanes):
     """Rows longer than the scratch stride and binning cells too full for LDS
     (a large sphere with a shell of 100 touching small ones, in a dense gas):
     contact sets bit-exact, then 10 FP64 steps against the oracle, so the
-    half-pair slots of the long rows must be right for the history to agree."""
+    half-pair slots of the long rows must be right for the history to agree.
+    With one lane per particle the step kernel's per-wave contact queue fills
+    and its rows span several rounds."""
     x, r = scenes.shells_in_gas(np.random.default_rng(5))
     w = dict(synth.c0())
     w["fluid"] = None
     w["walls"] = []
     g = gpu_for(w, "fp64", x=x, r=r)
+    g.set_lanes(lanes)
     margin = g.info()["cutoff_margin"]
     cand = oracle.pairs(x, r, extra=margin)
     assert np.bincount(cand.ravel(), minlength=len(r)).max() > 64
@@ -146,7 +150,7 @@ def test_c0_fp64_steps(nsteps):
     assert gs["n_contacts"] == sc["n_contacts"]
 
 
-@pytest.mark.parametrize("lanes", [4, 16])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
 def test_c0_fp64_lanes_per_particle(lanes):
     """the step kernel's lane-group size is a tuning knob: any setting matches
     the oracle to rounding"""
