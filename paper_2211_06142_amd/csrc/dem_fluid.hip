@@ -22,7 +22,7 @@ __global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
   const DevState& d = *dp;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  const SampleConst& c = d.sc[d.sample[i]];
+  const SampleConst& c = sample_const(d.sc, d.sample[i]);
   int64_t nd = (int64_t)c.dn[0] * c.dn[1] * c.dn[2];
   const int32_t skip = (int32_t)(c.dual_base + nd);
   if (*d.abort || !d.alive[buf][i] || !c.fluid_on) { d.dkey[i] = skip; return; }
@@ -78,27 +78,44 @@ __global__ __launch_bounds__(64) void k_fluid_partials(const DevState* __restric
 #pragma unroll
   for (int k = 0; k < m; ++k) acc[k] = 0.0;
   // the skipped particles of a sample sit in its sink bucket, which no cell reads
-  if (!d.dual_sink[b]) {
-    for (int32_t q = d.doff[b]; q < d.doff[b + 1]; ++q) {
-      const int32_t i = d.dmem[q];
-      const double4 fr = d.dfr[i];
-      double4 fp = make_double4(0.0, 0.0, 0.0, 0.0);
-      if (kKind == 1) fp = d.fpart[i];
+  // members in groups of four: all loads of a group are issued before any
+  // use (a bucket holds a few members, so this is one or two round trips)
+  constexpr int kU = 4;
+  const auto MEM = G((const int32_t*)d.dmem);
+  const auto FR = G((const double4*)d.dfr);
+  const auto FP = G((const double4*)d.fpart);
+  if (!G((const uint8_t*)d.dual_sink)[b]) {
+    const int32_t q1 = G((const int32_t*)d.doff)[b + 1];
+    for (int32_t q0 = G((const int32_t*)d.doff)[b]; q0 < q1; q0 += kU) {
+      int32_t ii[kU];
+      double4 fr[kU], fp[kU];
 #pragma unroll
-      for (int corner = 0; corner < 8; ++corner) {
-        const double w = corner_w(fr, corner & 1, (corner >> 1) & 1, corner >> 2);
-        if (kKind == 0) {
-          acc[corner] += w * fr.w;
-        } else {
-          acc[3 * corner] += w * fp.x;
-          acc[3 * corner + 1] += w * fp.y;
-          acc[3 * corner + 2] += w * fp.z;
+      for (int u = 0; u < kU; ++u) ii[u] = q0 + u < q1 ? MEM[q0 + u] : -1;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        fr[u] = ii[u] >= 0 ? gld(FR + ii[u]) : make_double4(0.0, 0.0, 0.0, 0.0);
+        fp[u] = kKind == 1 && ii[u] >= 0 ? gld(FP + ii[u]) : make_double4(0.0, 0.0, 0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (ii[u] < 0) break;
+#pragma unroll
+        for (int corner = 0; corner < 8; ++corner) {
+          const double w = corner_w(fr[u], corner & 1, (corner >> 1) & 1, corner >> 2);
+          if (kKind == 0) {
+            acc[corner] += w * fr[u].w;
+          } else {
+            acc[3 * corner] += w * fp[u].x;
+            acc[3 * corner + 1] += w * fp[u].y;
+            acc[3 * corner + 2] += w * fp[u].z;
+          }
         }
       }
     }
   }
+  const auto PART = G(d.dpart);
 #pragma unroll
-  for (int k = 0; k < m; ++k) d.dpart[m * b + k] = acc[k];
+  for (int k = 0; k < m; ++k) PART[m * b + k] = acc[k];
 }
 
 // per fluid cell: fixed-order sum of the corner partials of the adjacent buckets
@@ -108,7 +125,7 @@ __global__ void k_fluid_cells(const DevState* __restrict__ dp) {
   if (*d.abort) return;
   int64_t C = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (C >= d.ncell) return;
-  const SampleConst& c = d.sc[d.cell_sample[C]];
+  const SampleConst& c = sample_const(d.sc, d.cell_sample[C]);
   int64_t l = C - c.cell_base;
   const int cc[3] = {(int)(l % c.gn[0]), (int)((l / c.gn[0]) % c.gn[1]), (int)(l / ((int64_t)c.gn[0] * c.gn[1]))};
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
@@ -203,7 +220,7 @@ __global__ void k_closure_features(const DevState* __restrict__ dp, int buf) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   double* f = d.cfeat + 6 * i;
-  const SampleConst& c = d.sc[d.sample[i]];
+  const SampleConst& c = sample_const(d.sc, d.sample[i]);
   if (!d.alive[buf][i] || !c.fluid_on) {
     for (int k = 0; k < 6; ++k) f[k] = 0.0;
     return;
@@ -241,7 +258,7 @@ __global__ void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
   if (*d.abort) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  const SampleConst& c = d.sc[d.sample[i]];
+  const SampleConst& c = sample_const(d.sc, d.sample[i]);
   if (!d.alive[buf][i] || !c.fluid_on) {
     ((R4<R>*)d.fdr)[i] = mk4<R>(0, 0, 0, 0);
     d.fpart[i] = make_double4(0, 0, 0, 0);

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_aggregate_part(DevState d, const int64_
   const int s = blockIdx.x / kAggChunks, ch = blockIdx.x % kAggChunks;
   const int t = threadIdx.x;
   const int b = d.cur;
-  const SampleConst& c = d.sc[s];
+  const SampleConst& c = sample_const(d.sc, s);
   const int64_t a0 = soff[s], a1 = soff[s + 1];
   const int64_t k0 = a0 + (a1 - a0) * ch / kAggChunks, k1 = a0 + (a1 - a0) * (ch + 1) / kAggChunks;
   double pm = 0.0, ke = 0.0, na = 0.0, nc = 0.0;

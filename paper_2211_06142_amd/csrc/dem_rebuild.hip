@@ -13,7 +13,7 @@ namespace dem {
 __global__ void k_bin_keys(DevState d) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  const SampleConst& c = d.sc[d.sample[i]];
+  const SampleConst& c = sample_const(d.sc, d.sample[i]);
   int64_t nb = (int64_t)c.bn[0] * c.bn[1] * c.bn[2];
   if (!d.alive[d.cur][i]) { d.key[i] = (uint32_t)(c.bin_base + nb); return; }
   double4 p = d.xr[d.cur][i];
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   const int64_t cbin = blockIdx.x;
   const int32_t h0 = d.cell_start[cbin], h1 = d.cell_start[cbin + 1];
   if (h1 <= h0) return;
-  const SampleConst& c = d.sc[d.bin_sample[cbin]];
+  const SampleConst& c = sample_const(d.sc, d.bin_sample[cbin]);
   const int64_t local = cbin - c.bin_base;
   if (local >= (int64_t)c.bn[0] * c.bn[1] * c.bn[2]) return;   // the dead bucket
   const int cx = (int)(local % c.bn[0]);
@@ -284,7 +284,7 @@ void launch_nbr_search(DevState& d, hipStream_t s) {
 __global__ __launch_bounds__(64) void k_nbr_fill_overflow(DevState d) {
   __shared__ int32_t srs[27], srl[27];
   const int32_t i = d.ovf[blockIdx.x];
-  const SampleConst& c = d.sc[d.sample[i]];
+  const SampleConst& c = sample_const(d.sc, d.sample[i]);
   const double4* X = d.xr[d.cur];
   const double4 pi = X[i];
   const int cx = bin_coord(pi.x, c.blo[0], c.bh[0], c.bn[0]);
@@ -394,7 +394,7 @@ __global__ void k_wall_search(DevState d) {
   if (i >= d.n) return;
   int cnt = 0;
   if (d.alive[d.cur][i]) {
-    const SampleConst& c = d.sc[d.sample[i]];
+    const SampleConst& c = sample_const(d.sc, d.sample[i]);
     double4 p = d.xr[d.cur][i];
     int row = kFill ? d.wrow[i] : 0;
     for (int w = 0; w < c.n_walls; ++w) {
@@ -489,7 +489,7 @@ __global__ void k_mark_bonds(DevState d) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.nslots) return;
   int32_t i = d.sown[p], j = d.spart[p];
-  const SampleConst& c = d.sc[d.sample[i]];
+  const SampleConst& c = sample_const(d.sc, d.sample[i]);
   if (c.normal_model != DEM_NORMAL_JKR_MOD) return;
   double4 a = d.xr[d.cur][i], b = d.xr[d.cur][j];
   double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;

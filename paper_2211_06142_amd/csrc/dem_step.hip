@@ -65,7 +65,7 @@ __global__ void k_prologue(DevState d, StepArgs a) {
     d.alive[out][i] = 0;
     return;
   }
-  const SampleConst& c = d.sc[d.sample[i]];
+  const SampleConst& c = sample_const(d.sc, d.sample[i]);
   const R4<R> F = ((const R4<R>*)d.frc)[i];
   const R4<R> T = ((const R4<R>*)d.trq)[i];
   const double hdt = 0.5 * d.dt;
