@@ -75,16 +75,16 @@ __global__ void k_zero2(int32_t* a, int32_t* b, int64_t n) {
 }
 
 // Adds 1 to ctr[k] for every valid lane and returns the lane's slot (the
-// counter's value before its own addition).  The members of a sink bucket all
-// add to one counter, from every XCD of the chip: one contended address, whose
-// atomics serialise across the chip as the dead particles accumulate.  They
-// add per wave instead: one atomic per (wave, sink bucket), each lane taking
-// its rank among the wave's members of that bucket.
-__device__ inline int32_t bucket_add(int32_t* ctr, uint32_t k, bool valid, bool is_sink) {
+// counter's value before its own addition).  The lanes add per wave: one
+// atomic per (wave, bucket), each lane taking its rank among the wave's
+// members of that bucket.  Particles arrive in spatial order, so a wave holds
+// few distinct buckets; and the members of a sink bucket all add to one
+// counter from every XCD of the chip, one contended address whose atomics
+// would serialise across the chip as the dead particles accumulate.
+__device__ inline int32_t bucket_add(int32_t* ctr, uint32_t k, bool valid) {
   const int lane = threadIdx.x & 63;
   int32_t slot = 0;
-  if (valid && !is_sink) slot = atomicAdd(&ctr[k], 1);
-  const bool agg = valid && is_sink;
+  const bool agg = valid;
   uint64_t pend = __ballot(agg);
   while (pend) {                       // wave-uniform: one pass per distinct sink bucket
     const int leader = __builtin_ctzll(pend);
@@ -99,12 +99,12 @@ __device__ inline int32_t bucket_add(int32_t* ctr, uint32_t k, bool valid, bool 
   return slot;
 }
 
-__global__ void k_bucket_count(const uint32_t* key, int64_t n, int32_t* cnt, const uint8_t* sink, const int* gate) {
+__global__ void k_bucket_count(const uint32_t* key, int64_t n, int32_t* cnt, const int* gate) {
   if (gate && *gate) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   const uint32_t k = valid ? key[i] : 0u;
-  bucket_add(cnt, k, valid, valid && sink && sink[k]);
+  bucket_add(cnt, k, valid);
 }
 
 // Members of a sink bucket go straight to their final array (their order
@@ -116,7 +116,7 @@ __global__ void k_bucket_scatter(const uint32_t* key, int64_t n, const int32_t* 
   const bool valid = i < n;
   const uint32_t k = valid ? key[i] : 0u;
   const bool is_sink = valid && sink && sink[k];
-  const int32_t slot = bucket_add(fill, k, valid, is_sink);
+  const int32_t slot = bucket_add(fill, k, valid);
   if (valid) (is_sink ? final_order : order)[off[k] + slot] = (int32_t)i;
 }
 
@@ -171,7 +171,7 @@ void launch_bucket_sort(const uint32_t* key, int64_t n, int64_t nb, const int32_
                         int32_t* scan_tmp, const uint8_t* sink, const int* gate, hipStream_t s) {
   // cleared by a kernel, not a memset: the sort is also recorded into graphs
   hipLaunchKernelGGL(k_zero2, dim3(nblk(nb + 1)), dim3(kBlock), 0, s, cnt, fill, nb + 1);
-  if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt, sink, gate);
+  if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt, gate);
   scan_exclusive(cnt, off, nb + 1, scan_tmp, s);
   if (n > 0)
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, off, fill, order_tmp,
