@@ -103,8 +103,12 @@ def normaliser(X):
 # runs
 # ---------------------------------------------------------------------------
 def make_sim(w, closure=None, norm=None):
+    """a run of workload w; below 50 000 particles 8 lanes per particle
+    (timed on the coarse cylinders: the step kernel has too few particles to
+    fill the chip with 4)"""
     sim = dem.Simulation(dem.params_from_workload(w), w["x"], w["r"])
     sim.map_fluid(w["u_cell"], w["gradp_cell"])
+    sim.set_lanes(8 if len(w["r"]) < 50000 else 4)
     if closure is not None:
         sim.set_closure(closure, norm)
     return sim

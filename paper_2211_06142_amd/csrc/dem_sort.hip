@@ -75,27 +75,35 @@ __global__ void k_zero2(int32_t* a, int32_t* b, int64_t n) {
 }
 
 // Adds 1 to ctr[k] for every valid lane and returns the lane's slot (the
-// counter's value before its own addition).  The lanes add per wave: one
-// atomic per (wave, bucket), each lane taking its rank among the wave's
-// members of that bucket.  Particles arrive in spatial order, so a wave holds
-// few distinct buckets; and the members of a sink bucket all add to one
-// counter from every XCD of the chip, one contended address whose atomics
-// would serialise across the chip as the dead particles accumulate.
+// counter's value before its own addition).  The first two buckets of the wave
+// add per wave (one atomic each, every lane taking its rank among the wave's
+// members of that bucket), the remaining lanes one atomic each.  Particles
+// arrive in spatial order, so a wave often holds few buckets, and the members
+// of a sink bucket (the dead particles) all add to one counter from every XCD
+// of the chip: one contended address, whose atomics would serialise across the
+// chip as the dead particles accumulate.  More passes would chain their
+// atomics where every lane has a bucket of its own (coarse particles).
 __device__ inline int32_t bucket_add(int32_t* ctr, uint32_t k, bool valid) {
   const int lane = threadIdx.x & 63;
   int32_t slot = 0;
-  const bool agg = valid;
-  uint64_t pend = __ballot(agg);
-  while (pend) {                       // wave-uniform: one pass per distinct sink bucket
+  bool todo = valid;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const uint64_t pend = __ballot(todo);
+    if (!pend) break;                  // wave-uniform
     const int leader = __builtin_ctzll(pend);
     const uint32_t kl = (uint32_t)__shfl((int)k, leader);
-    const uint64_t peers = __ballot(agg && k == kl) & pend;
+    const bool mine = todo && k == kl;
+    const uint64_t peers = __ballot(mine);
     int32_t base = 0;
     if (lane == leader) base = atomicAdd(&ctr[kl], __popcll(peers));
     base = __shfl(base, leader);
-    if ((peers >> lane) & 1) slot = base + __popcll(peers & ((1ull << lane) - 1ull));
-    pend &= ~peers;
+    if (mine) {
+      slot = base + __popcll(peers & ((1ull << lane) - 1ull));
+      todo = false;
+    }
   }
+  if (todo) slot = atomicAdd(&ctr[k], 1);
   return slot;
 }
 
