@@ -169,7 +169,7 @@ def closure_block(w, torch):
     return out
 
 
-def learned_cg_block(horizon, ks=(2, 3)):
+def learned_cg_block(horizon, ks=(2, 3), c4=False):
     """The coarse-grained model against the fine run (the metric's second
     part): for each k, paired fine (c1) and coarse (SSW) runs, the closure
     trained on the first half of the horizon, and the produced mass at the
@@ -179,10 +179,10 @@ def learned_cg_block(horizon, ks=(2, 3)):
     from the initial packing over the whole horizon."""
     import synth
     from paper_2211_06142_amd import closure_train as ct
-    wf = synth.c1()
-    out = {"fine_particles": len(wf["r"]), "horizon_steps": horizon, "per_k": []}
+    wf = synth.c4(1) if c4 else synth.c1()
+    out = {"fine": "c4" if c4 else "c1", "fine_particles": len(wf["r"]), "horizon_steps": horizon, "per_k": []}
     for k in ks:
-        res = ct.gain_test(wf, synth.c2(k), horizon=horizon, window=500, epochs=30)
+        res = ct.gain_test(wf, synth.c4(k) if c4 else synth.c2(k), horizon=horizon, window=500, epochs=30)
         for key in ("net", "norm", "mass_series"):
             res.pop(key)
         kept = res["err_learned_cg"] if res["closure_accepted"] else res["err_plain_cg"]
@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--no-learned-cg", action="store_true", help="skip the coarse-grained model against the "
                     "fine run (paired runs, closure training, produced-mass error and speedup)")
     ap.add_argument("--cg-horizon", type=int, default=20000, help="steps of the fine/coarse comparison")
+    ap.add_argument("--cg-c4", action="store_true", help="the comparison on c4 (2 000 000 fine grains against "
+                    "k = 3 parcels) instead of c1 against c2 (needs the c4 packings, about an hour to generate)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU sharding of the DEM step is a "
@@ -346,7 +348,8 @@ def main():
         out["closure"] = closure_block(w, torch)
     sim.close()
     if not args.no_learned_cg and args.workload == "c1":
-        out["learned_cg"] = learned_cg_block(args.cg_horizon)
+        out["learned_cg"] = (learned_cg_block(args.cg_horizon, ks=(3,), c4=True) if args.cg_c4
+                             else learned_cg_block(args.cg_horizon))
     if not args.no_cpu and args.workload != "c3":
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

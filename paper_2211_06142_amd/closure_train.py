@@ -157,7 +157,7 @@ class Recorder:
         eps_mean = esum / max(nc, 1)
         rec = {"drag": dsum / max(nc, 1), "eps": eps_mean}
         alive = st["alive"].astype(bool)
-        pr = self.sim.pairs()
+        pr = self.sim.pairs(sort=False)
         rec["coh"] = pulloff_density(st["x"], self.w["r"], pr["pairs"], pr["bonded"], self.gamma,
                                      self.w["grid"], eps_mean)
         if self.features:

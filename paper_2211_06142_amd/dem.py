@@ -523,7 +523,7 @@ class Simulation:
             res[k] = getattr(st, k)
         return res
 
-    def pairs(self, which=0):
+    def pairs(self, which=0, sort=True):
         rc, cnt = dem_read_pairs(self.ctx, which, 0, None, None, None)
         _check(rc, "dem_read_pairs")
         pi = np.zeros((max(cnt, 1), 2), np.int64)
@@ -531,6 +531,8 @@ class Simulation:
         pb = np.zeros(max(cnt, 1), np.uint8)
         rc, cnt = dem_read_pairs(self.ctx, which, cnt, pi.ctypes.data, pdt.ctypes.data, pb.ctypes.data)
         _check(rc, "dem_read_pairs")
+        if not sort:
+            return {"pairs": pi[:cnt], "dt": pdt[:cnt], "bonded": pb[:cnt]}
         order = np.lexsort((pi[:cnt, 1], pi[:cnt, 0]))
         return {"pairs": pi[:cnt][order], "dt": pdt[:cnt][order], "bonded": pb[:cnt][order]}
 

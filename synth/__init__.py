@@ -276,6 +276,21 @@ def c2(k=2, scheme="ssw", n_fine=200000):
     return w
 
 
+def c4(k=1, scheme="ssw"):
+    """Fine-equivalent 2 000 000 grains: the c1 cylinder scaled by 10^(1/3)
+    (R 25.85 mm, cavity 4.31 mm, H 12.93 mm) with c1's fluid cell size
+    (grid 103 x 103 x 52); k > 1: the coarse-grained model (k = 3: 74 074
+    parcels)."""
+    s = 10.0 ** (1.0 / 3.0)
+    n_fine = 2000000
+    n = int(round(n_fine / k ** 3))
+    w = cylinder_workload(n, SEED0 + 4 + 10 * int(k) + (1 if scheme == "ssp" else 0),
+                          "c4_k%d_%s" % (k, scheme), k=float(k), scheme=scheme, R=12e-3 * s, r_cav=2e-3 * s,
+                          H=6e-3 * s, grid_n=(103, 103, 52))
+    w.update(precision="mixed", steps=5000, n_fine=n_fine)
+    return w
+
+
 def c3_sizes(n_samples=256, seed=SEED0 + 3):
     rng = np.random.default_rng(seed)
     ns = rng.integers(500, 20001, size=n_samples)
