@@ -104,9 +104,14 @@ __device__ inline R group_sum(R v) {
 // row order, so the sum of every particle is formed as with one lane walking
 // its row.  An entry's contribution is its force (sign applied) and its
 // torque (r (n x F_t) + sign x rolling torque).
+// The wave's own particles (position, velocity, angular velocity) are staged
+// there too.
 constexpr int kQCap = 128;
 constexpr int kKCap = 32;
-template <typename R> struct WaveQueue {
+template <typename R, int kGroup> struct WaveQueue {
+  static constexpr int kP = 64 / kGroup;   // particles of a wave
+  double4 sx[kP], sv[kP];
+  R4<R> sw[kP];
   int32_t j[kQCap], p[kQCap];
   uint8_t li[kQCap];
   R f[6][kQCap];
@@ -127,7 +132,7 @@ __device__ inline void wave_lds_sync() {
 // lanes, `lane` the lane in the wave and i0 the wave's first particle.
 template <typename R, int kGroup>
 __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs& a, int64_t i, int sub, int s,
-                                              int lane, int64_t i0, WaveQueue<R>& Q) {
+                                              int lane, int64_t i0, WaveQueue<R, kGroup>& Q) {
   const int in = a.in, out = a.out;
   const SampleConst& c = sample_const(d.sc, s);
   const LawK<R> lk = law_k<R>(c);
@@ -143,6 +148,13 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
   const auto NSL = G((const int32_t*)d.nslot);
   const auto CC = G((const double*)d.ccoh);
   const bool rolling = d.rolling != 0;
+  const uint8_t li = (uint8_t)(lane / kGroup);
+  if (sub == 0) {
+    Q.sx[li] = gld(X + i);
+    Q.sv[li] = gld(V + i);
+    Q.sw[li] = gld(W + i);
+  }
+  wave_lds_sync();
   R F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   const int32_t e0 = G((const int32_t*)d.nrow)[i] + sub;
   const int32_t e1 = G((const int32_t*)d.nrow)[i + 1];
@@ -151,7 +163,6 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
   const uint64_t live = __ballot(1);
   const bool leader = (live & below) == 0;
   const int nact = __popcll(live), rank = __popcll(live & below);
-  const uint8_t li = (uint8_t)(lane / kGroup);
   for (int k0 = 0; __ballot(k0 < nk);) {
     // collect: a pair that is neither touching nor bonded, or whose partner
     // is gone, gets its history cleared here (by its owner, the lower index)
@@ -175,7 +186,10 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
       }
       bool act = false;
       if (has) {
-        const double4 pi = gld(X + i);   // read again here: not held across the evaluation
+        // read here, not held in registers across the evaluation (the empty
+        // statement keeps the compiler from hoisting the read out of the loop)
+        asm volatile("" ::: "memory");
+        const double4 pi = Q.sx[li];
         const uint8_t alj = AL[j];
         const double4 pj = gld(X + j);
         const uint8_t fp = Fin[p];
@@ -208,10 +222,12 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
     // index, is body A); only the owner writes the new history
     for (int q = rank; q < total; q += nact) {
       const int32_t j = Q.j[q], p = Q.p[q];
-      const int64_t ia = i0 + Q.li[q];
-      const double4 pa = gld(X + ia), pj = gld(X + j);
-      const double4 va = gld(V + ia), vj = gld(V + j);
-      const R4<R> wa = gld(W + ia), wj = gld(W + j);
+      const int la = Q.li[q];
+      const int64_t ia = i0 + la;
+      asm volatile("" ::: "memory");
+      const double4 pa = Q.sx[la], pj = gld(X + j);
+      const double4 va = Q.sv[la], vj = gld(V + j);
+      const R4<R> wa = Q.sw[la], wj = gld(W + j);
       const R4<R> hp = gld(Hin + p);
       const uint8_t fp = Fin[p];
       double gam = c.gamma;
@@ -255,9 +271,9 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
     wave_lds_sync();
     k0 += kk;
   }
-  const double4 pi = gld(X + i);
-  double4 v = gld(V + i);
-  R4<R> w = gld(W + i);
+  const double4 pi = Q.sx[li];
+  double4 v = Q.sv[li];
+  R4<R> w = Q.sw[li];
   const R r = (R)pi.w;
   // walls: Hertz with R* = r and m* = m (rigid, static); entries private to i
   const double m = c.rho * (4.0 / 3.0) * M_PI * pi.w * pi.w * pi.w;
@@ -340,7 +356,7 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
 // block of one launch takes the same decision.
 template <typename R, int kGroup>
 __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, StepArgs a) {
-  __shared__ WaveQueue<R> wq[kBlock / 64];
+  __shared__ WaveQueue<R, kGroup> wq[kBlock / 64];
   const DevState& d = *dp;
   if (*d.abort_step <= a.step) return;
   const int sub = threadIdx.x & (kGroup - 1);
