@@ -11,10 +11,12 @@ CFD cell and coupling evaluation, the solid fraction and the drag density
 Targets, per CFD cell c and time window w:
   y_drag = ln( D_fine / D_coarse ),  D = |f_d,c| / eps_s,c, the drag force per
            unit solid volume, averaged over the couplings of the window;
-  y_coh  = ln( A_fine / A_coarse ),  A = the pull-off forces 3 pi gamma R* of
-           the bonded contacts whose contact point lies in c (the adhesion the
-           bonds can hold, Table 1 point B), per unit solid volume, at the end
-           of the window.
+  y_coh  = ln( A_fine / (k A_coarse) ),  A = the pull-off forces 3 pi gamma R*
+           of the bonded contacts whose contact point lies in c (the adhesion
+           the bonds can hold, Table 1 point B), per unit solid volume, at the
+           end of the window; k A_coarse is what the coarse-graining law
+           (gamma_g = k gamma, section 2.4) predicts for A_fine, so y_coh is
+           the law's residual.
 Both are clipped to [-ln 2, ln 2], the range the closure can express (its
 factors are exp(clip(y, +-ln 2))).  A cell enters only where both runs hold
 solid (eps_s above a floor) and, for y_coh, bonds.  Every coarse parcel that
@@ -170,12 +172,19 @@ class Recorder:
 
 
 def build_dataset(fine, coarse, eps_floor=0.05):
-    """(X, Y) over the windows both recorders kept"""
+    """(X, Y) over the windows both recorders kept.  The cohesion target is the
+    residual of the coarse-graining law: with gamma_g = k gamma and R*_g =
+    k R* a parcel bond holds k^2 the pull-off force of a grain bond, over k^3
+    fewer bonds per unit volume, so the law itself expects A_coarse = A_fine /
+    k; the target is ln(A_fine / (k A_coarse)).  The drag law k^3 f(d / k)
+    keeps the drag per unit solid volume, so the drag target needs no such
+    factor."""
+    kc = float(coarse.w.get("k", 1.0)) / float(fine.w.get("k", 1.0))
     Xs, Ys = [], []
     for wf, wc in zip(fine.windows, coarse.windows):
         valid = (wf["eps"] > eps_floor) & (wc["eps"] > eps_floor)
         yd = log_ratio(wf["drag"], wc["drag"], valid)
-        yc = log_ratio(wf["coh"], wc["coh"], valid)
+        yc = log_ratio(wf["coh"], kc * wc["coh"], valid)
         X, Y = assemble(wc["features"], wc["cells"], yd, yc)
         Xs.append(X)
         Ys.append(Y)
