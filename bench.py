@@ -233,8 +233,8 @@ def main():
                     "k = 3 parcels) instead of c1 against c2 (needs the c4 packings, about an hour to generate)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; the multi-GPU sharding of the DEM step is a "
-              "design (see DESIGN.md), not an implemented path", file=sys.stderr)
+        print("bench.py: measures one GPU only; sharding the DEM step over several GPUs is designed but not "
+              "implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
