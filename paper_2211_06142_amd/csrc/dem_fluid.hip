@@ -232,17 +232,41 @@ __global__ void k_closure_features(const DevState* __restrict__ dp, int buf) {
   double s[3] = {u[0] - v.x, u[1] - v.y, u[2] - v.z};
   double sm = sqrt((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
   double sum = 0.0, cnt = 0.0;
-  const uint8_t* al = d.alive[buf];
-  const uint8_t* fl = d.pfl[buf];
-  for (int32_t e = d.nrow[i]; e < d.nrow[i + 1]; ++e) {
-    const int32_t j = d.nbr[e];
-    if (!al[j] || !(fl[d.nslot[e]] & 3)) continue;
-    const double4 pj = d.xr[buf][j];
-    double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-    double delta = (pi.w + pj.w) - sqrt((dx * dx + dy * dy) + dz * dz);
-    double Rs = pi.w * pj.w / (pi.w + pj.w);
-    sum += delta / Rs;
-    cnt += 1.0;
+  const auto AL = G((const uint8_t*)d.alive[buf]);
+  const auto FL = G((const uint8_t*)d.pfl[buf]);
+  const auto XR = G((const double4*)d.xr[buf]);
+  const auto NBR = G((const int32_t*)d.nbr);
+  const auto NSL = G((const int32_t*)d.nslot);
+  const int32_t e1 = G((const int32_t*)d.nrow)[i + 1];
+  // row entries four at a time: all loads of a group are issued before any
+  // use; the sum runs in row order
+  constexpr int kU = 4;
+  for (int32_t e0 = G((const int32_t*)d.nrow)[i]; e0 < e1; e0 += kU) {
+    int32_t jj[kU], ss[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const bool ok = e0 + u < e1;
+      jj[u] = ok ? NBR[e0 + u] : -1;
+      ss[u] = ok ? NSL[e0 + u] : 0;
+    }
+    uint8_t a[kU], fp[kU];
+    double4 pj[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const bool ok = jj[u] >= 0;
+      a[u] = ok ? AL[jj[u]] : 0;
+      fp[u] = ok ? FL[ss[u]] : 0;
+      pj[u] = ok ? gld(XR + jj[u]) : make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (!a[u] || !(fp[u] & 3)) continue;
+      double dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
+      double delta = (pi.w + pj[u].w) - sqrt((dx * dx + dy * dy) + dz * dz);
+      double Rs = pi.w * pj[u].w / (pi.w + pj[u].w);
+      sum += delta / Rs;
+      cnt += 1.0;
+    }
   }
   f[0] = np;
   f[1] = sm;
