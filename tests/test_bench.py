@@ -1,0 +1,49 @@
+"""Host logic of bench.py: the one-GPU guard, the algorithmic-byte model, and
+the rule that a committed counter summary is used only for the kernel sources
+it was taken on.  No GPU."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+
+
+def test_algorithmic_bytes_per_unit():
+    # mixed precision: 128 B per particle update, 36 B per half pair, 40 B per fluid cell
+    assert bench.alg_bytes("step", 1000, 3000, 0, 4) == 1000 * 128 + 3000 * 36
+    assert bench.alg_bytes("step", 1000, 3000, 0, 8) == 1000 * 156 + 3000 * 60
+    assert bench.alg_bytes("fluid", 1000, 0, 500, 4) == 1000 * 64 + 500 * 40
+    assert bench.alg_bytes("prologue", 10, 99, 99, 4) == 10 * 128
+    assert bench.alg_bytes("rebuild", 10, 20, 0, 4) == 10 * 256 + 20 * 36
+
+
+def test_traffic_summary_needs_matching_sources(tmp_path, monkeypatch):
+    with open(os.path.join(ROOT, "profiles", "step_c1_pmc.json")) as f:
+        d = json.load(f)
+    assert set(d["sources"]) <= set(os.listdir(os.path.join(ROOT, "paper_2211_06142_amd", "csrc")))
+    assert d["traffic_bytes_per_launch"] == pytest.approx(
+        d["fetch_kib_median"] * 1024 * d["calibration"]["fetch_factor"]
+        + d["write_kib_median"] * 1024 * d["calibration"]["write_factor"])
+    # a summary taken on other sources is not used
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    d2 = dict(d, source_hash="0" * 16)
+    (prof / "step_c1_pmc.json").write_text(json.dumps(d2))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda files=None: "f" * 16)
+    assert bench.load_traffic("step", "c1") is None
+    d3 = dict(d, source_hash="f" * 16)
+    (prof / "step_c1_pmc.json").write_text(json.dumps(d3))
+    assert bench.load_traffic("step", "c1") == d["traffic_bytes_per_launch"]
