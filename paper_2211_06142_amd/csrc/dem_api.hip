@@ -811,6 +811,11 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   up &= hipMemcpyAsync(d.frc, hF.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.trq, hT.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemsetAsync(d.fdr, 0, n * R4B, st) == hipSuccess;
+  // the bucket sorts expect their counters at zero (each sort clears them after use)
+  up &= hipMemsetAsync(d.bucket_cnt, 0, sizeof(int32_t) * nbk, st) == hipSuccess;
+  up &= hipMemsetAsync(d.bucket_fill, 0, sizeof(int32_t) * nbk, st) == hipSuccess;
+  up &= hipMemsetAsync(d.dcnt, 0, sizeof(int32_t) * (d.ndual + 2), st) == hipSuccess;
+  up &= hipMemsetAsync(d.dfill, 0, sizeof(int32_t) * (d.ndual + 2), st) == hipSuccess;
   up &= hipMemcpyAsync(d.sample, hs.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.orig, ho.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.sc, c->sc.data(), sizeof(SampleConst) * n_samples, hipMemcpyHostToDevice, st) == hipSuccess;

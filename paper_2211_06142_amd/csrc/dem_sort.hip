@@ -66,13 +66,6 @@ void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hi
 // bucket size) would not scale.  With a gate flag set, the whole sort does
 // nothing.
 // ---------------------------------------------------------------------------
-__global__ void k_zero2(int32_t* a, int32_t* b, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    a[i] = 0;
-    b[i] = 0;
-  }
-}
 
 // Adds 1 to ctr[k] for every valid lane and returns the lane's slot (the
 // counter's value before its own addition).  The first two buckets of the wave
@@ -128,9 +121,12 @@ __global__ void k_bucket_scatter(const uint32_t* key, int64_t n, const int32_t* 
   if (valid) (is_sink ? final_order : order)[off[k] + slot] = (int32_t)i;
 }
 
+// The rank also clears the bucket's counter and fill level, which nothing
+// reads after the scatter: the next sort finds them at zero (they start at
+// zero when allocated), with no clearing launch of its own.
 __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t nb, const int32_t* src,
                                                      const int32_t* tiebreak, int32_t* dst, const uint8_t* sink,
-                                                     const int* gate) {
+                                                     const int* gate, int32_t* cnt, int32_t* fill) {
   __shared__ int32_t sm[4][64];
   __shared__ int32_t sk[4][64];
   if (gate && *gate) return;
@@ -140,6 +136,10 @@ __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t
   if (b < nb) {
     lo = off[b];
     k = off[b + 1] - lo;
+    if (lane == 0) {
+      cnt[b] = 0;
+      fill[b] = 0;
+    }
   }
   const bool small = k <= 64;
   if (small && lane < k) {
@@ -177,15 +177,15 @@ __global__ __launch_bounds__(256) void k_bucket_rank(const int32_t* off, int64_t
 void launch_bucket_sort(const uint32_t* key, int64_t n, int64_t nb, const int32_t* tiebreak, int32_t* cnt,
                         int32_t* off, int32_t* fill, int32_t* order_tmp, int32_t* out_order,
                         int32_t* scan_tmp, const uint8_t* sink, const int* gate, hipStream_t s) {
-  // cleared by a kernel, not a memset: the sort is also recorded into graphs
-  hipLaunchKernelGGL(k_zero2, dim3(nblk(nb + 1)), dim3(kBlock), 0, s, cnt, fill, nb + 1);
+  // cnt and fill are zero on entry: cleared by the previous sort's rank (see
+  // k_bucket_rank) and at allocation
   if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, cnt, gate);
   scan_exclusive(cnt, off, nb + 1, scan_tmp, s);
   if (n > 0)
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, key, n, off, fill, order_tmp,
                        out_order, sink, gate);
   hipLaunchKernelGGL(k_bucket_rank, dim3(nblk(nb, 4)), dim3(256), 0, s, off, nb, order_tmp, tiebreak, out_order,
-                     sink, gate);
+                     sink, gate, cnt, fill);
 }
 
 }  // namespace dem
