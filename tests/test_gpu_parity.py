@@ -386,8 +386,10 @@ def test_step_without_fluid_fields_is_state_error():
 # benchmark (mixed precision) against the oracle
 # ---------------------------------------------------------------------------
 def test_c1_full_size_against_oracle():
+    import bench
     w = synth.c1()
-    g = gpu_for(w, "mixed")
+    # built exactly as bench.py builds it: its skin and lanes per particle
+    g = bench.build_sim([w], bench.SKIN_FACTOR["c1"], bench.LANES, 0)
     o = oracle_for(w, bond_at_init=True)
     np.testing.assert_array_equal(g.pairs(which=0)["pairs"], oracle.pairs(w["x"], w["r"], extra=0.0))
     # one step from the identical FP64 state: the per-step bar
