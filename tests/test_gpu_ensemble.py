@@ -83,3 +83,29 @@ def test_ensemble_sample_equals_its_single_run():
     sb, so = sim.state(), one.state()
     for key in ("x", "v", "w", "F", "T"):
         np.testing.assert_array_equal(sb[key][a:b], so[key], err_msg=key)
+
+
+def test_c3_full_size_sampled_against_oracle():
+    """The whole 256-sample ensemble (2.66 M spheres), built exactly as the
+    bench builds it, stepped 3 times; sampled samples (the three smallest, one
+    in the middle of the sweep, the last) against their own oracle runs: the
+    same contact and bond sets, forces to the mixed-precision bar."""
+    import bench
+    ws = synth.c3()
+    sim = bench.build_sim(ws, bench.SKIN_FACTOR["c3"], bench.LANES, 0)
+    offs = np.cumsum([0] + [len(w["r"]) for w in ws]).astype(np.int64)
+    sim.step(3)
+    st = sim.state()
+    pairs = sim.pairs()["pairs"]
+    sizes = np.array([len(w["r"]) for w in ws])
+    picks = list(np.argsort(sizes, kind="stable")[:3]) + [128, 255]
+    for s in picks:
+        w = ws[s]
+        o = _oracle(w)
+        o.step(3)
+        os_ = o.state()
+        a, b = offs[s], offs[s + 1]
+        err = np.linalg.norm(st["F"][a:b] - os_["F"], axis=1) / (os_["fscale"] + 1e-300)
+        assert err.max() < 1e-5, s
+        mine = pairs[(pairs[:, 0] >= a) & (pairs[:, 0] < b)] - a
+        np.testing.assert_array_equal(mine, o.pairs()["pairs"])
