@@ -409,3 +409,22 @@ def test_c1_full_size_against_oracle():
     np.testing.assert_array_equal(gp["pairs"], op_["pairs"])
     np.testing.assert_array_equal(gp["bonded"], op_["bonded"])
     assert scaled_err(gs["F"], os_["F"], os_["fscale"]) < 1e-3
+
+
+def test_c0_full_run_aggregates():
+    """The whole c0 configuration (2 000 spheres, FP64, 1 000 steps) against
+    the oracle on aggregates, the comparison for horizons where the
+    trajectories may part by rounding: contacts within 2 %, broken bonds
+    within 2 % (or 2 bonds), kinetic energy within 5 %, produced mass equal
+    (the walled box has no outlet)."""
+    w = synth.c0()
+    g = gpu_for(w, "fp64")
+    o = oracle_for(w, bond_at_init=True)
+    g.step(1000)
+    o.step(1000)
+    gs, sc = g.state(), o.scalars()
+    assert gs["step"] == sc["step"] == 1000
+    assert gs["n_contacts"] == pytest.approx(sc["n_contacts"], rel=0.02)
+    assert abs(gs["broken_bonds"] - sc["broken_bonds"]) <= max(2, 0.02 * sc["broken_bonds"])
+    assert gs["kinetic"] == pytest.approx(sc["kinetic"], rel=0.05)
+    assert gs["produced_mass"] == sc["produced_mass"] == 0.0
