@@ -98,6 +98,8 @@ def lib():
         L.or_destroy.argtypes = [vp]
         L.or_set_fluid.restype = ctypes.c_int
         L.or_set_fluid.argtypes = [vp, vp, vp]
+        L.or_set_held.restype = ctypes.c_int
+        L.or_set_held.argtypes = [vp, i64, vp]
         L.or_set_closure.restype = ctypes.c_int
         L.or_set_closure.argtypes = [vp, vp, vp]
         L.or_set_closure_mlp.restype = ctypes.c_int
@@ -295,6 +297,12 @@ class OracleSim:
         u = _f64(u_cell)
         gp = _f64(gradp_cell)
         lib().or_set_fluid(self.h, _ptr(u), _ptr(gp))
+
+    def set_held(self, step, fluid_force=None):
+        """Resume at absolute step `step` (the coupling schedule) with the fluid
+        force (n x 3, drag plus buoyancy) held since the last coupling evaluation."""
+        ff = None if fluid_force is None else _f64(fluid_force, (-1, 3))
+        lib().or_set_held(self.h, int(step), _ptr(ff))
 
     def set_closure(self, c_drag=None, c_coh=None):
         cd = None if c_drag is None else _f64(c_drag)

@@ -364,6 +364,15 @@ int or_set_fluid(or_sim* s, const double* u_cell, const double* gradp_cell) {
   return 0;
 }
 
+int or_set_held(or_sim* s, int64_t step, const double* fluid_force) {
+  s->step = step;
+  for (int64_t k = 0; k < 3 * s->n; ++k) {
+    s->fdrag[k] = fluid_force ? fluid_force[k] : 0.0;
+    s->fbuoy[k] = 0.0;
+  }
+  return 0;
+}
+
 int or_set_closure(or_sim* s, const double* c_drag, const double* c_coh) {
   free(s->c_drag); free(s->c_coh);
   s->c_drag = c_drag ? dup(c_drag, s->n) : NULL;

@@ -94,6 +94,11 @@ or_sim* or_create(const or_params* p, int64_t n, const double* x, const double* 
 void    or_destroy(or_sim* s);
 int     or_set_fluid(or_sim* s, const double* u_cell, const double* gradp_cell);
 int     or_set_closure(or_sim* s, const double* c_drag, const double* c_coh);
+/* Resume from a given state: the step counter (which decides the coupling
+ * schedule, step % couple_every == 0) and the fluid force on every particle held
+ * since the last coupling evaluation (3n, drag plus buoyancy; NULL: zero).  The
+ * held force enters every step until the next evaluation replaces it. */
+int     or_set_held(or_sim* s, int64_t step, const double* fluid_force);
 /* learned closure (an extension): flat FP64 parameters (OR_MLP_NPARAMS) and the
  * feature normalisation mean[6], sd[6]; params NULL switches it off.  While on,
  * every coupling evaluation recomputes c_drag and c_coh of every particle. */

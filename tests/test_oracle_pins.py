@@ -545,3 +545,228 @@ def test_outlet_removes_and_counts_mass():
     st = sim.state()
     assert list(st["alive"]) == [0, 1]
     assert sim.scalars()["produced_mass"] == pytest.approx(RHO * 4 / 3 * math.pi * r[0] ** 3, rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# section 3.1 particle-wall law on the curved walls of the cylinder workloads
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [oracle.WALL_CYL_IN, oracle.WALL_CYL_OUT])
+def test_cylinder_wall_hertz_force_and_normal(kind):
+    """A sphere pressed by delta against a z-axis cylinder wall (axis off the
+    origin, arbitrary angle and height) at rest and without gravity: one step
+    gives the Hertz force 4/3 E* sqrt(r) delta^(3/2) (the wall law with R* = r)
+    along the radial direction, pointing to the axis for a sphere inside the
+    cylinder and away from it for a sphere outside, and no torque.  A second
+    sphere a gap away from the wall feels nothing."""
+    r, delta, Rw = 1e-4, 2e-6, 2e-3
+    ax = np.array([3e-4, -2e-4])
+    th, z = 0.7, 1.3e-3
+    e = np.array([math.cos(th), math.sin(th), 0.0])
+    if kind == oracle.WALL_CYL_IN:
+        rho1, rho2, sign = Rw - r + delta, Rw - r - 5e-6, -1.0
+    else:
+        rho1, rho2, sign = Rw + r - delta, Rw + r + 5e-6, 1.0
+    e2 = np.array([math.cos(th + 2.0), math.sin(th + 2.0), 0.0])
+    x = np.array([[ax[0], ax[1], z], [ax[0], ax[1], z]])
+    x[0] += rho1 * e
+    x[1] += rho2 * e2
+    p = _params(scenes.material(gamma=0.0), 1e-9, g=(0, 0, 0), walls=[(kind, (ax[0], ax[1], Rw))],
+                normal_model=oracle.NORMAL_HERTZ)
+    sim = oracle.OracleSim(p, x, np.array([r, r]), bond_at_init=False)
+    sim.step(1)
+    st = sim.state()
+    F0 = st["F"][0]
+    expect = 4.0 / 3.0 * ES * math.sqrt(r) * delta ** 1.5
+    assert np.linalg.norm(F0) == pytest.approx(expect, rel=1e-10)
+    np.testing.assert_allclose(F0 / np.linalg.norm(F0), sign * e, rtol=0, atol=1e-13)
+    assert np.all(st["T"] == 0.0)
+    assert np.all(st["F"][1] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# section 2.2: the fluid fields at the particle (porosity, fluid velocity,
+# pressure gradient), eq 1's buoyancy/pressure term and eq 6's porosity
+# ---------------------------------------------------------------------------
+def _tiny_spheres(rng, grid, n_in=12):
+    """Spheres too small and too far apart to touch: n_in inside the hull of the
+    cell centres, and points beyond it on every side (inside and outside the grid)."""
+    lo, hi, nn = (np.array(a, dtype=float) for a in grid)
+    h = (hi - lo) / nn
+    c0, c1 = lo + 0.5 * h, hi - 0.5 * h
+    x = [rng.uniform(c0, c1) for _ in range(n_in)]
+    mid = 0.5 * (lo + hi)
+    for ax in range(3):
+        for q in (lo[ax] + 0.2 * h[ax], hi[ax] - 0.1 * h[ax], hi[ax] + 0.7 * h[ax], lo[ax] - 0.3 * h[ax]):
+            p = mid + rng.uniform(-0.3, 0.3, 3) * h
+            p[ax] = q
+            x.append(p)
+    x = np.array(x)
+    return x, np.full(len(x), 1e-6), np.clip(x, c0, c1)
+
+
+def test_trilinear_interpolation_reproduces_linear_fields():
+    """Trilinear weights over the 8 surrounding cell centres reproduce any field
+    that is affine in position, exactly (to rounding), inside the hull of the
+    centres; beyond it the weights fold onto the boundary cells, which gives
+    the field at the nearest point of the hull (per axis).  Checked on an
+    interstitial fluid velocity u(x) = A x + b (the slip-speed feature |u - v|
+    and the drag direction, which is that of u - v by eq 8) and a pressure
+    gradient G x + c (F_b = -V (grad p + rho_f g), eq 1), on a grid with
+    unequal cells per axis."""
+    rng = np.random.default_rng(41)
+    grid = ((-1e-3, 0.5e-3, 2e-3), (1.5e-3, 2.5e-3, 3.2e-3), (5, 4, 3))
+    x, r, xc = _tiny_spheres(rng, grid)
+    centres = _centres(grid)
+    A, b = rng.normal(0, 40.0, (3, 3)), rng.normal(0, 0.05, 3)
+    G, c = rng.normal(0, 4e6, (3, 3)), rng.normal(0, 1e3, 3)
+    u = centres @ A.T + b
+    gp = centres @ G.T + c
+    g = (0.0, 0.0, -9.81)
+    for vf in (oracle.VOID_CIC,):
+        fluid = dict(rho_f=998.2, mu_f=1e-3, n_min=0.3, voidfrac=vf, u_superficial=0, couple_every=1)
+        p = _params(scenes.material(gamma=0.0), 1e-12, g=g, grid=grid, fluid=fluid,
+                    normal_model=oracle.NORMAL_HERTZ)
+        sim = oracle.OracleSim(p, x, r, bond_at_init=False)
+        sim.set_fluid(u, gp)
+        feat = sim.closure_features()
+        u_exp = xc @ A.T + b
+        np.testing.assert_allclose(feat[:, 1], np.linalg.norm(u_exp, axis=1), rtol=1e-12)
+        sim.step(1)
+        fl = sim.fluid()
+        V = 4.0 / 3.0 * math.pi * r ** 3
+        fb_exp = -V[:, None] * (xc @ G.T + c + 998.2 * np.array(g))
+        np.testing.assert_allclose(fl["fb_part"], fb_exp, rtol=1e-11, atol=0)
+        fp = fl["f_part"]
+        np.testing.assert_allclose(fp / np.linalg.norm(fp, axis=1)[:, None],
+                                   u_exp / np.linalg.norm(u_exp, axis=1)[:, None], rtol=0, atol=1e-12)
+
+
+def test_centroid_takes_the_value_of_the_containing_cell():
+    """Centroid deposition (the option of the unresolved coupling): a particle
+    sees the fields of the cell that holds its centre (positions beyond the
+    grid: the nearest boundary cell)."""
+    rng = np.random.default_rng(43)
+    grid = ((0.0, 0.0, 0.0), (2e-3, 1.5e-3, 1e-3), (4, 3, 2))
+    x, r, _ = _tiny_spheres(rng, grid)
+    lo, hi, nn = (np.array(a, dtype=float) for a in grid)
+    h = (hi - lo) / nn
+    ni = nn.astype(int)
+    cell = np.clip(np.floor((x - lo) / h), 0, nn - 1).astype(int)
+    cid = (cell[:, 2] * ni[1] + cell[:, 1]) * ni[0] + cell[:, 0]
+    nc = int(np.prod(nn))
+    gp = rng.normal(0, 1e4, (nc, 3))
+    u = rng.normal(0, 0.1, (nc, 3))
+    fluid = dict(rho_f=998.2, mu_f=1e-3, n_min=0.3, voidfrac=oracle.VOID_CENTROID, u_superficial=0, couple_every=1)
+    p = _params(scenes.material(gamma=0.0), 1e-12, g=(0, 0, 0), grid=grid, fluid=fluid,
+                normal_model=oracle.NORMAL_HERTZ)
+    sim = oracle.OracleSim(p, x, r, bond_at_init=False)
+    sim.set_fluid(u, gp)
+    np.testing.assert_allclose(sim.closure_features()[:, 1], np.linalg.norm(u[cid], axis=1), rtol=1e-14)
+    sim.step(1)
+    V = 4.0 / 3.0 * math.pi * r ** 3
+    np.testing.assert_allclose(sim.fluid()["fb_part"], -V[:, None] * gp[cid], rtol=1e-14)
+
+
+@pytest.mark.parametrize("vf", [oracle.VOID_CIC, oracle.VOID_CENTROID])
+def test_uniform_porosity_and_superficial_velocity(vf):
+    """One sphere at the centre of every cell: either deposition gives every
+    cell the solid fraction V/V_cell, so the porosity of eq 6 is the uniform
+    n = 1 - V/V_cell; a uniform superficial velocity U (the n u of eq 6) is
+    then the interstitial velocity U/n everywhere.  The particle at rest sees
+    porosity n and slip U/n, so its drag is eq 8-11 at slip U/n and porosity n
+    (the law itself is pinned by test_drag_limits and the terminal velocity),
+    the cell source of eq 7 is that drag over V_cell, and the total force is
+    m g + drag - V rho_f g."""
+    grid = ((0.0, 0.0, 0.0), (2e-3, 1.5e-3, 2.5e-3), (4, 3, 5))
+    centres = _centres(grid)
+    vcell = 0.5e-3 ** 3
+    r = np.full(len(centres), 0.1e-3)
+    V = 4.0 / 3.0 * math.pi * r[0] ** 3
+    n_exp = 1.0 - V / vcell
+    U = np.array([0.01, -0.02, 0.05])
+    nc = len(centres)
+    g = (0.0, 0.0, -9.81)
+    fluid = dict(rho_f=998.2, mu_f=1e-3, n_min=0.3, voidfrac=vf, u_superficial=1, couple_every=1)
+    mat = scenes.material(gamma=0.0)
+    p = _params(mat, 1e-12, g=g, grid=grid, fluid=fluid, normal_model=oracle.NORMAL_HERTZ)
+    sim = oracle.OracleSim(p, centres, r, bond_at_init=False)
+    sim.set_fluid(np.tile(U, (nc, 1)), np.zeros((nc, 3)))
+    feat = sim.closure_features()
+    np.testing.assert_allclose(feat[:, 0], n_exp, rtol=1e-14)
+    np.testing.assert_allclose(feat[:, 1], np.linalg.norm(U) / n_exp, rtol=1e-14)
+    sim.step(1)
+    fl = sim.fluid()
+    np.testing.assert_allclose(fl["eps_s"], V / vcell, rtol=1e-13)
+    f_exp = oracle.drag(U / n_exp, 2 * r[0], 1.0, n_exp, 998.2, 1e-3)
+    np.testing.assert_allclose(fl["f_part"], np.tile(f_exp, (nc, 1)), rtol=1e-12)
+    np.testing.assert_allclose(fl["fdrag_cell"], np.tile(f_exp / vcell, (nc, 1)), rtol=1e-12)
+    m = mat["rho"] * V
+    F_exp = f_exp + (m - 998.2 * V) * np.array(g)
+    np.testing.assert_allclose(sim.state()["F"], np.tile(F_exp, (nc, 1)), rtol=1e-12)
+
+
+def _centres(grid):
+    lo, hi, nn = (np.array(a, dtype=float) for a in grid)
+    h = (hi - lo) / nn
+    ax = [lo[c] + (np.arange(int(nn[c])) + 0.5) * h[c] for c in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def test_resume_from_held_state_equals_continuing():
+    """Stopping a run and resuming it from its state (positions, velocities,
+    forces, contact history, wall history, the held fluid force and the step
+    counter) continues it exactly: the held state is all the step depends on."""
+    rng = np.random.default_rng(3)
+    grid = ((0.0, 0.0, 0.0), (1e-3, 1e-3, 1e-3), (4, 4, 4))
+    x, r, v = scenes.random_gas(rng, 60, 1e-3, 4e-5, 9e-5, 0.5)
+    fluid = dict(rho_f=998.2, mu_f=1e-3, n_min=0.3, voidfrac=0, u_superficial=1, couple_every=3)
+    walls = [scenes.plane((0, 0, 1), 0.0), scenes.plane((1, 0, 0), 0.0)]
+    p = _params(scenes.material(), 2e-8, grid=grid, fluid=fluid, walls=walls)
+    u, gp = np.tile([0.0, 0.0, 0.05], (64, 1)), np.zeros((64, 3))
+    a = oracle.OracleSim(p, x, r, v=v, bond_at_init=False)
+    a.set_fluid(u, gp)
+    a.step(7)
+    s, pr = a.state(), a.pairs()
+    fl = a.fluid()
+    b = oracle.OracleSim(p, s["x"], r, v=s["v"], w=s["w"], F=s["F"], T=s["T"], alive=s["alive"],
+                         pairs=pr["pairs"], pair_dt=pr["dt"], pair_bonded=pr["bonded"], bond_at_init=False,
+                         wall_dt=a.wall_dt())
+    b.set_fluid(u, gp)
+    b.set_held(7, fl["f_part"] + fl["fb_part"])
+    a.step(5)
+    b.step(5)
+    sa, sb = a.state(), b.state()
+    for key in ("x", "v", "w"):
+        np.testing.assert_allclose(sb[key], sa[key], rtol=1e-13, atol=1e-300)
+
+
+def test_porosity_interpolated_between_cell_centres():
+    """A sphere at the centre of every cell deposits its whole volume into that
+    cell (either deposition); with volumes affine in position, V_c = a + b.x_c,
+    the porosity of eq 6 is the affine field 1 - (a + b.x)/V_cell at the centres,
+    and the porosity seen by a probe sphere (too small to change it) inside the
+    hull of the centres is that affine field at the probe's centre."""
+    rng = np.random.default_rng(47)
+    grid = ((0.0, 0.0, 0.0), (2e-3, 1.5e-3, 2.5e-3), (4, 3, 5))
+    centres = _centres(grid)
+    vcell = 0.5e-3 ** 3
+    a0, bv = 0.05 * vcell, np.array([4e-9, -6e-9, 3e-9]) * 0.5e-3
+    mid = centres.mean(0)
+    Vc = a0 + (centres - mid) @ bv
+    assert np.all(Vc > 0)
+    rc = np.cbrt(3.0 * Vc / (4.0 * math.pi))
+    lo, hi = centres.min(0), centres.max(0)
+    probes = rng.uniform(lo, hi, (25, 3))
+    x = np.vstack([centres, probes])
+    r = np.concatenate([rc, np.full(len(probes), 1e-9)])
+    nc = len(centres)
+    fluid = dict(rho_f=998.2, mu_f=1e-3, n_min=0.3, voidfrac=oracle.VOID_CIC, u_superficial=1, couple_every=1)
+    p = _params(scenes.material(gamma=0.0), 1e-12, g=(0, 0, 0), grid=grid, fluid=fluid,
+                normal_model=oracle.NORMAL_HERTZ)
+    sim = oracle.OracleSim(p, x, r, bond_at_init=False)
+    sim.set_fluid(np.zeros((nc, 3)), np.zeros((nc, 3)))
+    feat = sim.closure_features()
+    n_exp = 1.0 - (a0 + (probes - mid) @ bv) / vcell
+    np.testing.assert_allclose(feat[nc:, 0], n_exp, rtol=1e-12)
+    np.testing.assert_allclose(feat[:nc, 0], 1.0 - Vc / vcell, rtol=1e-12)
