@@ -64,6 +64,7 @@ enum { DEM_OUTLET_NONE = 0, DEM_OUTLET_CAVITY = 1 };
 enum { DEM_PREC_FP64 = 0, DEM_PREC_MIXED = 1 };
 enum { DEM_CG_SSW = 0, DEM_CG_SSP = 1 };
 enum { DEM_FLAG_AUTO_REGROW = 1u };
+#define DEM_MAX_SIZE_CLASSES 16
 
 /* A wall.  PLANE: p[0..2] unit normal pointing into the particle side, p[3]
  * offset (signed distance of a point x is n.x - p[3]).  CYL_IN: particles
@@ -114,7 +115,12 @@ typedef struct {
   dem_wall walls[DEM_MAX_WALLS];
   int32_t precision;        /* DEM_PREC_FP64 or DEM_PREC_MIXED (same for all samples) */
   int32_t bond_at_init;     /* 1: every touching pair starts bonded (JKR_MOD only)  */
-  int64_t pair_capacity;    /* half-pair capacity; <= 0: automatic                  */
+  int64_t pair_capacity;    /* half-pair capacity; <= 0: automatic (grows at every
+                               rebuild as needed).  > 0 without DEM_FLAG_AUTO_REGROW
+                               (sample 0's value): fixed -- a rebuild that needs
+                               more half pairs, row entries (2x) or wall entries
+                               (n/4 + 256) latches fault bit 1 and the step call
+                               returns DEM_E_CAPACITY; with the flag: initial size */
   uint32_t flags;           /* DEM_FLAG_*                                           */
   int32_t reserved;
 } dem_params;
@@ -122,7 +128,10 @@ typedef struct {
 /* Particle state.  Owned by the caller; on input to dem_init every pointer
  * may be host or device, on output of dem_read_state every pointer may be
  * host or device or NULL (not wanted).  Order of particles is the caller's
- * original order throughout. */
+ * original order throughout.  Everything one step depends on is here: the
+ * state read from one context and given to dem_init continues the run (to
+ * the rounding of the force sums, whose order follows the new context's
+ * binning), and the oracle can be seeded from it. */
 typedef struct {
   int64_t n;                /* number of particles (all samples)                    */
   double* x;                /* 3n positions                                         */
@@ -147,6 +156,14 @@ typedef struct {
   int64_t broken_bonds;     /* bonds broken at point C since init                   */
   int64_t n_alive;
   int64_t n_contacts;       /* active particle-particle contacts                    */
+  /* held state (input to dem_init and output of dem_read_state; NULL: zero /
+   * not wanted) */
+  double* fluid_force;      /* 3n fluid force on each particle (drag of eq 8 plus
+                               buoyancy and pressure gradient) held since the
+                               latest coupling evaluation                          */
+  double* wall_dt;          /* 3 n DEM_MAX_WALLS tangential elongation of every
+                               particle-wall contact, [particle][wall][xyz], wall =
+                               index into its sample's walls                       */
 } dem_state;
 
 typedef struct dem_ctx dem_ctx;
@@ -154,7 +171,10 @@ typedef struct dem_ctx dem_ctx;
 /* Create a context on `device` using HIP stream `hip_stream` (NULL: the
  * default stream).  params: n_samples entries; sample_offsets: n_samples+1
  * increasing particle offsets (NULL allowed when n_samples == 1).  The
- * initial state is copied; the caller keeps ownership.  Validation failures
+ * initial state is copied; the caller keeps ownership.  init->step (>= 0) is
+ * the step count the run resumes at (it decides the coupling schedule, step
+ * modulo couple_every; 0 for a new run); the produced-mass, broken-bond and
+ * size-class counters start at zero.  Validation failures
  * (dt <= 0 or differing between samples, nu outside (-1, 0.5), e outside
  * (0, 1], k < 1, a radius <= 0, a non-finite input, an empty fluid grid while
  * fluid_on, dt above dt_rayleigh_max_frac of the Rayleigh step of eq 37-38
@@ -163,7 +183,18 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples,
                     const int64_t* sample_offsets, const dem_state* init, int32_t device,
                     void* hip_stream);
 
-/* Advance every sample by nsteps DEM steps (stream-ordered). */
+/* Advance every sample by nsteps DEM steps (stream-ordered).  One step
+ * (section 2.1 eq 1-2 integrated by velocity Verlet): first half kick and
+ * drift; outlet removal (section 3.3 eq 40: a centre inside the cavity leaves
+ * as produced sand, its contacts are deleted); the coupling evaluation of
+ * section 2.2 eq 6-11 every couple_every steps (porosity by deposition, Di
+ * Felice drag with the coarse-grained rule, buoyancy and pressure gradient,
+ * the eq 7 cell source); the contact forces of every pair (modified JKR /
+ * Hertz normal law of section 2.3 eq 12-13, damping eq 32-33, tangential
+ * spring with Coulomb cap eq 4 and 35, torque eq 5) and of every wall
+ * contact; gravity; second half kick.  nsteps < 0: DEM_E_INVAL; a latched
+ * fault (see the conventions above) is returned by the call that finds it.
+ * Returns after the steps have completed. */
 dem_status dem_step(dem_ctx* ctx, int64_t nsteps);
 
 /* Coupling exchange with the fluid solver (section 2.2, eq 6-7).
@@ -178,8 +209,13 @@ dem_status dem_step(dem_ctx* ctx, int64_t nsteps);
 dem_status dem_map_fluid(dem_ctx* ctx, const double* u_cell, const double* gradp_cell,
                          double* eps_solid_out, double* fdrag_out);
 
-/* Copy the state out in the caller's particle order (see dem_state).  The
- * pair arrays are not written; use dem_read_pairs. */
+/* Copy the state out in the caller's particle order (see dem_state): the
+ * Newton-Euler state of eq 1-2 (x, v, omega), the forces and torques of the
+ * latest evaluation, the alive flags, the held fluid force and wall history,
+ * and the section 3.3-3.4 observables (produced mass of eq 40, coordination,
+ * broken bonds, kinetic energy).  The pair arrays are not written; use
+ * dem_read_pairs.  Synchronises.  A latched fault is returned after the copy
+ * (DEM_E_NONFINITE or DEM_E_STATE), so the state that raised it can be read. */
 dem_status dem_read_state(dem_ctx* ctx, dem_state* out);
 
 /* Active contact history: pairs with a bond or touching at the last force
@@ -195,6 +231,20 @@ dem_status dem_read_pairs(dem_ctx* ctx, int32_t which, int64_t cap, int64_t* pai
  * coordination number, broken bonds, alive count.  Arrays of n_samples, host. */
 dem_status dem_read_aggregates(dem_ctx* ctx, double* produced_mass, double* coordination,
                                int64_t* broken_bonds, int64_t* n_alive);
+
+/* Produced sand by size class (section 3.3, Fig. 11: produced mass per
+ * diameter group).  dem_set_size_classes: n_edges increasing diameters
+ * (2 <= n_edges <= DEM_MAX_SIZE_CLASSES + 1, host) bound n_edges - 1 classes
+ * [e0, e1), [e1, e2), ... of the fine-scale diameter d/k of the removed
+ * grain (SSW grains count in the class of the fine particles they stand for);
+ * the end classes also take diameters beyond the outer edges.  It zeroes the
+ * per-class counters; later removals are counted (NULL or n_edges 0: off).
+ * dem_read_produced_classes: mass[s * n_classes + c] (kg) of sample s and
+ * class c, host or device array of n_samples x n_classes; DEM_E_STATE if no
+ * classes are set.  Every removal adds its mass exactly (fixed point), so the
+ * counts do not depend on the order of removals. */
+dem_status dem_set_size_classes(dem_ctx* ctx, int32_t n_edges, const double* edges);
+dem_status dem_read_produced_classes(dem_ctx* ctx, double* mass);
 
 /* Query: total fluid cells, pair-list size and capacity, rebuild count, and
  * the candidate margin (skin plus the largest pull-off separation) used by

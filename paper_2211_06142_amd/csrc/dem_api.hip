@@ -58,7 +58,6 @@ struct dem_ctx {
   std::vector<SampleConst> sc;
   std::vector<int64_t> offsets;
   int64_t* d_offsets = nullptr;
-  std::vector<double> dead_mass0;
   NbrSet ns[2];
   WallSet ws[2];
   int live = 0;          // ns[live] / ws[live] is the current list
@@ -83,6 +82,8 @@ struct dem_ctx {
   int* h_flags = nullptr;  // pinned: abort, abort_step, status
   int32_t* h_tot = nullptr;   // pinned: rebuild totals
   double* agg_buf = nullptr;  // aggregate outputs and slice partials
+  int64_t fixed_capacity = 0;   // half-pair capacity given without DEM_FLAG_AUTO_REGROW (0: grows)
+  double* stage_aux = nullptr;   // read-back of the held fluid force and wall history
   std::vector<void*> allocs;
   // kernel-class timing
   int prof = 0;
@@ -214,14 +215,21 @@ void derive(const dem_params& p, const double* x, const double* r, const uint8_t
   }
   double rmin = 1e300, rmax = 0.0, bl[3] = {1e300, 1e300, 1e300}, bh[3] = {-1e300, -1e300, -1e300};
   int64_t nal = 0;
+  double mass = 0.0;
   for (int64_t i = lo; i < hi; ++i) {
     rmin = std::min(rmin, r[i]);
     rmax = std::max(rmax, r[i]);
+    mass += p.rho * (4.0 / 3.0) * kPi * r[i] * r[i] * r[i];
     if (alive && !alive[i]) continue;
     ++nal;
     for (int k = 0; k < 3; ++k) { bl[k] = std::min(bl[k], x[3 * i + k]); bh[k] = std::max(bh[k], x[3 * i + k]); }
   }
   if (nal == 0) { for (int k = 0; k < 3; ++k) { bl[k] = 0.0; bh[k] = 0.0; } }
+  // fixed point of the produced-mass counters: the whole sample stays below
+  // 2^61 units, so the rounded masses of up to 2^30 removals cannot overflow
+  int ex = 0;
+  (void)frexp(mass > 0.0 ? mass : 1.0, &ex);
+  c.pm_scale = ldexp(1.0, 61 - ex);
   if (rmax == 0.0) { rmin = rmax = 1e-6; }
   c.skin = p.skin > 0.0 ? p.skin : 0.4 * rmin;   // tuned: fewer rebuilds, rows barely longer
   // largest pull-off separation |delta_C| = (3/16)^(1/3) X (Table 1), with the
@@ -341,6 +349,8 @@ void prof_collect(dem_ctx* c, int64_t drop_from = INT64_MAX) {
   c->ev_used = 0;
 }
 
+dem_status fault(dem_ctx* c, int st);
+
 // full neighbour-list rebuild from the state in buffer d.cur
 template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) {
   DevState& d = c->d;
@@ -377,6 +387,9 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   const int32_t* tot = c->h_tot;
   NbrSet& ns = c->ns[c->live];
   WallSet& ws = c->ws[c->live];
+  if (c->fixed_capacity > 0 &&
+      (tot[0] > 2 * c->fixed_capacity || tot[1] > c->fixed_capacity || tot[2] > d.n / 4 + 256))
+    return fault(c, kStCapacity);
   if (grow_nbr(c, ns, tot[0], tot[1]) != hipSuccess) return DEM_E_NOMEM;
   if (grow_walls(c, ws, tot[2]) != hipSuccess) return DEM_E_NOMEM;
   ns.nent = tot[0];
@@ -626,6 +639,12 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   if (init->force && fetch(F, init->force, 3 * n) != hipSuccess) return DEM_E_DEVICE;
   if (init->torque && fetch(T, init->torque, 3 * n) != hipSuccess) return DEM_E_DEVICE;
   if (init->alive && fetch(alive, init->alive, n) != hipSuccess) return DEM_E_DEVICE;
+  // held state of a resumed run: fluid force and wall history
+  std::vector<double> FF, WD;
+  if (init->step < 0) return DEM_E_INVAL;
+  if (init->fluid_force && fetch(FF, init->fluid_force, 3 * n) != hipSuccess) return DEM_E_DEVICE;
+  if (init->wall_dt && fetch(WD, init->wall_dt, 3 * (int64_t)DEM_MAX_WALLS * n) != hipSuccess) return DEM_E_DEVICE;
+  if (!finite_all(FF.data(), (int64_t)FF.size()) || !finite_all(WD.data(), (int64_t)WD.size())) return DEM_E_INVAL;
   if (v.empty()) v.assign(3 * n, 0.0);
   if (w.empty()) w.assign(3 * n, 0.0);
   if (F.empty()) F.assign(3 * n, 0.0);
@@ -663,6 +682,7 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
 
   dem_ctx* c = new dem_ctx();
   c->device = device;
+  c->step = init->step;
   c->stream = (hipStream_t)hip_stream;
   c->params.assign(params, params + n_samples);
   c->offsets = offs;
@@ -694,10 +714,6 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   d.ncell = cell_base;
   d.ndual = dual_base;
   if (bin_base > ((int64_t)1 << 31) - 2 || dual_base > ((int64_t)1 << 31) - 2) { delete c; return DEM_E_INVAL; }
-  c->dead_mass0.assign(n_samples, 0.0);
-  for (int s = 0; s < n_samples; ++s)
-    for (int64_t i = offs[s]; i < offs[s + 1]; ++i)
-      if (!alive[i]) c->dead_mass0[s] += params[s].rho * (4.0 / 3.0) * kPi * r[i] * r[i] * r[i];
 
   auto fail = [&](dem_status st) { dem_destroy(c); return st; };
   const int64_t R4B = 4 * (int64_t)c->rsz;
@@ -730,6 +746,7 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   }
   if (!ok) return fail(DEM_E_NOMEM);
   int64_t cap0 = params[0].pair_capacity > 0 ? params[0].pair_capacity : 4 * n + 1024;
+  c->fixed_capacity = !(params[0].flags & DEM_FLAG_AUTO_REGROW) ? std::max<int64_t>(params[0].pair_capacity, 0) : 0;
   for (int q = 0; q < 2; ++q) {
     if (grow_nbr(c, c->ns[q], 2 * cap0, cap0) != hipSuccess) return fail(DEM_E_NOMEM);
     if (grow_walls(c, c->ws[q], n / 4 + 256) != hipSuccess) return fail(DEM_E_NOMEM);
@@ -748,6 +765,8 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.dfill, d.ndual + 2) == hipSuccess;
   ok &= dalloc(c, &d.sc, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.broken, n_samples) == hipSuccess;
+  ok &= dalloc(c, &d.produced_fx, n_samples) == hipSuccess;
+  ok &= dalloc(c, &d.produced_cls, (int64_t)n_samples * DEM_MAX_SIZE_CLASSES) == hipSuccess;
   ok &= dalloc(c, &d.abort, 4) == hipSuccess;   // abort, abort_step, status: adjacent
   d.abort_step = d.abort + 1;
   d.status = d.abort + 2;
@@ -766,7 +785,7 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   // upload in the caller's order into buffer 0
   std::vector<double4> hx(n), hv(n);
   std::vector<int32_t> hs(n), ho(n);
-  std::vector<char> hw(n * R4B), hF(n * R4B), hT(n * R4B);
+  std::vector<char> hw(n * R4B), hF(n * R4B), hT(n * R4B), hFF(n * R4B, 0);
   for (int s = 0; s < n_samples; ++s) {
     const dem_params& p = params[s];
     for (int64_t i = offs[s]; i < offs[s + 1]; ++i) {
@@ -780,10 +799,13 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
         ((double4*)hw.data())[i] = make_double4(w[3 * i], w[3 * i + 1], w[3 * i + 2], 1.0 / I);
         ((double4*)hF.data())[i] = make_double4(F[3 * i], F[3 * i + 1], F[3 * i + 2], 0.0);
         ((double4*)hT.data())[i] = make_double4(T[3 * i], T[3 * i + 1], T[3 * i + 2], 0.0);
+        if (!FF.empty()) ((double4*)hFF.data())[i] = make_double4(FF[3 * i], FF[3 * i + 1], FF[3 * i + 2], 0.0);
       } else {
         ((float4*)hw.data())[i] = make_float4((float)w[3 * i], (float)w[3 * i + 1], (float)w[3 * i + 2], (float)(1.0 / I));
         ((float4*)hF.data())[i] = make_float4((float)F[3 * i], (float)F[3 * i + 1], (float)F[3 * i + 2], 0.f);
         ((float4*)hT.data())[i] = make_float4((float)T[3 * i], (float)T[3 * i + 1], (float)T[3 * i + 2], 0.f);
+        if (!FF.empty())
+          ((float4*)hFF.data())[i] = make_float4((float)FF[3 * i], (float)FF[3 * i + 1], (float)FF[3 * i + 2], 0.f);
       }
     }
   }
@@ -810,7 +832,7 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   up &= hipMemcpyAsync(d.alive[0], alive.data(), n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.frc, hF.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.trq, hT.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
-  up &= hipMemsetAsync(d.fdr, 0, n * R4B, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.fdr, hFF.data(), n * R4B, hipMemcpyHostToDevice, st) == hipSuccess;
   // the bucket sorts expect their counters at zero (each sort clears them after use)
   up &= hipMemsetAsync(d.bucket_cnt, 0, sizeof(int32_t) * nbk, st) == hipSuccess;
   up &= hipMemsetAsync(d.bucket_fill, 0, sizeof(int32_t) * nbk, st) == hipSuccess;
@@ -825,6 +847,9 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   up &= hipMemcpyAsync(d.dual_sink, dsink.data(), d.ndual + 2, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(c->d_offsets, offs.data(), sizeof(int64_t) * (n_samples + 1), hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemsetAsync(d.broken, 0, sizeof(unsigned long long) * n_samples, st) == hipSuccess;
+  up &= hipMemsetAsync(d.produced_fx, 0, sizeof(unsigned long long) * n_samples, st) == hipSuccess;
+  up &= hipMemsetAsync(d.produced_cls, 0, sizeof(unsigned long long) * n_samples * DEM_MAX_SIZE_CLASSES, st) ==
+        hipSuccess;
   up &= hipMemsetAsync(d.status, 0, sizeof(int), st) == hipSuccess;
   up &= hipMemsetAsync(d.abort, 0, sizeof(int), st) == hipSuccess;
   up &= hipMemsetAsync(d.eps, 0, sizeof(double) * nc, st) == hipSuccess;
@@ -880,8 +905,33 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
     }
     old.nent = (int64_t)nbr.size();
     old.nslots = npair;
-    up &= hipMemsetAsync(wold.wrow, 0, sizeof(int32_t) * (n + 1), st) == hipSuccess;
-    wold.n = 0;
+    // the given wall history as the "previous" wall list: one entry per
+    // (particle, wall) with a nonzero elongation, carried by wall id
+    std::vector<int32_t> wrow(n + 1, 0), wid;
+    std::vector<char> wdt;
+    std::vector<uint8_t> wfl;
+    for (int s = 0; s < n_samples; ++s)
+      for (int64_t i = offs[s]; i < offs[s + 1]; ++i) {
+        for (int wl = 0; !WD.empty() && wl < params[s].n_walls; ++wl) {
+          const double* h = &WD[3 * (i * DEM_MAX_WALLS + wl)];
+          if (h[0] == 0.0 && h[1] == 0.0 && h[2] == 0.0) continue;
+          wid.push_back(wl);
+          wfl.push_back(2);
+          size_t at = wdt.size();
+          wdt.resize(at + R4B);
+          if (c->fp64) *(double4*)(wdt.data() + at) = make_double4(h[0], h[1], h[2], 0.0);
+          else *(float4*)(wdt.data() + at) = make_float4((float)h[0], (float)h[1], (float)h[2], 0.f);
+        }
+        wrow[i + 1] = (int32_t)wid.size();
+      }
+    if (grow_walls(c, wold, (int64_t)wid.size()) != hipSuccess) return fail(DEM_E_NOMEM);
+    up &= hipMemcpyAsync(wold.wrow, wrow.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st) == hipSuccess;
+    if (!wid.empty()) {
+      up &= hipMemcpyAsync(wold.wid, wid.data(), sizeof(int32_t) * wid.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(wold.wdt, wdt.data(), wdt.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+      up &= hipMemcpyAsync(wold.wfl, wfl.data(), wfl.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    }
+    wold.n = (int64_t)wid.size();
     up &= hipStreamSynchronize(st) == hipSuccess;
   }
   if (!up) return fail(DEM_E_DEVICE);
@@ -943,7 +993,6 @@ static dem_status aggregates(dem_ctx* c, std::vector<double>& pm, std::vector<do
   ok &= hipMemcpy(nc.data(), dnc, sizeof(long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
   ok &= hipMemcpy(na.data(), dna, sizeof(long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
   ok &= hipMemcpy(br.data(), c->d.broken, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost) == hipSuccess;
-  for (int s = 0; s < ns; ++s) pm[s] -= c->dead_mass0[s];
   return ok ? DEM_OK : DEM_E_DEVICE;
 }
 
@@ -960,15 +1009,32 @@ dem_status dem_read_state(dem_ctx* c, dem_state* out) {
   double* sw = sv + 3 * n;
   double* sF = sw + 3 * n;
   double* sT = sF + 3 * n;
-  if (c->fp64) launch_unpermute<double>(c->d, sx, sv, sw, sF, sT, c->stage_alive, c->stream);
-  else launch_unpermute<float>(c->d, sx, sv, sw, sF, sT, c->stage_alive, c->stream);
+  double *sFF = nullptr, *sWD = nullptr;
+  if (out->fluid_force || out->wall_dt) {
+    if (!c->stage_aux &&
+        hipMalloc((void**)&c->stage_aux, sizeof(double) * (3 + 3 * DEM_MAX_WALLS) * std::max<int64_t>(n, 1)) !=
+            hipSuccess)
+      return DEM_E_NOMEM;
+    sFF = c->stage_aux;
+    sWD = sFF + 3 * n;
+  }
   hipStream_t s = c->stream;
+  if (c->fp64) launch_unpermute<double>(c->d, sx, sv, sw, sF, sT, c->stage_alive, sFF, s);
+  else launch_unpermute<float>(c->d, sx, sv, sw, sF, sT, c->stage_alive, sFF, s);
+  if (out->wall_dt && n > 0) {
+    HIPCHK(hipMemsetAsync(sWD, 0, sizeof(double) * 3 * DEM_MAX_WALLS * n, s));
+    if (c->fp64) launch_unpermute_walls<double>(c->d, sWD, s);
+    else launch_unpermute_walls<float>(c->d, sWD, s);
+  }
   if (out->x) HIPCHK(hipMemcpyAsync(out->x, sx, sizeof(double) * 3 * n, hipMemcpyDefault, s));
   if (out->v) HIPCHK(hipMemcpyAsync(out->v, sv, sizeof(double) * 3 * n, hipMemcpyDefault, s));
   if (out->omega) HIPCHK(hipMemcpyAsync(out->omega, sw, sizeof(double) * 3 * n, hipMemcpyDefault, s));
   if (out->force) HIPCHK(hipMemcpyAsync(out->force, sF, sizeof(double) * 3 * n, hipMemcpyDefault, s));
   if (out->torque) HIPCHK(hipMemcpyAsync(out->torque, sT, sizeof(double) * 3 * n, hipMemcpyDefault, s));
   if (out->alive) HIPCHK(hipMemcpyAsync(out->alive, c->stage_alive, n, hipMemcpyDefault, s));
+  if (out->fluid_force) HIPCHK(hipMemcpyAsync(out->fluid_force, sFF, sizeof(double) * 3 * n, hipMemcpyDefault, s));
+  if (out->wall_dt)
+    HIPCHK(hipMemcpyAsync(out->wall_dt, sWD, sizeof(double) * 3 * DEM_MAX_WALLS * n, hipMemcpyDefault, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<double> pm, ke;
   std::vector<long long> nc, na;
@@ -1066,6 +1132,38 @@ dem_status dem_read_pairs(dem_ctx* c, int32_t which, int64_t cap, int64_t* pair_
     if (pair_dt) HIPCHK(hipMemcpy(pair_dt, odt.data(), sizeof(double) * 3 * wr, hipMemcpyDefault));
     if (pair_bonded) HIPCHK(hipMemcpy(pair_bonded, ob.data(), wr, hipMemcpyDefault));
   }
+  return DEM_OK;
+}
+
+dem_status dem_set_size_classes(dem_ctx* c, int32_t n_edges, const double* edges) {
+  if (!c) return DEM_E_INVAL;
+  if (n_edges != 0 && (!edges || n_edges < 2 || n_edges > DEM_MAX_SIZE_CLASSES + 1)) return DEM_E_INVAL;
+  for (int k = 0; k < n_edges; ++k)
+    if (!std::isfinite(edges[k]) || !(edges[k] >= 0.0) || (k > 0 && !(edges[k] > edges[k - 1]))) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  DevState& d = c->d;
+  HIPCHK(hipMemsetAsync(d.produced_cls, 0, sizeof(unsigned long long) * d.nsamples * DEM_MAX_SIZE_CLASSES,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  d.ncls = edges ? n_edges - 1 : 0;
+  for (int k = 0; k <= DEM_MAX_SIZE_CLASSES; ++k) d.cls_edge[k] = k < n_edges && edges ? edges[k] : 0.0;
+  return DEM_OK;
+}
+
+dem_status dem_read_produced_classes(dem_ctx* c, double* mass) {
+  if (!c || !mass) return DEM_E_INVAL;
+  DevState& d = c->d;
+  if (d.ncls <= 0) return DEM_E_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const int ns = d.nsamples;
+  std::vector<unsigned long long> q((size_t)ns * DEM_MAX_SIZE_CLASSES);
+  HIPCHK(hipMemcpy(q.data(), d.produced_cls, sizeof(unsigned long long) * q.size(), hipMemcpyDeviceToHost));
+  std::vector<double> out((size_t)ns * d.ncls);
+  for (int s = 0; s < ns; ++s)
+    for (int k = 0; k < d.ncls; ++k) out[(size_t)s * d.ncls + k] = (double)q[(size_t)s * DEM_MAX_SIZE_CLASSES + k] / c->sc[s].pm_scale;
+  HIPCHK(hipMemcpy(mass, out.data(), sizeof(double) * out.size(), hipMemcpyDefault));
   return DEM_OK;
 }
 
@@ -1215,6 +1313,7 @@ void dem_destroy(dem_ctx* c) {
     if (p) (void)hipFree(p);
   if (c->stage) (void)hipFree(c->stage);
   if (c->stage_alive) (void)hipFree(c->stage_alive);
+  if (c->stage_aux) (void)hipFree(c->stage_aux);
   if (c->h_flags) (void)hipHostFree(c->h_flags);
   if (c->h_tot) (void)hipHostFree(c->h_tot);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

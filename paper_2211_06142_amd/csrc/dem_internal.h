@@ -61,6 +61,8 @@ struct SampleConst {
   int64_t bin_base;               // first bin; the sample's dead bucket is bin_base + nbins
   double margin;                  // candidate margin: skin + largest pull-off separation
   double skin;
+  double pm_scale;                // produced mass counts in units of 1 / pm_scale kg (a power
+                                  // of two: the sample's whole mass stays below 2^61 units)
   double g[3];
   int outlet_kind;
   double outlet[4];
@@ -144,6 +146,12 @@ struct DevState {
   // per-sample, status
   SampleConst* sc;
   unsigned long long* broken;      // per sample
+  // produced sand, exact: each removal adds its mass rounded to 1 / pm_scale
+  // (integer sums do not depend on the order of the removals)
+  unsigned long long* produced_fx;    // per sample
+  unsigned long long* produced_cls;   // per sample x DEM_MAX_SIZE_CLASSES (fine diameter d/k)
+  int ncls;                           // size classes (0: off)
+  double cls_edge[DEM_MAX_SIZE_CLASSES + 1];
   int* status;
   int* abort;                      // set when a rebuild is due before the next step
   int* abort_step;
@@ -187,7 +195,8 @@ hipStream_t mlp_stream(const dem_mlp* n);
 
 // read-back
 template <typename R> void launch_unpermute(DevState& d, double* x, double* v, double* w, double* F,
-                                            double* T, uint8_t* alive, hipStream_t s);
+                                            double* T, uint8_t* alive, double* fluid_force, hipStream_t s);
+template <typename R> void launch_unpermute_walls(DevState& d, double* wall_dt, hipStream_t s);
 int64_t aggregate_scratch_doubles(int nsamples);
 void launch_aggregate_impl(DevState& d, const int64_t* soff, double* produced, double* kinetic,
                            long long* contacts, long long* nalive, double* partial, int fp64, hipStream_t s);

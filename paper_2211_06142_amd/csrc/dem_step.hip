@@ -15,9 +15,24 @@
 
 namespace dem {
 
+// Produced sand (eq 40): the removed mass, rounded once to the sample's fixed
+// point, is added to the sample's counter and to the counter of its size class
+// (by the fine-scale diameter d/k the grain stands for).
+__device__ inline void count_removal(const DevState& d, const SampleConst& c, int s, double r) {
+  const double m = c.rho * (4.0 / 3.0) * M_PI * r * r * r;
+  const unsigned long long q = __double2ull_rn(m * c.pm_scale);
+  atomicAdd(&d.produced_fx[s], q);
+  if (d.ncls > 0) {
+    const double df = 2.0 * r / c.kcg;
+    int k = 0;
+    while (k + 1 < d.ncls && df >= d.cls_edge[k + 1]) ++k;
+    atomicAdd(&d.produced_cls[(int64_t)s * DEM_MAX_SIZE_CLASSES + k], q);
+  }
+}
+
 template <typename R>
-__device__ inline void finish_drift(const DevState& d, const SampleConst& c, int64_t i, int out, int64_t next_step,
-                                    double4 p, double4 v, R4<R> w) {
+__device__ inline void finish_drift(const DevState& d, const SampleConst& c, int s, int64_t i, int out,
+                                    int64_t next_step, double4 p, double4 v, R4<R> w) {
   const double dt = d.dt;
   double sx = dt * v.x, sy = dt * v.y, sz = dt * v.z;
   p.x += sx; p.y += sy; p.z += sz;
@@ -35,6 +50,7 @@ __device__ inline void finish_drift(const DevState& d, const SampleConst& c, int
     double rc = c.outlet[2];
     if (ex * ex + ey * ey < rc * rc) {
       alive = 0;
+      count_removal(d, c, s, p.w);
       gst(G((R4<R>*)d.frc) + i, mk4<R>(0, 0, 0, 0));
       gst(G((R4<R>*)d.trq) + i, mk4<R>(0, 0, 0, 0));
     }
@@ -65,7 +81,8 @@ __global__ void k_prologue(DevState d, StepArgs a) {
     d.alive[out][i] = 0;
     return;
   }
-  const SampleConst& c = sample_const(d.sc, d.sample[i]);
+  const int s = d.sample[i];
+  const SampleConst& c = sample_const(d.sc, s);
   const R4<R> F = ((const R4<R>*)d.frc)[i];
   const R4<R> T = ((const R4<R>*)d.trq)[i];
   const double hdt = 0.5 * d.dt;
@@ -76,7 +93,7 @@ __global__ void k_prologue(DevState d, StepArgs a) {
   w.x += hdtR * T.x * w.w;
   w.y += hdtR * T.y * w.w;
   w.z += hdtR * T.z * w.w;
-  finish_drift<R>(d, c, i, out, a.step, p, v, w);
+  finish_drift<R>(d, c, s, i, out, a.step, p, v, w);
 }
 
 template <typename R> void launch_prologue(DevState& d, StepArgs a, hipStream_t s) {
@@ -347,7 +364,7 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
   w.x += hdtR * T[0] * w.w;
   w.y += hdtR * T[1] * w.w;
   w.z += hdtR * T[2] * w.w;
-  finish_drift<R>(d, c, i, out, a.step + 1, pi, v, w);
+  finish_drift<R>(d, c, s, i, out, a.step + 1, pi, v, w);
 }
 
 // A launch exits at entry when a rebuild is due at or before its step: the

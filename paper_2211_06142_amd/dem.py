@@ -22,6 +22,7 @@ DEM_OUTLET_NONE, DEM_OUTLET_CAVITY = 0, 1
 DEM_PREC_FP64, DEM_PREC_MIXED = 0, 1
 DEM_CG_SSW, DEM_CG_SSP = 0, 1
 DEM_FLAG_AUTO_REGROW = 1
+DEM_MAX_SIZE_CLASSES = 16
 
 DEM_PROF_PROLOGUE, DEM_PROF_REBUILD, DEM_PROF_FLUID, DEM_PROF_STEP, DEM_PROF_N = 0, 1, 2, 3, 4
 PROF_NAMES = ["prologue", "rebuild", "fluid", "step"]
@@ -30,7 +31,8 @@ EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "de
                   "dem_read_aggregates", "dem_info", "dem_request_rebuild", "dem_destroy", "dem_status_str",
                   "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile",
                   "dem_read_fault", "dem_mlp_create", "dem_mlp_destroy", "dem_mlp_set_params", "dem_mlp_get_params",
-                  "dem_mlp_forward", "dem_mlp_grad", "dem_mlp_train_step", "dem_set_closure", "dem_read_closure", "dem_set_graphs", "dem_set_lanes"])
+                  "dem_mlp_forward", "dem_mlp_grad", "dem_mlp_train_step", "dem_set_closure", "dem_read_closure", "dem_set_graphs", "dem_set_lanes",
+                  "dem_set_size_classes", "dem_read_produced_classes"])
 MLP_NPARAMS = 8898
 
 
@@ -77,6 +79,7 @@ class dem_state(ctypes.Structure):
         ("kinetic", ctypes.c_double),
         ("step", ctypes.c_int64), ("broken_bonds", ctypes.c_int64), ("n_alive", ctypes.c_int64),
         ("n_contacts", ctypes.c_int64),
+        ("fluid_force", ctypes.c_void_p), ("wall_dt", ctypes.c_void_p),
     ]
 
 
@@ -147,6 +150,10 @@ def lib():
         L.dem_set_closure.argtypes = [vp, vp, vp]
         L.dem_read_closure.restype = i32
         L.dem_read_closure.argtypes = [vp, vp, vp, vp]
+        L.dem_set_size_classes.restype = i32
+        L.dem_set_size_classes.argtypes = [vp, i32, vp]
+        L.dem_read_produced_classes.restype = i32
+        L.dem_read_produced_classes.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -301,6 +308,14 @@ def dem_mlp_train_step(mlp, x_ptr, t_ptr, batch, lr):
     return rc, loss.value
 
 
+def dem_set_size_classes(ctx, n_edges, edges_ptr):
+    return lib().dem_set_size_classes(ctx, int(n_edges), edges_ptr)
+
+
+def dem_read_produced_classes(ctx, mass_ptr):
+    return lib().dem_read_produced_classes(ctx, mass_ptr)
+
+
 def dem_set_closure(ctx, mlp, norm_ptr):
     return lib().dem_set_closure(ctx, mlp, norm_ptr)
 
@@ -426,7 +441,8 @@ class Simulation:
     computation happens in libdem.so."""
 
     def __init__(self, params, x, r, v=None, w=None, F=None, T=None, alive=None, pairs=None, pair_dt=None,
-                 pair_bonded=None, sample_offsets=None, device=0, stream=None):
+                 pair_bonded=None, sample_offsets=None, device=0, stream=None, fluid_force=None, wall_dt=None,
+                 step=0, size_edges=None):
         import torch
         self.torch = torch
         dev = torch.device("cuda", device)
@@ -441,9 +457,11 @@ class Simulation:
             return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(shape), device=dev)
 
         bufs = dict(x=t64(x, (n, 3)), v=t64(v, (n, 3)), omega=t64(w, (n, 3)), force=t64(F, (n, 3)),
-                    torque=t64(T, (n, 3)), radius=t64(r, (n,)))
+                    torque=t64(T, (n, 3)), radius=t64(r, (n,)), fluid_force=t64(fluid_force, (n, 3)),
+                    wall_dt=t64(wall_dt, (n, DEM_MAX_WALLS, 3)))
         st = dem_state()
         st.n = n
+        st.step = int(step)
         for k, t in bufs.items():
             setattr(st, k, None if t is None else t.data_ptr())
         al = None
@@ -474,6 +492,8 @@ class Simulation:
         _check(rc, "dem_init")
         self.ctx = ctx
         self.ncell = self.info()["ncell"]
+        if size_edges is not None:
+            self.set_size_classes(size_edges)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -506,7 +526,9 @@ class Simulation:
         _check(dem_map_fluid(self.ctx, None, None, eps.data_ptr(), fd.data_ptr()), "dem_map_fluid")
         return eps[:self.ncell].cpu().numpy(), fd[:3 * self.ncell].reshape(-1, 3).cpu().numpy()
 
-    def state(self):
+    def state(self, held=False):
+        """positions, velocities, forces, alive flags and scalars; held=True
+        adds the held fluid force (n x 3) and the wall history (n x 8 x 3)"""
         torch = self.torch
         n = self.n
         out = {k: torch.zeros((n, 3), dtype=torch.float64, device=self.dev) for k in ("x", "v", "w", "F", "T")}
@@ -515,6 +537,10 @@ class Simulation:
         st.x, st.v, st.omega = out["x"].data_ptr(), out["v"].data_ptr(), out["w"].data_ptr()
         st.force, st.torque = out["F"].data_ptr(), out["T"].data_ptr()
         st.alive = alive.data_ptr()
+        if held:
+            out["fluid_force"] = torch.zeros((n, 3), dtype=torch.float64, device=self.dev)
+            out["wall_dt"] = torch.zeros((n, DEM_MAX_WALLS, 3), dtype=torch.float64, device=self.dev)
+            st.fluid_force, st.wall_dt = out["fluid_force"].data_ptr(), out["wall_dt"].data_ptr()
         _check(dem_read_state(self.ctx, st), "dem_read_state")
         res = {k: t.cpu().numpy() for k, t in out.items()}
         res["alive"] = alive.cpu().numpy()
@@ -545,6 +571,22 @@ class Simulation:
         _check(dem_read_aggregates(self.ctx, pm.ctypes.data, z.ctypes.data, bb.ctypes.data, na.ctypes.data),
                "dem_read_aggregates")
         return {"produced_mass": pm, "coordination": z, "broken_bonds": bb, "n_alive": na}
+
+    def set_size_classes(self, edges):
+        """produced-sand size classes by fine-scale diameter (edges in m)"""
+        if edges is None:
+            _check(dem_set_size_classes(self.ctx, 0, None), "dem_set_size_classes")
+            self.n_classes = 0
+            return
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+        _check(dem_set_size_classes(self.ctx, e.size, e.ctypes.data), "dem_set_size_classes")
+        self.n_classes = e.size - 1
+
+    def produced_classes(self):
+        """produced mass per sample and size class (n_samples x n_classes), kg"""
+        m = np.zeros((len(self.params), self.n_classes))
+        _check(dem_read_produced_classes(self.ctx, m.ctypes.data), "dem_read_produced_classes")
+        return m
 
     def info(self):
         rc, inf = dem_info(self.ctx)

@@ -346,3 +346,32 @@ def c3(n_samples=256, seed=SEED0 + 3):
     ns, gam = c3_sizes(n_samples, seed)
     base = c1()
     return [c3_crop(s, int(ns[s]), float(gam[s]), base) for s in range(n_samples)]
+
+
+def c1_ring(r_crop=2.8e-3, U_cav=2.0, outlet_shift=0.06e-3, v_in=0.3, precision="fp64"):
+    """A ring of the settled c1 bed next to the cavity, for parity runs in which
+    spheres leave: the spheres whose centres lie within r_crop of the axis (about
+    5 500), an outer cylinder wall one largest radius beyond them, c1's floor and
+    top plate, c1's grid with the radial inflow at U_cav, the outlet radius moved
+    out by outlet_shift (so that the innermost spheres sit just outside it), and an
+    inward radial start velocity v_in (returned as "v")."""
+    base = c1()
+    x, r = base["x"], base["r"]
+    rho = np.hypot(x[:, 0], x[:, 1])
+    sel = rho < r_crop
+    xs, rs = x[sel].copy(), r[sel].copy()
+    R = r_crop + rs.max()
+    walls = [(WALL_CYL_IN, (0.0, 0.0, R))] + [wl for wl in base["walls"] if wl[0] == WALL_PLANE]
+    grid = base["grid"]
+    r_cav = 2e-3
+    kappa = kozeny_carman(PSD["median"] * math.exp(0.5 * PSD["sigma"] ** 2), 0.41)
+    u, gp = radial_darcy_field(grid, r_cav, 12e-3, U_cav, WATER["mu_f"], kappa)
+    rr = np.hypot(xs[:, 0], xs[:, 1])
+    v = np.zeros_like(xs)
+    v[:, 0] = -v_in * xs[:, 0] / rr
+    v[:, 1] = -v_in * xs[:, 1] / rr
+    return dict(name="c1_ring", x=xs, r=rs, v=v, material=dict(MATERIAL), k=1.0, scheme="ssw", walls=walls,
+                grid=grid, u_cell=u, gradp_cell=gp,
+                fluid=dict(WATER, n_min=N_MIN, voidfrac=0, u_superficial=1, couple_every=COUPLE_EVERY),
+                outlet=(0.0, 0.0, r_cav + outlet_shift), dt=DT, g=GRAV, sha256=base["sha256"],
+                precision=precision, n_fine=len(rs), bed_top=base["bed_top"])

@@ -6,9 +6,9 @@ Tolerances.  The GPU rounds the inputs, weights and every hidden activation
 to bfloat16 (unit roundoff 2^-9) and accumulates in FP32; the oracle gets the
 same bfloat16 weights and FP32 biases and computes in FP64.  Over 20 random
 He-initialised networks and 4000 standard-normal inputs each, a model of those
-rounding points gives |dy| <= 0.027 (1 + |y|); the tests allow 0.08 (1 + |y|).
+rounding points gives |dy| <= 0.027 (1 + |y|); the tests allow that bound.
 Gradients pass through four more roundings (the backward signals) and are
-compared per layer in relative L2 norm (<= 0.06) and direction (cosine >= 0.998).
+compared per layer in relative L2 norm (<= 0.02) and direction (cosine >= 0.9999).
 """
 import math
 
@@ -52,7 +52,9 @@ def test_forward_matches_oracle(batch):
     y = net.forward(x)
     yo = mlp.forward(oracle_view(p), mlp.bf16_round(x))
     assert y.shape == (batch, 2)
-    assert np.all(np.abs(y - yo) <= 0.08 * (1.0 + np.abs(yo)))
+    err = np.max(np.abs(y - yo) / (1.0 + np.abs(yo)))
+    print("forward batch %d: max |dy| / (1 + |y|) = %.4f" % (batch, err))
+    assert err <= 0.027
 
 
 def test_forward_special_cases():
@@ -85,10 +87,13 @@ def test_gradient_matches_oracle(batch):
     loss, g = net.grad(x, t)
     lo, go = mlp.grad(oracle_view(p), mlp.bf16_round(x), t)
     assert loss == pytest.approx(lo, rel=0.05)
-    for sl in LAYER_SLICES:
+    for li, sl in enumerate(LAYER_SLICES):
         a, b = g[sl].astype(np.float64), go[sl]
-        assert np.linalg.norm(a - b) <= 0.06 * np.linalg.norm(b)
-        assert a @ b >= 0.998 * np.linalg.norm(a) * np.linalg.norm(b)
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+        print("gradient batch %d layer %d: relative L2 %.4f, cosine %.6f" % (batch, li, rel, cos))
+        assert rel <= 0.02
+        assert cos >= 0.9999
 
 
 def test_gradient_is_deterministic():
@@ -177,7 +182,9 @@ def test_closure_features_and_factors_match_oracle():
     cdo, cco = o.closure_factors()
     yo = np.log(np.stack([cdo, cco], axis=1))
     yg = np.log(np.stack([cl["c_drag"], cl["c_coh"]], axis=1))
-    assert np.all(np.abs(yg - yo) <= 0.08 * (1.0 + np.abs(yo)))
+    err = np.max(np.abs(yg - yo) / (1.0 + np.abs(yo)))
+    print("closure factors: max |dy| / (1 + |y|) = %.4f" % err)
+    assert err <= 0.027
     assert np.all((cl["c_drag"] >= 0.5) & (cl["c_drag"] <= 2.0))
     assert np.all((cl["c_coh"] >= 0.5) & (cl["c_coh"] <= 2.0))
 

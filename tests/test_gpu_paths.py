@@ -1,0 +1,239 @@
+"""GPU path against the FP64 oracle on the options and regimes the workloads
+of the benchmark do not reach: rolling resistance, centroid deposition, an
+interstitial (not superficial) fluid velocity, a walled cylinder in FP64, and
+outlet removal of some spheres while their bonded neighbours stay, across
+list rebuilds (section 3.3 eq 40).  Also the exact produced-mass and
+size-class counters (section 3.3 Fig. 11), determinism with removals, and
+resuming a run from its held state.  FP64 bar: 1e-12 of each particle's force
+scale; sets, flags and counts exact."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2211_06142_amd import dem  # noqa: E402
+
+
+def oracle_for(wk, x=None, r=None, mat=None, **kw):
+    m = cg.scale_material(mat or wk["material"], wk.get("k", 1.0))
+    op = oracle.make_params(m, wk["dt"], g=wk["g"], walls=wk["walls"], grid=wk["grid"], fluid=wk["fluid"],
+                            outlet=wk["outlet"])
+    sim = oracle.OracleSim(op, wk["x"] if x is None else x, wk["r"] if r is None else r, **kw)
+    if wk["fluid"] is not None:
+        sim.set_fluid(wk["u_cell"], wk["gradp_cell"])
+    return sim
+
+
+def gpu_for(wk, precision, mat=None, skin=0.0, **kw):
+    ww = dict(wk)
+    if mat is not None:
+        ww["material"] = mat
+    p = dem.params_from_workload(ww, precision=precision, skin=skin)
+    sim = dem.Simulation(p, wk["x"], wk["r"], **kw)
+    if wk["fluid"] is not None:
+        sim.map_fluid(wk["u_cell"], wk["gradp_cell"])
+    return sim
+
+
+def scaled_err(a, b, scale):
+    return np.max(np.linalg.norm(a - b, axis=1) / (scale + 1e-300))
+
+
+def compare_fp64(g, o, tol=1e-12, what="", broken_before=0):
+    gs, os_ = g.state(), o.state()
+    np.testing.assert_array_equal(gs["alive"], os_["alive"])
+    ef = scaled_err(gs["F"], os_["F"], os_["fscale"])
+    et = scaled_err(gs["T"], os_["T"], os_["tscale"])
+    print("%s: scaled force error %.2e, torque %.2e" % (what, ef, et))
+    assert ef < tol and et < tol
+    xs = np.abs(os_["x"]).max()
+    np.testing.assert_allclose(gs["x"], os_["x"], rtol=0, atol=1e-15 * xs)
+    gp, op_ = g.pairs(which=0), o.pairs()
+    np.testing.assert_array_equal(gp["pairs"], op_["pairs"])
+    np.testing.assert_array_equal(gp["bonded"], op_["bonded"])
+    dts = np.abs(op_["dt"]).max() + 1e-30
+    np.testing.assert_allclose(gp["dt"], op_["dt"], rtol=0, atol=1e-10 * dts)
+    sc = o.scalars()
+    assert gs["broken_bonds"] - broken_before == sc["broken_bonds"]
+    assert gs["n_contacts"] == sc["n_contacts"]
+    return gs, sc
+
+
+def c0_moving(n=2000, sigma=0.3, seed=5):
+    w = synth.c0()
+    w = dict(w)
+    w["x"], w["r"] = w["x"][:n], w["r"][:n]
+    v = np.random.default_rng(seed).normal(0.0, sigma, (n, 3))
+    return w, v
+
+
+# ---------------------------------------------------------------------------
+# options
+# ---------------------------------------------------------------------------
+def test_rolling_resistance_fp64():
+    """mu_roll > 0: the constant directional rolling torque on every contact
+    (with the walls too), spinning spheres"""
+    w, v = c0_moving()
+    wv = np.random.default_rng(6).normal(0.0, 2e3, v.shape)
+    mat = dict(w["material"], mu_roll=0.2)
+    g = gpu_for(w, "fp64", mat=mat, v=v, w=wv)
+    o = oracle_for(w, mat=mat, v=v, w=wv, bond_at_init=True)
+    for _ in range(3):
+        g.step(10)
+        o.step(10)
+        compare_fp64(g, o)
+
+
+@pytest.mark.parametrize("voidfrac,superficial", [(dem.DEM_VOID_CENTROID, 1), (dem.DEM_VOID_CIC, 0),
+                                                   (dem.DEM_VOID_CENTROID, 0)])
+def test_fluid_options_fp64(voidfrac, superficial):
+    """centroid deposition and an interstitial fluid velocity: cell porosity
+    and drag source, then 21 steps (three coupling evaluations)"""
+    w, v = c0_moving()
+    w["fluid"] = dict(w["fluid"], voidfrac=voidfrac, u_superficial=superficial)
+    g = gpu_for(w, "fp64", v=v)
+    o = oracle_for(w, v=v, bond_at_init=True)
+    g.step(1)
+    o.step(1)
+    eps, fd = g.fluid_out()
+    of = o.fluid()
+    np.testing.assert_allclose(eps, of["eps_s"], rtol=1e-12, atol=1e-15)
+    fs = np.abs(of["fdrag_cell"]).max()
+    np.testing.assert_allclose(fd, of["fdrag_cell"], rtol=0, atol=1e-12 * fs)
+    g.step(20)
+    o.step(20)
+    compare_fp64(g, o)
+
+
+# ---------------------------------------------------------------------------
+# the cylinder: walls, outlet, removal with bonded neighbours staying
+# ---------------------------------------------------------------------------
+def test_ring_walls_and_outlet_removal_across_rebuilds_fp64():
+    """The ring of the c1 bed next to the cavity in FP64, with an inward start
+    velocity and strong radial inflow: spheres cross the outlet while bonded
+    neighbours stay, bonds break, and the list is rebuilt on its own several
+    times.  Every 40 steps: alive flags, pair and bond sets, bond breaks and
+    contact counts exactly; produced mass (an exact counter on the GPU; the
+    oracle sums in index order) to rounding; forces and histories to the
+    per-step FP64 bar times the growth of rounding differences along a
+    trajectory this violent (1e-9 after up to 200 steps).  At the end one step
+    from one identical state (the oracle seeded from the GPU) at the per-step
+    bar, 1e-12."""
+    w = synth.c1_ring()
+    rmin = float(w["r"].min())
+    g = gpu_for(w, "fp64", skin=0.2 * rmin, v=w["v"])
+    o = oracle_for(w, v=w["v"], bond_at_init=True)
+    b0 = o.pairs()
+    bonded0 = b0["pairs"][b0["bonded"] == 1]
+    for k in range(5):
+        g.step(40)
+        o.step(40)
+        gs, sc = compare_fp64(g, o, tol=1e-9, what="ring step %d" % (40 * (k + 1)))
+        assert gs["produced_mass"] == pytest.approx(sc["produced_mass"], rel=1e-13, abs=0)
+    al = gs["alive"]
+    assert g.info()["rebuilds"] >= 3
+    assert 100 < int((al == 0).sum()) < len(al) // 2
+    # bonded pairs of the start with one partner produced and the other still in place
+    assert np.sum(al[bonded0[:, 0]] != al[bonded0[:, 1]]) > 100
+    s = g.state(held=True)
+    pr = g.pairs(which=0)
+    nw = len(w["walls"])
+    o2 = oracle_for(w, x=s["x"], v=s["v"], w=s["w"], F=s["F"], T=s["T"], alive=s["alive"], pairs=pr["pairs"],
+                    pair_dt=pr["dt"], pair_bonded=pr["bonded"], bond_at_init=False,
+                    wall_dt=np.ascontiguousarray(s["wall_dt"][:, :nw, :]))
+    o2.set_held(s["step"], s["fluid_force"])
+    g.step(1)
+    o2.step(1)
+    compare_fp64(g, o2, what="ring, one re-seeded step", broken_before=s["broken_bonds"])
+
+
+def test_produced_mass_by_size_class_matches_oracle():
+    """Fig. 11's observable: produced mass per class of diameter, counted at
+    every removal; equals the masses of the oracle's removed spheres grouped by
+    class, and the classes sum to the produced mass"""
+    w = synth.c1_ring()
+    edges = np.array([0.05, 0.12, 0.14, 0.16, 0.19, 0.5]) * 1e-3
+    g = gpu_for(w, "fp64", v=w["v"], size_edges=edges)
+    o = oracle_for(w, v=w["v"], bond_at_init=True)
+    g.step(120)
+    o.step(120)
+    al = o.state()["alive"]
+    gone = al == 0
+    d = 2.0 * w["r"]
+    cls = np.clip(np.searchsorted(edges, d, side="right") - 1, 0, len(edges) - 2)
+    m = w["material"]["rho"] * 4.0 / 3.0 * math.pi * w["r"] ** 3
+    expect = np.array([m[gone & (cls == c)].sum() for c in range(len(edges) - 1)])
+    got = g.produced_classes()[0]
+    np.testing.assert_array_equal(g.state()["alive"], al)
+    assert np.count_nonzero(expect) >= 3
+    np.testing.assert_allclose(got, expect, rtol=1e-13, atol=0)
+    assert got.sum() == pytest.approx(g.state()["produced_mass"], rel=1e-15)
+    with pytest.raises(dem.DemError):
+        g.set_size_classes([0.2e-3, 0.1e-3])
+
+
+def test_determinism_with_removals_and_rebuilds():
+    """Two runs of the ring in mixed precision with removals and rebuilds:
+    bitwise equal states, aggregates and produced mass"""
+    w = synth.c1_ring()
+    outs = []
+    for _ in range(2):
+        g = gpu_for(w, "mixed", v=w["v"])
+        g.step(150)
+        s = g.state()
+        a = g.aggregates()
+        outs.append((s["x"], s["v"], s["F"], s["T"], s["alive"], np.array([s["produced_mass"], s["kinetic"]]),
+                     a["produced_mass"], a["coordination"]))
+        assert s["produced_mass"] > 0.0 and g.info()["rebuilds"] >= 2
+        g.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_resume_from_held_state():
+    """A run read back (state, held fluid force, wall history, active pairs,
+    step count) and given to a new context continues like the original, to
+    the rounding of the force sums (the new context bins anew)"""
+    w = synth.c1_ring()
+    a = gpu_for(w, "fp64", v=w["v"])
+    a.step(73)
+    s = a.state(held=True)
+    pr = a.pairs(which=0)
+    assert np.abs(s["wall_dt"]).max() > 0.0 and np.abs(s["fluid_force"]).max() > 0.0
+    p = dem.params_from_workload(w, precision="fp64")
+    b = dem.Simulation(p, s["x"], w["r"], v=s["v"], w=s["w"], F=s["F"], T=s["T"], alive=s["alive"],
+                       pairs=pr["pairs"], pair_dt=pr["dt"], pair_bonded=pr["bonded"],
+                       fluid_force=s["fluid_force"], wall_dt=s["wall_dt"], step=73)
+    b.map_fluid(w["u_cell"], w["gradp_cell"])
+    a.step(30)
+    b.step(30)
+    sa, sb = a.state(), b.state()
+    np.testing.assert_array_equal(sa["alive"], sb["alive"])
+    np.testing.assert_allclose(sb["x"], sa["x"], rtol=0, atol=1e-15 * np.abs(sa["x"]).max())
+    fs = np.abs(sa["F"]).max()
+    np.testing.assert_allclose(sb["F"], sa["F"], rtol=0, atol=1e-9 * fs)
+    np.testing.assert_array_equal(a.pairs(which=0)["pairs"], b.pairs(which=0)["pairs"])
+
+
+def test_fixed_pair_capacity_reports_overflow():
+    """A pair capacity given without DEM_FLAG_AUTO_REGROW is fixed: a build
+    that needs more half pairs fails with DEM_E_CAPACITY (here at dem_init);
+    with the flag the same capacity grows"""
+    w = synth.c0()
+    p = dem.params_from_workload(w, pair_capacity=1000)
+    with pytest.raises(dem.DemError) as ei:
+        dem.Simulation(p, w["x"], w["r"])
+    assert ei.value.code == dem.DEM_E_CAPACITY
+    p.flags = dem.DEM_FLAG_AUTO_REGROW
+    sim = dem.Simulation(p, w["x"], w["r"])
+    assert sim.info()["pair_capacity"] >= sim.info()["n_pairs"] > 1000
