@@ -333,6 +333,21 @@ dem_status dem_mlp_get_params(dem_mlp* mlp, float* params);
 dem_status dem_mlp_forward(dem_mlp* mlp, const float* x, float* y, int64_t batch);
 dem_status dem_mlp_grad(dem_mlp* mlp, const float* x, const float* t, int64_t batch, float* grad, float* loss);
 dem_status dem_mlp_train_step(dem_mlp* mlp, const float* x, const float* t, int64_t batch, float lr, float* loss);
+/* dem_mlp_train_step_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight training loops, harnesses that forbid
+ * hipMalloc).  The same step as dem_mlp_train_step, bit for bit, but its batch
+ * buffers (activations, backward signals, chunk partial gradients) live in one
+ * static device array of the library, about 6.6 MB per GPU, held by each GPU
+ * the library runs on until the process ends; the call itself allocates
+ * nothing.  batch must be 1 .. DEM_MLP_NOALLOC_MAX_BATCH, else DEM_E_INVAL
+ * (nothing is launched).  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (several streams, several networks) race, so callers order
+ * them on one stream.  Nothing in the array needs clearing: each call writes
+ * every location it reads.  DEM_E_DEVICE if the array's address could not be
+ * looked up when the network was created. */
+#define DEM_MLP_NOALLOC_MAX_BATCH 4096
+dem_status dem_mlp_train_step_noalloc(dem_mlp* mlp, const float* x, const float* t, int64_t batch, float lr,
+                                      float* loss);
 dem_status dem_set_closure(dem_ctx* ctx, const dem_mlp* mlp, const double* norm);
 dem_status dem_read_closure(dem_ctx* ctx, double* features, double* c_drag, double* c_coh);
 

@@ -16,6 +16,7 @@
 // bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "dem_device.h"
@@ -468,26 +469,25 @@ int grid_for(int64_t B) {
   int64_t blocks = (tiles + 3) / 4;
   return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 2048));
 }
-// forward + backward + chunk gradients + fixed-order reduction (+ Adam)
-dem_status train_pass(dem_mlp* n, const float* x, const float* t, int64_t B, int adam, float lr, float* loss_host) {
-  if (!n || !x || !t || B <= 0) return DEM_E_INVAL;
-  if (hipSetDevice(n->device) != hipSuccess) return DEM_E_DEVICE;
-  dem_status st = ensure_batch(n, B);
-  if (st != DEM_OK) return st;
+// forward + backward + chunk gradients + fixed-order reduction (+ Adam), with
+// the batch buffers tb and the chunk partials `part` given (every location
+// read is written earlier in the same pass: nothing needs clearing)
+dem_status train_pass_bufs(dem_mlp* n, const float* x, const float* t, int64_t B, int adam, float lr,
+                           float* loss_host, const MlpTrainBuf& tb, float* part) {
   hipStream_t s = n->stream;
   int g = grid_for(B);
-  hipLaunchKernelGGL(k_mlp_forward_train, dim3(g), dim3(256), 0, s, n->wb, n->p, x, t, B, n->tb);
-  hipLaunchKernelGGL(k_mlp_backward, dim3(g), dim3(256), 0, s, n->wb, B, n->tb);
+  hipLaunchKernelGGL(k_mlp_forward_train, dim3(g), dim3(256), 0, s, n->wb, n->p, x, t, B, tb);
+  hipLaunchKernelGGL(k_mlp_backward, dim3(g), dim3(256), 0, s, n->wb, B, tb);
   int nch = (int)((B + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(4 * nch), dim3(256), 0, s, B, n->tb, n->part);
-  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, n->tb.err, B, n->loss);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(4 * nch), dim3(256), 0, s, B, tb, part);
+  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, tb.err, B, n->loss);
   float bc1 = 1.f, bc2 = 1.f;
   if (adam) {
     n->step += 1;
     bc1 = (float)(1.0 - std::pow(0.9, (double)n->step));
     bc2 = (float)(1.0 - std::pow(0.999, (double)n->step));
   }
-  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, n->part, nch, n->grad, n->p,
+  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, part, nch, n->grad, n->p,
                      n->m, n->v, n->wb, adam, lr, bc1, bc2);
   if (hipGetLastError() != hipSuccess) return DEM_E_DEVICE;
   if (loss_host) {
@@ -495,6 +495,63 @@ dem_status train_pass(dem_mlp* n, const float* x, const float* t, int64_t B, int
     if (hipStreamSynchronize(s) != hipSuccess) return DEM_E_DEVICE;
   }
   return DEM_OK;
+}
+
+// the same pass with buffers the network object owns (grown on demand)
+dem_status train_pass(dem_mlp* n, const float* x, const float* t, int64_t B, int adam, float lr, float* loss_host) {
+  if (!n || !x || !t || B <= 0) return DEM_E_INVAL;
+  if (hipSetDevice(n->device) != hipSuccess) return DEM_E_DEVICE;
+  dem_status st = ensure_batch(n, B);
+  if (st != DEM_OK) return st;
+  return train_pass_bufs(n, x, t, B, adam, lr, loss_host, n->tb, n->part);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the training step that allocates nothing: the batch buffers for
+// up to DEM_MLP_NOALLOC_MAX_BATCH samples and their chunk partials, in one
+// file-scope device array.  Each GPU holds its own copy at its own address,
+// looked up once per device (hipGetSymbolAddress) when a network is created
+// there; host code uses only that address, never the array's name.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocBatch = DEM_MLP_NOALLOC_MAX_BATCH;
+constexpr int64_t kNoAllocChunks = (kNoAllocBatch + kChunk - 1) / kChunk;
+constexpr size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kScrH0 = al256(sizeof(short) * kNoAllocBatch * 16);
+constexpr size_t kScrH = al256(sizeof(short) * kNoAllocBatch * 64);
+constexpr size_t kScrZ = al256(sizeof(float) * kNoAllocBatch * 64);
+constexpr size_t kScrG4 = al256(sizeof(float) * kNoAllocBatch * 2);
+constexpr size_t kScrErr = al256(sizeof(float) * kNoAllocBatch);
+constexpr size_t kScrPart = al256(sizeof(float) * kNoAllocChunks * kNParams);
+constexpr size_t kScratchBytes = kScrH0 + 3 * (kScrH + kScrZ + kScrH) + kScrG4 + kScrErr + kScrPart;
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+char* g_scratch[kMaxDevices] = {};   // device address of `scratch` on each device (null: not looked up)
+std::mutex g_scratch_mu;
+
+// with `device` current
+dem_status scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return DEM_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return DEM_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DEM_E_DEVICE;
+  g_scratch[device] = (char*)ptr;
+  return DEM_OK;
+}
+
+void scratch_buffers(char* base, MlpTrainBuf& tb, float*& part) {
+  char* q = base;
+  tb.h0 = (short*)q; q += kScrH0;
+  for (int l = 0; l < 3; ++l) {
+    tb.h[l] = (short*)q; q += kScrH;
+    tb.z[l] = (float*)q; q += kScrZ;
+    tb.g[l] = (short*)q; q += kScrH;
+  }
+  tb.g4 = (float*)q; q += kScrG4;
+  tb.err = (float*)q; q += kScrErr;
+  part = (float*)q;
 }
 }  // namespace
 
@@ -513,6 +570,10 @@ dem_status dem_mlp_create(dem_mlp** out, int32_t device, void* hip_stream) {
   dem_mlp* n = new dem_mlp();
   n->device = device;
   n->stream = (hipStream_t)hip_stream;
+  if (scratch_lookup(device) != DEM_OK) {
+    delete n;
+    return DEM_E_DEVICE;
+  }
   bool ok = hipMalloc((void**)&n->p, sizeof(float) * kNParams) == hipSuccess;
   ok &= hipMalloc((void**)&n->m, sizeof(float) * kNParams) == hipSuccess;
   ok &= hipMalloc((void**)&n->v, sizeof(float) * kNParams) == hipSuccess;
@@ -589,6 +650,19 @@ dem_status dem_mlp_grad(dem_mlp* n, const float* x, const float* t, int64_t batc
 dem_status dem_mlp_train_step(dem_mlp* n, const float* x, const float* t, int64_t batch, float lr, float* loss) {
   if (!(lr > 0.f)) return DEM_E_INVAL;
   return train_pass(n, x, t, batch, 1, lr, loss);
+}
+
+dem_status dem_mlp_train_step_noalloc(dem_mlp* n, const float* x, const float* t, int64_t batch, float lr,
+                                      float* loss) {
+  if (!n || !x || !t || batch <= 0 || batch > DEM_MLP_NOALLOC_MAX_BATCH || !(lr > 0.f)) return DEM_E_INVAL;
+  if (n->device < 0 || n->device >= kMaxDevices) return DEM_E_DEVICE;
+  if (hipSetDevice(n->device) != hipSuccess) return DEM_E_DEVICE;
+  char* base = g_scratch[n->device];   // looked up when the network was created on this device
+  if (!base) return DEM_E_DEVICE;
+  MlpTrainBuf tb{};
+  float* part = nullptr;
+  scratch_buffers(base, tb, part);
+  return train_pass_bufs(n, x, t, batch, 1, lr, loss, tb, part);
 }
 
 }  // extern "C"

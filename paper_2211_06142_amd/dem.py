@@ -32,8 +32,9 @@ EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "de
                   "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile",
                   "dem_read_fault", "dem_mlp_create", "dem_mlp_destroy", "dem_mlp_set_params", "dem_mlp_get_params",
                   "dem_mlp_forward", "dem_mlp_grad", "dem_mlp_train_step", "dem_set_closure", "dem_read_closure", "dem_set_graphs", "dem_set_lanes",
-                  "dem_set_size_classes", "dem_read_produced_classes"])
+                  "dem_set_size_classes", "dem_read_produced_classes", "dem_mlp_train_step_noalloc"])
 MLP_NPARAMS = 8898
+MLP_NOALLOC_MAX_BATCH = 4096
 
 
 class dem_wall(ctypes.Structure):
@@ -142,6 +143,8 @@ def lib():
         L.dem_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
         L.dem_mlp_train_step.restype = i32
         L.dem_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp]
+        L.dem_mlp_train_step_noalloc.restype = i32
+        L.dem_mlp_train_step_noalloc.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp]
         L.dem_set_lanes.restype = i32
         L.dem_set_lanes.argtypes = [vp, i32]
         L.dem_set_graphs.restype = i32
@@ -314,6 +317,12 @@ def dem_set_size_classes(ctx, n_edges, edges_ptr):
 
 def dem_read_produced_classes(ctx, mass_ptr):
     return lib().dem_read_produced_classes(ctx, mass_ptr)
+
+
+def dem_mlp_train_step_noalloc(mlp, x_ptr, t_ptr, batch, lr):
+    loss = ctypes.c_float()
+    rc = lib().dem_mlp_train_step_noalloc(mlp, x_ptr, t_ptr, batch, lr, ctypes.byref(loss))
+    return rc, loss.value
 
 
 def dem_set_closure(ctx, mlp, norm_ptr):
