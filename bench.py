@@ -194,7 +194,7 @@ def learned_cg_block(horizon, ks=(2, 3), c4=False):
     return out
 
 
-def build_sim(ws, skin_factor, lanes, graphs):
+def build_sim(ws, skin_factor, lanes, graphs, pair_mode=None):
     from paper_2211_06142_amd import dem
     rmin = min(float(np.min(w["r"])) for w in ws)
     skin = skin_factor * rmin if skin_factor > 0 else 0.0
@@ -208,6 +208,8 @@ def build_sim(ws, skin_factor, lanes, graphs):
     sim.map_fluid(np.concatenate([w["u_cell"] for w in ws]), np.concatenate([w["gradp_cell"] for w in ws]))
     sim.set_lanes(lanes)
     sim.set_graphs(graphs)
+    if pair_mode is not None:
+        sim.set_pair_mode(pair_mode)
     return sim
 
 
@@ -223,6 +225,8 @@ def main():
                     help="neighbour skin as a multiple of the smallest radius (default per workload)")
     ap.add_argument("--lanes", type=int, default=LANES, help="lanes per particle of the step kernel")
     ap.add_argument("--graphs", type=int, default=0, help="replay recorded step windows (timing off)")
+    ap.add_argument("--pair-mode", default=None, choices=["full", "half"],
+                    help="contact evaluation: full rows (each pair twice) or half pairs with force records")
     ap.add_argument("--tune", action="store_true", help="autotune skin and lanes before the timed run")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure measurement (network "
                     "throughput on the matrix cores, cost inside the coupling)")
@@ -256,7 +260,7 @@ def main():
         rmin = min(float(np.min(x["r"])) for x in ws)
         args.skin_factor, args.lanes = best["skin"] / rmin, best["lanes"]
         tuned = {"skin_factor": args.skin_factor, "lanes": args.lanes, "trials": table}
-    sim = build_sim(ws, args.skin_factor, args.lanes, args.graphs)
+    sim = build_sim(ws, args.skin_factor, args.lanes, args.graphs, args.pair_mode)
     n_total = sum(len(x["r"]) for x in ws)
     print("bench: %s set up, %d particles in %d sample(s)" % (args.workload, n_total, len(ws)), file=sys.stderr,
           flush=True)

@@ -271,6 +271,18 @@ dem_status dem_set_graphs(dem_ctx* ctx, int32_t enable);
  * by rounding only, and are reproducible for each. */
 dem_status dem_set_lanes(dem_ctx* ctx, int32_t lanes);
 
+/* How the step evaluates the contact law of a pair (a tuning knob; results
+ * are identical bit for bit).  DEM_PAIRS_FULL_ROWS: each particle walks its
+ * full neighbour row and evaluates every contact itself, in the pair's
+ * canonical orientation, so each pair is evaluated twice and no force record
+ * is written (one launch per step).  DEM_PAIRS_HALF: a first launch evaluates
+ * every half pair once and writes its force record (force, n x F_t and rolling
+ * torque on the owner); a second adds the records of each particle's row in
+ * the same order (two launches per step; the default, faster at 200 000
+ * spheres).  Anything else is DEM_E_INVAL. */
+enum { DEM_PAIRS_FULL_ROWS = 0, DEM_PAIRS_HALF = 1 };
+dem_status dem_set_pair_mode(dem_ctx* ctx, int32_t mode);
+
 /* Kernel-class timing with HIP events recorded on the context's stream
  * around every launch of each class (for roofline reporting).  enable = 1
  * starts (and zeroes) the accumulators, 0 stops.  dem_read_profile fills

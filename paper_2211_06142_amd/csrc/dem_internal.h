@@ -82,7 +82,10 @@ struct DevState {
   double dt;
   int couple_every;
   int rolling;                     // any sample with mu_roll > 0
-  int group;                       // lanes per particle of the step kernel (4, 8, 16)
+  int group;                       // lanes per particle of the step kernel (1, 2, 4, 8, 16)
+  int pair_mode;                   // DEM_PAIRS_FULL_ROWS or DEM_PAIRS_HALF
+  void* rec[3];                    // half-pair mode: per slot R4 force on the owner, n x F_t,
+                                   // rolling torque on the owner (written and read in one step)
   int cur;                         // buffer holding the current particle state and history
   // double-buffered particle state
   double4 *xr[2], *vel[2];

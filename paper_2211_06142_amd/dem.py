@@ -24,6 +24,7 @@ DEM_CG_SSW, DEM_CG_SSP = 0, 1
 DEM_FLAG_AUTO_REGROW = 1
 DEM_MAX_SIZE_CLASSES = 16
 
+DEM_PAIRS_FULL_ROWS, DEM_PAIRS_HALF = 0, 1
 DEM_PROF_PROLOGUE, DEM_PROF_REBUILD, DEM_PROF_FLUID, DEM_PROF_STEP, DEM_PROF_N = 0, 1, 2, 3, 4
 PROF_NAMES = ["prologue", "rebuild", "fluid", "step"]
 
@@ -32,7 +33,7 @@ EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "de
                   "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile",
                   "dem_read_fault", "dem_mlp_create", "dem_mlp_destroy", "dem_mlp_set_params", "dem_mlp_get_params",
                   "dem_mlp_forward", "dem_mlp_grad", "dem_mlp_train_step", "dem_set_closure", "dem_read_closure", "dem_set_graphs", "dem_set_lanes",
-                  "dem_set_size_classes", "dem_read_produced_classes", "dem_mlp_train_step_noalloc"])
+                  "dem_set_size_classes", "dem_read_produced_classes", "dem_mlp_train_step_noalloc", "dem_set_pair_mode"])
 MLP_NPARAMS = 8898
 MLP_NOALLOC_MAX_BATCH = 4096
 
@@ -147,6 +148,8 @@ def lib():
         L.dem_mlp_train_step_noalloc.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp]
         L.dem_set_lanes.restype = i32
         L.dem_set_lanes.argtypes = [vp, i32]
+        L.dem_set_pair_mode.restype = i32
+        L.dem_set_pair_mode.argtypes = [vp, i32]
         L.dem_set_graphs.restype = i32
         L.dem_set_graphs.argtypes = [vp, i32]
         L.dem_set_closure.restype = i32
@@ -615,6 +618,11 @@ class Simulation:
 
     def set_lanes(self, lanes):
         _check(lib().dem_set_lanes(self.ctx, int(lanes)), "dem_set_lanes")
+
+    def set_pair_mode(self, mode):
+        """DEM_PAIRS_FULL_ROWS or DEM_PAIRS_HALF (or "full" / "half")"""
+        m = {"full": DEM_PAIRS_FULL_ROWS, "half": DEM_PAIRS_HALF}.get(mode, mode)
+        _check(lib().dem_set_pair_mode(self.ctx, int(m)), "dem_set_pair_mode")
 
     def set_graphs(self, enable):
         _check(lib().dem_set_graphs(self.ctx, 1 if enable else 0), "dem_set_graphs")

@@ -237,3 +237,50 @@ def test_fixed_pair_capacity_reports_overflow():
     p.flags = dem.DEM_FLAG_AUTO_REGROW
     sim = dem.Simulation(p, w["x"], w["r"])
     assert sim.info()["pair_capacity"] >= sim.info()["n_pairs"] > 1000
+
+
+# ---------------------------------------------------------------------------
+# the two ways of evaluating pairs (a tuning knob): bit-identical results
+# ---------------------------------------------------------------------------
+def _run_mode(wk, precision, mode, lanes, steps, graphs=False, mat=None, **kw):
+    g = gpu_for(wk, precision, mat=mat, **kw)
+    g.set_pair_mode(mode)
+    g.set_lanes(lanes)
+    g.set_graphs(graphs)
+    for k in steps:
+        g.step(k)
+    s = g.state(held=True)
+    pr = g.pairs(which=0)
+    out = [s[key] for key in ("x", "v", "w", "F", "T", "alive", "fluid_force", "wall_dt")]
+    out += [pr["pairs"], pr["dt"], pr["bonded"], np.array([s["produced_mass"], s["broken_bonds"], s["n_contacts"]])]
+    info = g.info()
+    g.close()
+    return out, info
+
+
+@pytest.mark.parametrize("case", ["c0_fp64_rolling", "ring_mixed", "ring_fp64_graphs"])
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_half_pairs_equal_full_rows_bitwise(case, lanes):
+    """The half-pair mode (each contact law once, force records, a second
+    launch that adds them per row) against the full-row mode (each pair
+    evaluated by both partners): same states, histories, sets and counters,
+    bit for bit, through rebuilds, removals, coupling and graph replay"""
+    if case == "c0_fp64_rolling":
+        w, v = c0_moving()
+        mat = dict(w["material"], mu_roll=0.2)
+        wv = np.random.default_rng(6).normal(0.0, 2e3, v.shape)
+        args = dict(precision="fp64", steps=(7, 20, 1), mat=mat, v=v, w=wv)
+    elif case == "ring_mixed":
+        w = synth.c1_ring()
+        args = dict(precision="mixed", steps=(60, 61), v=w["v"])
+    else:
+        w = synth.c1_ring()
+        args = dict(precision="fp64", steps=(50, 45), graphs=True, v=w["v"])
+    res = {}
+    for mode in ("full", "half"):
+        res[mode] = _run_mode(w, args["precision"], mode, lanes, args["steps"], graphs=args.get("graphs", False),
+                              mat=args.get("mat"), **{k: args[k] for k in ("v", "w") if k in args})
+    (a, ia), (b, ib) = res["full"], res["half"]
+    assert ia["rebuilds"] == ib["rebuilds"]
+    for k, (x, y) in enumerate(zip(a, b)):
+        assert np.array_equal(x, y), k
