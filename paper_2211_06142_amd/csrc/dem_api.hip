@@ -736,11 +736,11 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   for (void** q : r4s) ok &= dalloc_bytes(c, q, n * R4B) == hipSuccess;
   ok &= dalloc(c, &d.sample, n) == hipSuccess && dalloc(c, &d.orig, n) == hipSuccess;
   ok &= dalloc(c, &d.t_i[0], n) == hipSuccess && dalloc(c, &d.t_i[1], n) == hipSuccess;
-  int64_t nbk = std::max<int64_t>(std::max<int64_t>(d.nbins_total, n), d.ndual) + 2;
+  int64_t nbk = std::max<int64_t>(d.nbins_total, n) + 2;
   ok &= dalloc(c, &d.key, n) == hipSuccess;
   ok &= dalloc(c, &d.bucket_cnt, nbk) == hipSuccess && dalloc(c, &d.bucket_fill, nbk) == hipSuccess;
   ok &= dalloc(c, &d.cell_start, nbk) == hipSuccess && dalloc(c, &d.bin_sample, nbk) == hipSuccess;
-  ok &= dalloc(c, &d.bin_sink, nbk) == hipSuccess && dalloc(c, &d.dual_sink, d.ndual + 2) == hipSuccess;
+  ok &= dalloc(c, &d.bin_sink, nbk) == hipSuccess;
   ok &= dalloc(c, &d.order, n) == hipSuccess && dalloc(c, &d.order_tmp, n) == hipSuccess;
   ok &= dalloc(c, &d.inv_order, n) == hipSuccess;
   ok &= dalloc(c, &d.ncnt, n + 1) == hipSuccess && dalloc(c, &d.ocnt, n + 1) == hipSuccess;
@@ -765,12 +765,11 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.u_in, 3 * nc) == hipSuccess && dalloc(c, &d.gp_in, 3 * nc) == hipSuccess;
   ok &= dalloc(c, &d.cell_n, nc) == hipSuccess && dalloc(c, &d.cell_u, 3 * nc) == hipSuccess;
   ok &= dalloc(c, &d.eps, nc) == hipSuccess && dalloc(c, &d.fdc, 3 * nc) == hipSuccess;
-  ok &= dalloc(c, &d.dpart, 24 * (d.ndual + 1)) == hipSuccess;
   ok &= dalloc(c, &d.dkey, n) == hipSuccess && dalloc(c, &d.dfr, n) == hipSuccess;
-  ok &= dalloc(c, &d.fpart, n) == hipSuccess && dalloc(c, &d.dmem, n) == hipSuccess;
-  ok &= dalloc(c, &d.dmem_tmp, n) == hipSuccess;
-  ok &= dalloc(c, &d.dcnt, d.ndual + 2) == hipSuccess && dalloc(c, &d.doff, d.ndual + 2) == hipSuccess;
-  ok &= dalloc(c, &d.dfill, d.ndual + 2) == hipSuccess;
+  ok &= dalloc(c, &d.fpart, n) == hipSuccess;
+  ok &= dalloc(c, &d.dpart, 24 * (d.ndual + 1)) == hipSuccess;
+  ok &= dalloc(c, &d.docc, d.ndual + 1) == hipSuccess && dalloc(c, &d.dual_sample, d.ndual + 1) == hipSuccess;
+  ok &= dalloc(c, &d.dlmem, 32 * (d.ndual + 1)) == hipSuccess && dalloc(c, &d.dlcnt, 8 * (d.ndual + 1)) == hipSuccess;
   ok &= dalloc(c, &d.sc, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.broken, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.produced_fx, n_samples) == hipSuccess;
@@ -783,7 +782,7 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   d.self = c->d_dev;
   d.group = 4;   // tuned on the 200 000-sphere cylinder (4 beat 8 and 16 at every skin)
   d.pair_mode = DEM_PAIRS_HALF;   // 48.6 against 55.9 us per step at 200 000 spheres
-  int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nbk, n + 1), d.ndual + 2);
+  int64_t scan_n = std::max<int64_t>(nbk, n + 1);
   d.scan_tmp_n = scan_n / 256 + 4096;
   ok &= dalloc(c, &d.scan_tmp, d.scan_tmp_n) == hipSuccess;
   if (!ok) return fail(DEM_E_NOMEM);
@@ -819,11 +818,15 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
     }
   }
   std::vector<int32_t> cs(nc, 0), bs(nbk, 0);
-  std::vector<uint8_t> bsink(nbk, 0), dsink(d.ndual + 2, 0);
+  std::vector<uint8_t> bsink(nbk, 0);
+  std::vector<int32_t> dsamp(d.ndual + 1, 0);
+  for (int s = 0; s < n_samples; ++s) {
+    const SampleConst& k = c->sc[s];
+    for (int64_t q = 0; q <= (int64_t)k.dn[0] * k.dn[1] * k.dn[2]; ++q) dsamp[k.dual_base + q] = s;
+  }
   for (int s = 0; s < n_samples; ++s) {
     const SampleConst& k = c->sc[s];
     bsink[k.bin_base + (int64_t)k.bn[0] * k.bn[1] * k.bn[2]] = 1;
-    dsink[k.dual_base + (int64_t)k.dn[0] * k.dn[1] * k.dn[2]] = 1;
   }
   for (int s = 0; s < n_samples; ++s) {
     if (params[s].fluid_on)
@@ -845,15 +848,12 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   // the bucket sorts expect their counters at zero (each sort clears them after use)
   up &= hipMemsetAsync(d.bucket_cnt, 0, sizeof(int32_t) * nbk, st) == hipSuccess;
   up &= hipMemsetAsync(d.bucket_fill, 0, sizeof(int32_t) * nbk, st) == hipSuccess;
-  up &= hipMemsetAsync(d.dcnt, 0, sizeof(int32_t) * (d.ndual + 2), st) == hipSuccess;
-  up &= hipMemsetAsync(d.dfill, 0, sizeof(int32_t) * (d.ndual + 2), st) == hipSuccess;
   up &= hipMemcpyAsync(d.sample, hs.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.orig, ho.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.sc, c->sc.data(), sizeof(SampleConst) * n_samples, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.cell_sample, cs.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.bin_sample, bs.data(), sizeof(int32_t) * nbk, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(d.bin_sink, bsink.data(), nbk, hipMemcpyHostToDevice, st) == hipSuccess;
-  up &= hipMemcpyAsync(d.dual_sink, dsink.data(), d.ndual + 2, hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemcpyAsync(c->d_offsets, offs.data(), sizeof(int64_t) * (n_samples + 1), hipMemcpyHostToDevice, st) == hipSuccess;
   up &= hipMemsetAsync(d.broken, 0, sizeof(unsigned long long) * n_samples, st) == hipSuccess;
   up &= hipMemsetAsync(d.produced_fx, 0, sizeof(unsigned long long) * n_samples, st) == hipSuccess;
@@ -862,6 +862,9 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   up &= hipMemsetAsync(d.status, 0, sizeof(int), st) == hipSuccess;
   up &= hipMemsetAsync(d.abort, 0, sizeof(int), st) == hipSuccess;
   up &= hipMemsetAsync(d.eps, 0, sizeof(double) * nc, st) == hipSuccess;
+  up &= hipMemsetAsync(d.docc, 0, d.ndual + 1, st) == hipSuccess;
+  up &= hipMemcpyAsync(d.dual_sample, dsamp.data(), sizeof(int32_t) * (d.ndual + 1), hipMemcpyHostToDevice, st) ==
+        hipSuccess;
   up &= hipMemsetAsync(d.fdc, 0, sizeof(double) * 3 * nc, st) == hipSuccess;
   up &= hipMemsetAsync(d.u_in, 0, sizeof(double) * 3 * nc, st) == hipSuccess;
   up &= hipMemsetAsync(d.gp_in, 0, sizeof(double) * 3 * nc, st) == hipSuccess;

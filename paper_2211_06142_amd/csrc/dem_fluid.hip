@@ -1,12 +1,14 @@
 // dem_fluid.hip -- fluid-particle coupling (arXiv:2211.06142 section 2.2).
 //
 // Every reduction is a sorted segmented reduction, no floating-point atomics:
-// particles are bucket-sorted by the cell of the grid of fluid-cell centres
-// that holds them ("dual cell": its 8 corners are the 8 fluid cells a
-// trilinear weight reaches; for centroid deposition the bucket is the fluid
-// cell itself); each bucket sums its members in index order into 8 corner
-// partials; each fluid cell then sums the corner partials of the (up to 8)
-// buckets around it in a fixed order.
+// each particle has a bucket, the cell of the grid of fluid-cell centres that
+// holds it ("dual cell": its 8 corners are the 8 fluid cells a trilinear weight
+// reaches; for centroid deposition the bucket is the fluid cell itself); a
+// bucket sums its members' contributions to its 8 corners in a fixed order, and
+// a fluid cell sums the partials of the (up to 8) buckets around it in a fixed
+// order.  The members are found through the neighbour list's binning (particles
+// sorted by binning cell at the last rebuild, none moved more than half the skin
+// since), so the coupling needs no sort of its own.
 //   porosity  n = clamp(1 - sum w V / V_cell, n_min, 1)           (eq 6)
 //   drag      Di Felice, coarse-grained k^3 f(d/k), closure factor (eq 8-11)
 //   buoyancy  F_b = -V (grad p + rho_f g)                           (eq 1)
@@ -15,9 +17,9 @@
 
 namespace dem {
 
-// Every particle gets a key in range, also when the window was aborted (then
-// buffer `buf` may never have been written and every particle goes to its
-// sample's skip bucket): the bucket sort that follows is not gated.
+// Key (bucket) and trilinear fractions of every particle; dead particles, and
+// every particle of a sample without fluid, get their sample's skip key, which
+// no cell reads.
 __global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
   const DevState& d = *dp;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,7 +52,9 @@ __global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
       f[k] = t - (double)bb;
     }
   }
-  d.dkey[i] = (int32_t)(c.dual_base + ((int64_t)b[2] * c.dn[1] + b[1]) * c.dn[0] + b[0]);
+  const int64_t key = c.dual_base + ((int64_t)b[2] * c.dn[1] + b[1]) * c.dn[0] + b[0];
+  d.dkey[i] = (int32_t)key;
+  d.docc[key] = 1;   // the bucket has a member in this evaluation
   const double V = (4.0 / 3.0) * M_PI * p.w * p.w * p.w;
   d.dfr[i] = make_double4(f[0], f[1], f[2], V);
 }
@@ -63,59 +67,146 @@ __device__ inline double corner_w(const double4& fr, int kx, int ky, int kz) {
   return (wx * wy) * wz;
 }
 
-// corner partials of every bucket: kind 0 volume (8 per bucket), kind 1 drag (24 per bucket)
+// Range of binning cells along one axis that can hold a member of bucket b: the
+// bucket's extent (open towards the outside at the first and last bucket,
+// where the weights fold onto the boundary cells) widened by half the skin,
+// the farthest a particle moves between list rebuilds.  Binning cells are those
+// of the last rebuild, positions then clamped into the grid as the bucket keys
+// clamp them, so bin_coord of the widened ends bounds every member's cell.
+__device__ inline void member_bins(const SampleConst& c, int k, int b, int cen, int& q0, int& q1) {
+  // (widened a little more than half the skin: the bounds below and the keys
+  // are computed with different roundings)
+  const double h = c.gh[k], hs = 0.5 * c.skin * (1.0 + 1e-6) + 1e-9 * h;
+  const int nb = c.dn[k];
+  const double off = cen ? 0.0 : 0.5;
+  q0 = b == 0 ? 0 : bin_coord(c.glo[k] + (b + off) * h - hs, c.blo[k], c.bh[k], c.bn[k]);
+  q1 = b == nb - 1 ? c.bn[k] - 1 : bin_coord(c.glo[k] + (b + off + 1.0) * h + hs, c.blo[k], c.bh[k], c.bn[k]);
+}
+
+// Corner partials of every bucket, a sorted segmented reduction with no sort of
+// its own: the members of bucket b are the particles whose key is b, and they
+// lie in the binning cells of member_bins, sorted by binning cell since the last
+// rebuild; a group of 8 lanes scans those cells' particles in increasing index
+// (lane u takes every 8th, starting at u) and adds each member's weighted value
+// to the bucket's 8 corners; the lanes' sums are then added in a fixed tree.  The
+// order of every sum is fixed by the binning and the keys.  Buckets that no
+// particle's key named in this evaluation (the occupancy byte) are skipped.
+// kind 0: solid volume (8 per bucket); it also records each lane's members (up
+// to kLaneMem, in scan order) so that kind 1, the particle drag (24 per bucket),
+// visits the same members in the same order without scanning again (a lane with
+// more members scans again); kind 1 clears the occupancy for the next evaluation.
+constexpr int kLaneMem = 4;
+
 template <int kKind>
-__global__ __launch_bounds__(64) void k_fluid_partials(const DevState* __restrict__ dp) {
-  // one thread per bucket, all its outputs (8 corner volumes, or 8 corners x 3
-  // drag components): each member is read once, and every output sums the
-  // bucket's members in bucket order
+__device__ inline void add_member(const DevState& d, int32_t q, double* acc) {
+  const double4 fr = gld(G((const double4*)d.dfr) + q);
+  double4 fp = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (kKind == 1) fp = gld(G((const double4*)d.fpart) + q);
+#pragma unroll
+  for (int corner = 0; corner < 8; ++corner) {
+    const double w = corner_w(fr, corner & 1, (corner >> 1) & 1, corner >> 2);
+    if (kKind == 0) {
+      acc[corner] += w * fr.w;
+    } else {
+      acc[3 * corner] += w * fp.x;
+      acc[3 * corner + 1] += w * fp.y;
+      acc[3 * corner + 2] += w * fp.z;
+    }
+  }
+}
+
+// Sum over the 8 lanes of a group of each of M values (M a multiple of 8) in a
+// fixed tree (partners at lane distance 4, then 2, then 1), leaving lane u with
+// the totals of values u, u + 8, u + 16, ... in out[0 .. M/8).
+template <int M>
+__device__ inline void group8_reduce_scatter(const double (&v)[M], int u, double (&out)[M / 8]) {
+  const bool h2 = (u >> 2) & 1, h1 = (u >> 1) & 1, h0 = u & 1;
+  double w[M / 2], x[M / 4];
+#pragma unroll
+  for (int j = 0; j < M / 8; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double lo = v[8 * j + r], hi = v[8 * j + r + 4];
+      w[4 * j + r] = (h2 ? hi : lo) + __shfl_xor(h2 ? lo : hi, 4, 64);
+    }
+#pragma unroll
+  for (int j = 0; j < M / 8; ++j)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const double lo = w[4 * j + r], hi = w[4 * j + r + 2];
+      x[2 * j + r] = (h1 ? hi : lo) + __shfl_xor(h1 ? lo : hi, 2, 64);
+    }
+#pragma unroll
+  for (int j = 0; j < M / 8; ++j) {
+    const double lo = x[2 * j], hi = x[2 * j + 1];
+    out[j] = (h0 ? hi : lo) + __shfl_xor(h0 ? lo : hi, 1, 64);
+  }
+}
+
+template <int kKind>
+__global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restrict__ dp) {
   const DevState& d = *dp;
   if (*d.abort) return;
   constexpr int m = kKind == 0 ? 8 : 24;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= d.ndual) return;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = gid >> 3;
+  const int u = (int)(gid & 7);
+  if (b >= d.ndual) return;   // whole group
+  const auto OCC = G((uint8_t*)d.docc);
+  const auto PART = G(d.dpart);
+  if (!OCC[b]) {   // no member: zero partials (lane u writes outputs u, u + 8, ...)
+#pragma unroll
+    for (int j = 0; j < m / 8; ++j) PART[m * b + 8 * j + u] = 0.0;
+    return;
+  }
   double acc[m];
 #pragma unroll
   for (int k = 0; k < m; ++k) acc[k] = 0.0;
-  // the skipped particles of a sample sit in its sink bucket, which no cell reads
-  // members in groups of four: all loads of a group are issued before any
-  // use (a bucket holds a few members, so this is one or two round trips)
-  constexpr int kU = 4;
-  const auto MEM = G((const int32_t*)d.dmem);
-  const auto FR = G((const double4*)d.dfr);
-  const auto FP = G((const double4*)d.fpart);
-  if (!G((const uint8_t*)d.dual_sink)[b]) {
-    const int32_t q1 = G((const int32_t*)d.doff)[b + 1];
-    for (int32_t q0 = G((const int32_t*)d.doff)[b]; q0 < q1; q0 += kU) {
-      int32_t ii[kU];
-      double4 fr[kU], fp[kU];
+  const auto LM = G((int32_t*)d.dlmem) + gid * kLaneMem;
+  const auto LN = G((uint8_t*)d.dlcnt);
+  {
+    const int listed = kKind == 1 ? LN[gid] : 255;
+    if (listed <= kLaneMem) {
+      for (int v = 0; v < listed; ++v) add_member<kKind>(d, LM[v], acc);
+    } else {
+      const SampleConst& c = sample_const(d.sc, G((const int32_t*)d.dual_sample)[b]);
+      const int64_t l = b - c.dual_base;
+      const int D[3] = {(int)(l % c.dn[0]), (int)((l / c.dn[0]) % c.dn[1]), (int)(l / ((int64_t)c.dn[0] * c.dn[1]))};
+      const int cen = c.voidfrac == DEM_VOID_CENTROID;
+      int q0[3], q1[3];
+      for (int k = 0; k < 3; ++k) member_bins(c, k, D[k], cen, q0[k], q1[k]);
+      const auto KEY = G((const int32_t*)d.dkey);
+      const auto CS = G((const int32_t*)d.cell_start);
+      int found = 0;
+      for (int bz = q0[2]; bz <= q1[2]; ++bz)
+        for (int by = q0[1]; by <= q1[1]; ++by) {
+          const int64_t row = c.bin_base + ((int64_t)bz * c.bn[1] + by) * c.bn[0];
+          const int32_t m1 = CS[row + q1[0] + 1];
+          // four candidates per lane and round: all key loads before any use
+          constexpr int kU = 4;
+          for (int32_t m0 = CS[row + q0[0]] + u; m0 < m1; m0 += 8 * kU) {
+            int32_t ks[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) ii[u] = q0 + u < q1 ? MEM[q0 + u] : -1;
+            for (int v = 0; v < kU; ++v) ks[v] = m0 + 8 * v < m1 ? KEY[m0 + 8 * v] : -1;
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        fr[u] = ii[u] >= 0 ? gld(FR + ii[u]) : make_double4(0.0, 0.0, 0.0, 0.0);
-        fp[u] = kKind == 1 && ii[u] >= 0 ? gld(FP + ii[u]) : make_double4(0.0, 0.0, 0.0, 0.0);
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (ii[u] < 0) break;
-#pragma unroll
-        for (int corner = 0; corner < 8; ++corner) {
-          const double w = corner_w(fr[u], corner & 1, (corner >> 1) & 1, corner >> 2);
-          if (kKind == 0) {
-            acc[corner] += w * fr[u].w;
-          } else {
-            acc[3 * corner] += w * fp[u].x;
-            acc[3 * corner + 1] += w * fp[u].y;
-            acc[3 * corner + 2] += w * fp[u].z;
+            for (int v = 0; v < kU; ++v) {
+              if (ks[v] != (int32_t)b) continue;
+              const int32_t q = m0 + 8 * v;
+              add_member<kKind>(d, q, acc);
+              if (kKind == 0 && found < kLaneMem) LM[found] = q;
+              ++found;
+            }
           }
         }
-      }
+      if (kKind == 0) LN[gid] = (uint8_t)(found < 255 ? found : 255);
     }
   }
-  const auto PART = G(d.dpart);
+  // the 8 lanes' sums in a fixed tree; lane u writes outputs u, u + 8, ...
+  double tot[m / 8];
+  group8_reduce_scatter<m>(acc, u, tot);
 #pragma unroll
-  for (int k = 0; k < m; ++k) PART[m * b + k] = acc[k];
+  for (int j = 0; j < m / 8; ++j) PART[m * b + 8 * j + u] = tot[j];
+  if (kKind == 1 && u == 0) OCC[b] = 0;
 }
 
 // per fluid cell: fixed-order sum of the corner partials of the adjacent buckets
@@ -316,16 +407,14 @@ __global__ void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
 
 template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
   hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
-  launch_bucket_sort((const uint32_t*)d.dkey, d.n, d.ndual, nullptr, d.dcnt, d.doff, d.dfill, d.dmem_tmp,
-                     d.dmem, d.scan_tmp, d.dual_sink, d.abort, s);
-  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual, 64)), dim3(64), 0, s, d.self);
+  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
   if (d.closure_on) {
     hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
     launch_closure_infer(d, s);
   }
   hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
-  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual, 64)), dim3(64), 0, s, d.self);
+  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
 }
 template void launch_fluid<double>(DevState&, int, hipStream_t);

@@ -142,10 +142,12 @@ struct DevState {
   double *eps, *fdc;               // ncell, 3*ncell (latest evaluation)
   double* dpart;                   // 8 * ndual corner partial sums (reused for 3 * 8 drag partials)
   int32_t* dkey;
+  uint8_t* docc;                   // ndual: bucket named by some particle's key in this evaluation
+  int32_t* dlmem;                  // 8 * ndual * 4: members found by each lane of a bucket's group
+  uint8_t* dlcnt;                  // 8 * ndual: their count (more than 4: the lane scans again)
+  int32_t* dual_sample;            // ndual: sample of each bucket
   double4* dfr;                    // CIC fractions (fx, fy, fz, volume)
   double4* fpart;                  // particle drag of the latest evaluation
-  int32_t *dcnt, *doff, *dfill, *dmem, *dmem_tmp;
-  uint8_t* dual_sink;              // ndual: 1 for each sample's skip bucket
   // per-sample, status
   SampleConst* sc;
   unsigned long long* broken;      // per sample
