@@ -58,7 +58,16 @@ typedef enum {
 #define DEM_MAX_WALLS 8
 
 enum { DEM_WALL_PLANE = 0, DEM_WALL_CYL_IN = 1, DEM_WALL_CYL_OUT = 2 };
-enum { DEM_NORMAL_JKR_MOD = 0, DEM_NORMAL_HERTZ = 1, DEM_NORMAL_LINEAR = 2 };
+/* Normal laws.  JKR_MOD: the modified JKR model of section 2.3 (Fig. 2), bonds
+ * set at init (bond_at_init or the given history) break at point C and never
+ * re-form, other contacts are Hertz.  HERTZ: no cohesion.  LINEAR: eq 3, a test
+ * law.  JKR_ORIG: the original JKR cycle of section 2.3 (Fig. 1), the paper's
+ * generation stage: a contact forms whenever two particles touch (point A,
+ * where the force drops to -8/9 F_C), follows eq 12-13 through C and separates
+ * at point S, the smallest overlap of eq 13, (-delta_S)^3 = (27/16) pi^2 gamma^2
+ * R* / E*^2 (separations count in broken_bonds), and forms again on the next
+ * touch. */
+enum { DEM_NORMAL_JKR_MOD = 0, DEM_NORMAL_HERTZ = 1, DEM_NORMAL_LINEAR = 2, DEM_NORMAL_JKR_ORIG = 3 };
 enum { DEM_VOID_CIC = 0, DEM_VOID_CENTROID = 1 };
 enum { DEM_OUTLET_NONE = 0, DEM_OUTLET_CAVITY = 1 };
 enum { DEM_PREC_FP64 = 0, DEM_PREC_MIXED = 1 };
@@ -114,7 +123,7 @@ typedef struct {
   double outlet[4];         /* CAVITY: axis x, axis y, radius; centres inside leave */
   dem_wall walls[DEM_MAX_WALLS];
   int32_t precision;        /* DEM_PREC_FP64 or DEM_PREC_MIXED (same for all samples) */
-  int32_t bond_at_init;     /* 1: every touching pair starts bonded (JKR_MOD only)  */
+  int32_t bond_at_init;     /* 1: every touching pair starts bonded (JKR_MOD, ORIG) */
   int64_t pair_capacity;    /* half-pair capacity; <= 0: automatic (grows at every
                                rebuild as needed).  > 0 without DEM_FLAG_AUTO_REGROW
                                (sample 0's value): fixed -- a rebuild that needs

@@ -24,7 +24,7 @@ SRC = os.path.join(HERE, "dem_oracle.c")
 
 MAX_WALLS = 8
 WALL_PLANE, WALL_CYL_IN, WALL_CYL_OUT = 0, 1, 2
-NORMAL_JKR_MOD, NORMAL_HERTZ, NORMAL_LINEAR = 0, 1, 2
+NORMAL_JKR_MOD, NORMAL_HERTZ, NORMAL_LINEAR, NORMAL_JKR_ORIG = 0, 1, 2, 3
 VOID_CIC, VOID_CENTROID = 0, 1
 OUTLET_NONE, OUTLET_CAVITY = 0, 1
 
@@ -83,6 +83,8 @@ def lib():
         L.or_jkr_a_of_delta.argtypes = [d, d, d, d]
         L.or_bond_holds.restype = ctypes.c_int
         L.or_bond_holds.argtypes = [d, d, d, d, d]
+        L.or_contact_holds_to_S.restype = ctypes.c_int
+        L.or_contact_holds_to_S.argtypes = [d, d, d, d, d]
         L.or_beta_of_e.restype = d
         L.or_beta_of_e.argtypes = [d]
         L.or_drag.restype = None
@@ -158,6 +160,10 @@ def jkr_a_of_delta(delta, Rs, Es, gamma):
 
 def bond_holds(d2, c, Rs, Es, gamma):
     return bool(lib().or_bond_holds(d2, c, Rs, Es, gamma))
+
+
+def contact_holds_to_S(d2, c, Rs, Es, gamma):
+    return bool(lib().or_contact_holds_to_S(d2, c, Rs, Es, gamma))
 
 
 def beta_of_e(e):

@@ -87,6 +87,19 @@ int or_bond_holds(double d2, double c, double Rs, double Es, double gamma) {
   return lhs <= rhs;
 }
 
+/* Original JKR (section 2.3, Fig. 1): the contact lasts down to point S, the
+ * smallest overlap of eq 13, where d(delta)/da = 0: a_S^3 = pi gamma R*^2 /
+ * (4 E*), which gives delta_S = -3 (1/16)^(1/3) (pi^2 gamma^2 R* / E*^2)^(1/3),
+ * i.e. (-delta_S)^3 = (27/16) pi^2 gamma^2 R* / E*^2.  Written with cubes, as
+ * the bond test above; delta equal to delta_S holds. */
+int or_contact_holds_to_S(double d2, double c, double Rs, double Es, double gamma) {
+  if (d2 < c * c) return 1;
+  double sep = sqrt(d2) - c;
+  double lhs = (sep * sep) * sep;
+  double rhs = (((27.0 / 16.0) * (M_PI * M_PI)) * (gamma * gamma)) * Rs / (Es * Es);
+  return lhs <= rhs;
+}
+
 /* Critical damping ratio from the restitution coefficient (eq 33, with the
  * square on ln e that the printed equation drops). */
 double or_beta_of_e(double e) {
@@ -330,11 +343,11 @@ or_sim* or_create(const or_params* p, int64_t n, const double* x, const double* 
       s->h[k].i = a; s->h[k].j = b;
       for (int c = 0; c < 3; ++c) s->h[k].dt[c] = pdt ? sg * pdt[3 * k + c] : 0.0;
       s->h[k].bonded = pbond ? pbond[k] : 0;
-      if (p->normal_model != OR_NORMAL_JKR_MOD) s->h[k].bonded = 0;
+      if (p->normal_model != OR_NORMAL_JKR_MOD && p->normal_model != OR_NORMAL_JKR_ORIG) s->h[k].bonded = 0;
     }
     s->nh = npairs;
     qsort(s->h, (size_t)s->nh, sizeof(hrec), cmp_hrec);
-  } else if (bond_at_init && p->normal_model == OR_NORMAL_JKR_MOD) {
+  } else if (bond_at_init && (p->normal_model == OR_NORMAL_JKR_MOD || p->normal_model == OR_NORMAL_JKR_ORIG)) {
     /* every touching pair (delta > 0) starts bonded */
     ipair* buf;
     int64_t cnt = pairs_grid_alloc(n, s->x, s->r, s->alive, 0.0, &buf);
@@ -854,7 +867,16 @@ static void one_step(or_sim* s) {
     double gam = p->gamma;
     if (s->c_coh) gam = p->gamma * sqrt(s->c_coh[i] * s->c_coh[j]);
     int bonded = old ? old->bonded : 0;
-    if (bonded && !or_bond_holds(d2, cc, Rs, s->Es, gam)) {
+    if (p->normal_model == OR_NORMAL_JKR_ORIG) {
+      /* original JKR: a touching pair is in contact (snap-in at point A); the
+       * contact separates below delta_S (point S), counted like a broken bond,
+       * and forms again on the next touch */
+      if (d2 < cc * cc) bonded = 1;
+      if (bonded && !or_contact_holds_to_S(d2, cc, Rs, s->Es, gam)) {
+        s->broken += 1;
+        continue;
+      }
+    } else if (bonded && !or_bond_holds(d2, cc, Rs, s->Es, gam)) {
       s->broken += 1;                       /* broke at point C; never re-forms */
       continue;
     }

@@ -23,7 +23,10 @@
 #define OR_MAX_WALLS 8
 
 enum { OR_WALL_PLANE = 0, OR_WALL_CYL_IN = 1, OR_WALL_CYL_OUT = 2 };
-enum { OR_NORMAL_JKR_MOD = 0, OR_NORMAL_HERTZ = 1, OR_NORMAL_LINEAR = 2 };
+/* JKR_ORIG: the original JKR cycle of section 2.3 (Fig. 1): a contact snaps in
+ * on touch (point A), follows eq 12-13 through C and separates at S, and may
+ * form again on a later touch */
+enum { OR_NORMAL_JKR_MOD = 0, OR_NORMAL_HERTZ = 1, OR_NORMAL_LINEAR = 2, OR_NORMAL_JKR_ORIG = 3 };
 enum { OR_VOID_CIC = 0, OR_VOID_CENTROID = 1 };
 enum { OR_OUTLET_NONE = 0, OR_OUTLET_CAVITY = 1 };
 
@@ -71,6 +74,7 @@ double or_jkr_delta_of_a(double a, double Rs, double Es, double gamma);   /* eq 
 double or_jkr_force_of_a(double a, double Rs, double Es, double gamma);   /* eq 12 */
 double or_jkr_a_of_delta(double delta, double Rs, double Es, double gamma); /* eq 13 inverted */
 int    or_bond_holds(double d2, double c, double Rs, double Es, double gamma);
+int    or_contact_holds_to_S(double d2, double c, double Rs, double Es, double gamma);
 double or_beta_of_e(double e);                                             /* eq 33 (squared) */
 
 /* ---- Di Felice drag on one particle (eq 8-11) ---- */

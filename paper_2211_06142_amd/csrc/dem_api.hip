@@ -150,7 +150,7 @@ dem_status validate(const dem_params& p) {
   if (!(p.rho > 0.0) || !(p.E > 0.0) || !(p.mu >= 0.0) || !(p.mu_roll >= 0.0) || !(p.gamma >= 0.0))
     return DEM_E_INVAL;
   if (p.n_walls < 0 || p.n_walls > DEM_MAX_WALLS) return DEM_E_INVAL;
-  if (p.normal_model < 0 || p.normal_model > 2) return DEM_E_INVAL;
+  if (p.normal_model < 0 || p.normal_model > 3) return DEM_E_INVAL;
   if (p.normal_model == DEM_NORMAL_LINEAR && !(p.k_lin > 0.0)) return DEM_E_INVAL;
   if (p.precision != DEM_PREC_FP64 && p.precision != DEM_PREC_MIXED) return DEM_E_INVAL;
   if (p.fluid_on) {
@@ -174,7 +174,9 @@ void derive(const dem_params& p, const double* x, const double* r, const uint8_t
   c.beta = beta_of_e(p.e);
   c.cdamp = 2.0 * sqrt(5.0 / 6.0) * c.beta;
   c.gamma = p.k * p.gamma;                           // eq 24
-  if (p.normal_model != DEM_NORMAL_JKR_MOD) c.gamma = 0.0;
+  const bool jkr = p.normal_model == DEM_NORMAL_JKR_MOD || p.normal_model == DEM_NORMAL_JKR_ORIG;
+  if (!jkr) c.gamma = 0.0;
+  c.jkr_break = p.normal_model == DEM_NORMAL_JKR_ORIG ? 27.0 / 16.0 : 3.0 / 16.0;
   c.mu = p.mu;
   c.mu_roll = p.mu_roll;
   c.rho = p.rho;
@@ -233,11 +235,12 @@ void derive(const dem_params& p, const double* x, const double* r, const uint8_t
   c.pm_scale = ldexp(1.0, 61 - ex);
   if (rmax == 0.0) { rmin = rmax = 1e-6; }
   c.skin = p.skin > 0.0 ? p.skin : 0.4 * rmin;   // tuned: fewer rebuilds, rows barely longer
-  // largest pull-off separation |delta_C| = (3/16)^(1/3) X (Table 1), with the
-  // surface energy bounded by twice its value (closure factors are <= 2)
+  // largest separation a contact survives, |delta_C| = (3/16)^(1/3) X (Table 1),
+  // or |delta_S| = (27/16)^(1/3) X for the original JKR cycle, with the surface
+  // energy bounded by twice its value (closure factors are <= 2)
   double gmax = 2.0 * c.gamma;
   double Rsmax = 0.5 * rmax;
-  double dC = cbrt(3.0 / 16.0) * cbrt((kPi * kPi) * gmax * gmax * Rsmax / (c.Es * c.Es));
+  double dC = cbrt(c.jkr_break) * cbrt((kPi * kPi) * gmax * gmax * Rsmax / (c.Es * c.Es));
   c.margin = c.skin + 1.01 * dC;
   double h = 2.0 * rmax + c.margin;
   double ext[3];
@@ -894,7 +897,7 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
       spart[q] = (int32_t)b;
       double sg = hp[2 * k] < hp[2 * k + 1] ? 1.0 : -1.0;
       pfl[q] = hb.empty() ? 0 : (hb[k] ? 1 : 0);
-      if (params[0].normal_model != DEM_NORMAL_JKR_MOD) pfl[q] = 0;
+      if (params[0].normal_model != DEM_NORMAL_JKR_MOD && params[0].normal_model != DEM_NORMAL_JKR_ORIG) pfl[q] = 0;
       double t3[3] = {0, 0, 0};
       if (!hdt.empty()) for (int e = 0; e < 3; ++e) t3[e] = sg * hdt[3 * k + e];
       if (c->fp64) ((double4*)ph.data())[q] = make_double4(t3[0], t3[1], t3[2], 0.0);

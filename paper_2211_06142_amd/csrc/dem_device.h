@@ -115,21 +115,38 @@ __device__ inline bool wall_geom(const Wall& w, double x, double y, double z, do
 // eq 13 becomes b^4 - 2 b = D and eq 12 F = pi gamma R* (4/3 b^6 - 4 b^3).
 // The branch through point C (b_C^3 = 3/2) is taken: two fixed-point steps of
 // b = (D + 2b)^(1/4) from b_C, then Newton on the convex increasing quartic.
+// The original JKR cycle reaches below C down to point S (b_S^3 = 1/2, where
+// the quartic's slope vanishes): from above the root both iterations decrease
+// monotonically towards it, more Newton steps are taken, each kept on the
+// branch (b >= b_S).
 template <typename R>
-__device__ inline void jkr_bonded(R delta, R Rs, R gam, R jkrK, R& a, R& Fel) {
+__device__ inline void jkr_bonded(R delta, R Rs, R gam, R jkrK, R& a, R& Fel, bool to_S) {
   constexpr R kPi = (R)3.14159265358979323846;
   constexpr R kbC = (R)1.1447142425533319;   // (3/2)^(1/3)
+  constexpr R kbS = (R)0.79370052598409974;  // (1/2)^(1/3)
   constexpr int kNewton = sizeof(R) == 8 ? 3 : 2;
+  constexpr int kNewtonS = sizeof(R) == 8 ? 12 : 8;
   R X = rcbrt_<R>(jkrK * Rs);
   R D = delta * frcp_<R>(X);
   R b = fsqrt_<R>(fsqrt_<R>(D + (R)2 * kbC));
   b = fsqrt_<R>(fsqrt_<R>(D + (R)2 * b));
+  if (!to_S) {
 #pragma unroll
-  for (int it = 0; it < kNewton; ++it) {
-    R b3 = b * b * b;
-    R f = b3 * b - (R)2 * b - D;
-    R fp = (R)4 * b3 - (R)2;
-    b -= f * frcp_<R>(fp);
+    for (int it = 0; it < kNewton; ++it) {
+      R b3 = b * b * b;
+      R f = b3 * b - (R)2 * b - D;
+      R fp = (R)4 * b3 - (R)2;
+      b -= f * frcp_<R>(fp);
+    }
+  } else {
+    for (int it = 0; it < kNewtonS; ++it) {
+      R b3 = b * b * b;
+      R f = b3 * b - (R)2 * b - D;
+      R fp = (R)4 * b3 - (R)2;
+      if (!(fp > (R)0)) break;
+      b -= f * frcp_<R>(fp);
+      if (b < kbS) b = kbS;
+    }
   }
   R b3 = b * b * b;
   R u = kPi * gam * Rs;
@@ -141,13 +158,16 @@ __device__ inline void jkr_bonded(R delta, R Rs, R gam, R jkrK, R& a, R& Fel) {
 template <typename R> struct LawK {
   R Es, Gs, beta, cdamp, mu, mu_roll, k_lin;
   bool linear;
+  bool orig;   // original JKR cycle: contacts form on touch, hold down to point S
 };
 template <typename R> __device__ inline LawK<R> law_k(const SampleConst& c);
 template <> __device__ inline LawK<double> law_k<double>(const SampleConst& c) {
-  return {c.Es, c.Gs, c.beta, c.cdamp, c.mu, c.mu_roll, c.k_lin, c.normal_model == DEM_NORMAL_LINEAR};
+  return {c.Es, c.Gs, c.beta, c.cdamp, c.mu, c.mu_roll, c.k_lin, c.normal_model == DEM_NORMAL_LINEAR,
+          c.normal_model == DEM_NORMAL_JKR_ORIG};
 }
 template <> __device__ inline LawK<float> law_k<float>(const SampleConst& c) {
-  return {c.f_Es, c.f_Gs, c.f_beta, c.f_cdamp, c.f_mu, c.f_mu_roll, c.f_k_lin, c.normal_model == DEM_NORMAL_LINEAR};
+  return {c.f_Es, c.f_Gs, c.f_beta, c.f_cdamp, c.f_mu, c.f_mu_roll, c.f_k_lin, c.normal_model == DEM_NORMAL_LINEAR,
+          c.normal_model == DEM_NORMAL_JKR_ORIG};
 }
 
 template <typename R> struct LawOut {
@@ -173,7 +193,7 @@ __device__ inline void contact_law(const LawK<R>& c, int bonded, R delta, R Rs, 
     L = c.mu * Fel;
   } else {
     if (bonded && gam > (R)0) {
-      jkr_bonded<R>(delta, Rs, gam, jkrK, a, Fel);
+      jkr_bonded<R>(delta, Rs, gam, jkrK, a, Fel, c.orig);
       L = c.mu * (Fel + (R)2 * ((R)3 * (R)3.14159265358979323846 * gam * Rs));
     } else {
       a = fsqrt_<R>(Rs * (delta > (R)0 ? delta : (R)0));
@@ -233,13 +253,14 @@ __device__ inline void contact_law(const LawK<R>& c, int bonded, R delta, R Rs, 
 }
 
 // Bond persistence down to the pull-off overlap of point C (Table 1, Fig. 2),
-// written with cubes so that no cube root enters the decision:
-// (-delta)^3 <= (3/16) pi^2 gamma^2 R* / E*^2.  Same operation order as the
-// FP64 reference definition; called only for bonded pairs that do not touch.
-__device__ inline bool bond_holds_apart(double d2, double cs, double Rsd, double gam, double Es) {
+// or for the original JKR cycle down to point S, written with cubes so that no
+// cube root enters the decision: (-delta)^3 <= brk pi^2 gamma^2 R* / E*^2 with
+// brk = 3/16 (C) or 27/16 (S).  Same operation order as the FP64 reference
+// definition; called only for bonded pairs that do not touch.
+__device__ inline bool bond_holds_apart(double d2, double cs, double Rsd, double gam, double Es, double brk) {
   double sep = sqrt(d2) - cs;
   double lhs = (sep * sep) * sep;
-  double rhs = ((3.0 / 16.0) * (M_PI * M_PI)) * (gam * gam) * Rsd / (Es * Es);
+  double rhs = ((brk * (M_PI * M_PI)) * (gam * gam)) * Rsd / (Es * Es);
   return lhs <= rhs;
 }
 
@@ -263,8 +284,10 @@ __device__ inline void pair_eval(const LawK<R>& c, double Es, double dt, bool ro
   const double d2 = (dx * dx + dy * dy) + dz * dz;
   const double cs = A.w + B.w;
   const bool touching = d2 < cs * cs;
-  const int bonded = fl & 1;
-  if (bonded && !touching && !bond_holds_apart(d2, cs, A.w * B.w / (A.w + B.w), gam, Es)) {
+  // the original JKR cycle bonds every touching pair (snap-in at point A)
+  const int bonded = (fl & 1) | ((c.orig && touching) ? 1 : 0);
+  if (bonded && !touching &&
+      !bond_holds_apart(d2, cs, A.w * B.w / (A.w + B.w), gam, Es, c.orig ? 27.0 / 16.0 : 3.0 / 16.0)) {
     out.broke = true;
     out.h = mk4<R>(0, 0, 0, 0);
     out.fl = 0;

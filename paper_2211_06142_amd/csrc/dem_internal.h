@@ -50,6 +50,8 @@ struct SampleConst {
   // the contact constants rounded to FP32 (the mixed-precision force path)
   float f_Es, f_Gs, f_beta, f_cdamp, f_mu, f_mu_roll, f_k_lin;
   int normal_model;
+  double jkr_break;               // bonded pairs apart hold while (-delta)^3 <= jkr_break pi^2 gamma^2 R*/E*^2:
+                                  // 3/16 (point C, modified JKR) or 27/16 (point S, original JKR)
   int fluid_on, voidfrac, u_superficial;
   double rho_f, mu_f, n_min;
   double glo[3], gh[3], vcell;    // fluid grid

@@ -490,7 +490,7 @@ __global__ void k_mark_bonds(DevState d) {
   if (p >= d.nslots) return;
   int32_t i = d.sown[p], j = d.spart[p];
   const SampleConst& c = sample_const(d.sc, d.sample[i]);
-  if (c.normal_model != DEM_NORMAL_JKR_MOD) return;
+  if (c.normal_model != DEM_NORMAL_JKR_MOD && c.normal_model != DEM_NORMAL_JKR_ORIG) return;
   double4 a = d.xr[d.cur][i], b = d.xr[d.cur][j];
   double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
   double d2 = (dx * dx + dy * dy) + dz * dz;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdem.so")
 DEM_OK, DEM_E_INVAL, DEM_E_NOMEM, DEM_E_CAPACITY, DEM_E_NONFINITE, DEM_E_DEVICE, DEM_E_STATE = 0, -1, -2, -3, -4, -5, -6
 DEM_MAX_WALLS = 8
 DEM_WALL_PLANE, DEM_WALL_CYL_IN, DEM_WALL_CYL_OUT = 0, 1, 2
-DEM_NORMAL_JKR_MOD, DEM_NORMAL_HERTZ, DEM_NORMAL_LINEAR = 0, 1, 2
+DEM_NORMAL_JKR_MOD, DEM_NORMAL_HERTZ, DEM_NORMAL_LINEAR, DEM_NORMAL_JKR_ORIG = 0, 1, 2, 3
 DEM_VOID_CIC, DEM_VOID_CENTROID = 0, 1
 DEM_OUTLET_NONE, DEM_OUTLET_CAVITY = 0, 1
 DEM_PREC_FP64, DEM_PREC_MIXED = 0, 1

@@ -45,7 +45,7 @@ def build(force=True):
     if not force and os.path.exists(LIB_PATH):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp,
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp,
                            os.path.join(HERE, "packing.c"), "-lm"])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -64,6 +64,8 @@ def _L():
         L.settle_packing.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                      ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double]
+        L.settle_packing_jacobi.restype = ctypes.c_double
+        L.settle_packing_jacobi.argtypes = L.settle_packing.argtypes
         _lib = L
     return _lib
 
@@ -86,9 +88,11 @@ def sample_diameters(rng, n, psd=PSD):
 # packings
 # ---------------------------------------------------------------------------
 def settle(r, region_kind, region, rng, phi_start=0.25, shrink=0.998, iters=2000,
-           settle_iters=600, relax=1.0):
+           settle_iters=600, relax=1.0, parallel=False):
     """Random start in a dilute column, then geometric settling (packing.c).
-    region_kind 0: box (x0,y0,z0,x1,y1,z1); 1: annulus (cx,cy,r_in,r_out,z0,z1)."""
+    region_kind 0: box (x0,y0,z0,x1,y1,z1); 1: annulus (cx,cy,r_in,r_out,z0,z1).
+    parallel: the OpenMP Jacobi sweep (deterministic for any thread count; for
+    millions of spheres), else the serial Gauss-Seidel sweep."""
     n = r.size
     vs = float(np.sum(4.0 / 3.0 * math.pi * r ** 3))
     if region_kind == 0:
@@ -116,7 +120,8 @@ def settle(r, region_kind, region, rng, phi_start=0.25, shrink=0.998, iters=2000
     prm = np.ascontiguousarray(region, dtype=np.float64)
     x = np.ascontiguousarray(x)
     rr = np.ascontiguousarray(r, dtype=np.float64)
-    worst = _L().settle_packing(n, x.ctypes.data_as(ctypes.c_void_p), rr.ctypes.data_as(ctypes.c_void_p),
+    fn = _L().settle_packing_jacobi if parallel else _L().settle_packing
+    worst = fn(n, x.ctypes.data_as(ctypes.c_void_p), rr.ctypes.data_as(ctypes.c_void_p),
                                 region_kind, prm.ctypes.data_as(ctypes.c_void_p), shrink, iters,
                                 settle_iters, drop, relax)
     return x, worst
@@ -230,7 +235,7 @@ def c0():
 
 
 def cylinder_workload(n, seed, name, k=1.0, scheme="ssw", R=12e-3, r_cav=2e-3, H=6e-3,
-                      grid_n=(48, 48, 24), U_cav=0.5, psd_sample_n=None):
+                      grid_n=(48, 48, 24), U_cav=0.5, psd_sample_n=None, parallel=False):
     """Hollow cylinder (axis z), outer Hertz wall, floor and a top plate on the
     settled bed; the cavity r < r_cav is the outlet.  k > 1: grains, SSW (each
     sampled fine diameter times k) or SSP (one diameter, k times the mass-mean
@@ -245,7 +250,10 @@ def cylinder_workload(n, seed, name, k=1.0, scheme="ssw", R=12e-3, r_cav=2e-3, H
         else:
             d = k * sample_diameters(rng, n)
         r = 0.5 * d
-        x, worst = settle(r, 1, (0.0, 0.0, r_cav, R, 0.0, H), rng)
+        if parallel:
+            x, worst = settle(r, 1, (0.0, 0.0, r_cav, R, 0.0, H), rng, parallel=True, relax=0.7)
+        else:
+            x, worst = settle(r, 1, (0.0, 0.0, r_cav, R, 0.0, H), rng)
         return {"x": x, "r": r, "worst": np.array(worst)}
 
     pk = cached(name, make)
@@ -262,16 +270,27 @@ def cylinder_workload(n, seed, name, k=1.0, scheme="ssw", R=12e-3, r_cav=2e-3, H
                 outlet=(0.0, 0.0, r_cav), dt=DT, g=GRAV, sha256=str(pk["sha256"]), bed_top=top)
 
 
-def c1(n=200000):
-    w = cylinder_workload(n, SEED0 + 1, "c1" if n == 200000 else "c1_n%d" % n)
+def c1(n=200000, seed=0):
+    """seed 0: the benchmark's packing; seeds 1, 2, ...: other packings of the
+    same configuration (held-out runs of the learned closure), made with the
+    parallel packer"""
+    if seed == 0:
+        w = cylinder_workload(n, SEED0 + 1, "c1" if n == 200000 else "c1_n%d" % n)
+    else:
+        w = cylinder_workload(n, SEED0 + 1 + 100 * seed, "c1_n%d_s%d" % (n, seed), parallel=True)
     w.update(precision="mixed", steps=5000, n_fine=n)
     return w
 
 
-def c2(k=2, scheme="ssw", n_fine=200000):
+def c2(k=2, scheme="ssw", n_fine=200000, seed=0):
     n = int(round(n_fine / k ** 3))
-    w = cylinder_workload(n, SEED0 + 2 + 10 * int(k) + (1 if scheme == "ssp" else 0),
-                          "c2_k%d_%s_n%d" % (k, scheme, n_fine), k=float(k), scheme=scheme)
+    if seed == 0:
+        w = cylinder_workload(n, SEED0 + 2 + 10 * int(k) + (1 if scheme == "ssp" else 0),
+                              "c2_k%d_%s_n%d" % (k, scheme, n_fine), k=float(k), scheme=scheme)
+    else:
+        w = cylinder_workload(n, SEED0 + 2 + 10 * int(k) + (1 if scheme == "ssp" else 0) + 100 * seed,
+                              "c2_k%d_%s_n%d_s%d" % (k, scheme, n_fine, seed), k=float(k), scheme=scheme,
+                              parallel=True)
     w.update(precision="mixed", steps=5000, n_fine=n_fine)
     return w
 
@@ -286,7 +305,7 @@ def c4(k=1, scheme="ssw"):
     n = int(round(n_fine / k ** 3))
     w = cylinder_workload(n, SEED0 + 4 + 10 * int(k) + (1 if scheme == "ssp" else 0),
                           "c4_k%d_%s" % (k, scheme), k=float(k), scheme=scheme, R=12e-3 * s, r_cav=2e-3 * s,
-                          H=6e-3 * s, grid_n=(103, 103, 52))
+                          H=6e-3 * s, grid_n=(103, 103, 52), parallel=True)
     w.update(precision="mixed", steps=5000, n_fine=n_fine)
     return w
 

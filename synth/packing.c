@@ -205,3 +205,139 @@ double settle_packing(int64_t n, double* x, const double* r, int kind, const dou
   free(rr); free(tmp); free(xref); free(pi); free(pj);
   return worst;
 }
+
+/*
+ * settle_packing_jacobi: the same settling as settle_packing for large n,
+ * parallel (OpenMP) and deterministic for any thread count.  Each iteration
+ * shifts every sphere down (as above), then removes overlaps by a Jacobi sweep:
+ * every sphere gathers, over its own neighbour row (all spheres within
+ * r_i + r_j + skin, found by a search of the grid cells around it, in a fixed
+ * cell order), the displacement its share of each overlap asks for, and all
+ * spheres then move at once by `relax` times their sum; then confinement.  Rows
+ * are rebuilt when a sphere has moved more than half the skin.
+ */
+static void rows_build(int64_t n, const double* x, const double* rr, double rmax, double h, double skin,
+                       int64_t** rowp, int64_t** cols, int64_t* cap) {
+  grid_t g;
+  grid_build(&g, n, x, h);
+  int64_t* cnt = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+      if (cnt[n] > *cap) {
+        *cap = cnt[n] + cnt[n] / 4 + 1024;
+        *cols = (int64_t*)realloc(*cols, sizeof(int64_t) * (size_t)*cap);
+      }
+    }
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+      double R = rr[i] + rmax + skin;
+      int64_t k0[3], k1[3];
+      for (int c = 0; c < 3; ++c) {
+        k0[c] = clampi((int64_t)floor((x[3 * i + c] - R - g.lo[c]) / h), 0, g.nc[c] - 1);
+        k1[c] = clampi((int64_t)floor((x[3 * i + c] + R - g.lo[c]) / h), 0, g.nc[c] - 1);
+      }
+      int64_t at = pass == 1 ? cnt[i] : 0, m = 0;
+      for (int64_t kz = k0[2]; kz <= k1[2]; ++kz)
+        for (int64_t ky = k0[1]; ky <= k1[1]; ++ky)
+          for (int64_t kx = k0[0]; kx <= k1[0]; ++kx) {
+            int64_t cid = (kz * g.nc[1] + ky) * g.nc[0] + kx;
+            for (int64_t q = g.start[cid]; q < g.start[cid + 1]; ++q) {
+              int64_t j = g.idx[q];
+              if (j == i) continue;
+              double d2 = 0.0;
+              for (int c = 0; c < 3; ++c) { double d = x[3 * j + c] - x[3 * i + c]; d2 += d * d; }
+              double cc = rr[i] + rr[j] + skin;
+              if (d2 >= cc * cc) continue;
+              if (pass == 1) (*cols)[at + m] = j;
+              ++m;
+            }
+          }
+      if (pass == 0) cnt[i + 1] = m;
+    }
+  }
+  free(*rowp);
+  *rowp = cnt;
+  grid_free(&g);
+}
+
+double settle_packing_jacobi(int64_t n, double* x, const double* r, int kind, const double* prm, double shrink,
+                             int iters, int settle_iters, double drop, double relax) {
+  double* rr = (double*)malloc(sizeof(double) * (size_t)n);
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)n);
+  double* xref = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  double* disp = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    rr[i] = r[i] * shrink;
+    tmp[i] = rr[i];
+    if (rr[i] > rmax) rmax = rr[i];
+  }
+  qsort(tmp, (size_t)n, sizeof(double), cmpd);
+  double rmed = tmp[n / 2];
+  double h = 2.0 * rmed;
+  double skin = 0.5 * rmed;
+  int64_t *rowp = NULL, *cols = NULL, cap = 0;
+  double cum = 0.0;
+  int need = 1;
+  double worst = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    double dz = 0.0;
+    if (it < settle_iters) dz = drop * (1.0 - (double)it / (double)settle_iters);
+    cum += dz;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      x[3 * i + 2] -= dz;
+      confine(kind, prm, rr[i], &x[3 * i]);
+    }
+    if (!need) {
+      double m2 = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : m2)
+      for (int64_t i = 0; i < n; ++i) {
+        double d0 = x[3 * i] - xref[3 * i], d1 = x[3 * i + 1] - xref[3 * i + 1];
+        double d2 = x[3 * i + 2] - (xref[3 * i + 2] - cum);
+        double q = d0 * d0 + d1 * d1 + d2 * d2;
+        if (q > m2) m2 = q;
+      }
+      if (m2 > 0.25 * skin * skin) need = 1;
+    }
+    if (need) {
+      rows_build(n, x, rr, rmax, h, skin, &rowp, &cols, &cap);
+      memcpy(xref, x, sizeof(double) * 3 * (size_t)n);
+      cum = 0.0;
+      need = 0;
+    }
+    double w = 0.0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(max : w)
+    for (int64_t i = 0; i < n; ++i) {
+      double s[3] = {0.0, 0.0, 0.0};
+      double vi = rr[i] * rr[i] * rr[i];
+      for (int64_t e = rowp[i]; e < rowp[i + 1]; ++e) {
+        int64_t j = cols[e];
+        double d[3], d2 = 0.0;
+        for (int c = 0; c < 3; ++c) { d[c] = x[3 * j + c] - x[3 * i + c]; d2 += d[c] * d[c]; }
+        double cc = rr[i] + rr[j];
+        if (d2 >= cc * cc) continue;
+        double dist = sqrt(d2);
+        double ov = cc - dist;
+        double rel = ov / (rr[j] < rr[i] ? rr[j] : rr[i]);
+        if (rel > w) w = rel;
+        double nn[3];
+        if (dist > 0.0) { for (int c = 0; c < 3; ++c) nn[c] = d[c] / dist; }
+        else { nn[0] = 0.0; nn[1] = 0.0; nn[2] = (i < j) ? 1.0 : -1.0; }
+        double vj = rr[j] * rr[j] * rr[j];
+        double si = ov * vj / (vi + vj);
+        for (int c = 0; c < 3; ++c) s[c] -= si * nn[c];
+      }
+      for (int c = 0; c < 3; ++c) disp[3 * i + c] = s[c];
+    }
+    worst = w;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      for (int c = 0; c < 3; ++c) x[3 * i + c] += relax * disp[3 * i + c];
+      confine(kind, prm, rr[i], &x[3 * i]);
+    }
+  }
+  free(rr); free(tmp); free(xref); free(disp); free(rowp); free(cols);
+  return worst;
+}

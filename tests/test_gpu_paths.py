@@ -14,6 +14,7 @@ import pytest
 import oracle
 import synth
 from oracle import cg
+from synth import scenes
 
 pytestmark = pytest.mark.gpu
 
@@ -284,3 +285,64 @@ def test_half_pairs_equal_full_rows_bitwise(case, lanes):
     assert ia["rebuilds"] == ib["rebuilds"]
     for k, (x, y) in enumerate(zip(a, b)):
         assert np.array_equal(x, y), k
+
+
+# ---------------------------------------------------------------------------
+# the original JKR cycle (section 2.3, Fig. 1): snap-in, separation at S, re-forming
+# ---------------------------------------------------------------------------
+def test_original_jkr_two_spheres_match_oracle():
+    """a contact pulled apart past C separates at S on the same step as in the
+    oracle, with the same forces on every step; brought back, it forms again at
+    touch with the same snap-in force"""
+    r = 7.5e-5
+    Rs = r / 2
+    Es, _ = oracle.effective_moduli(70e6, 0.3)
+    X = (math.pi ** 2 * 0.25 * Rs / Es ** 2) ** (1 / 3)
+    mat = dict(synth.MATERIAL, e=1.0, mu=0.0, rho=1e9)
+    x, rr, v = scenes.two_spheres(r, r, -0.5 * X, -2e-3)
+    p = dem.make_params(mat, 1e-7, g=(0, 0, 0), normal_model=dem.DEM_NORMAL_JKR_ORIG, bond_at_init=True)
+    op = oracle.make_params(mat, 1e-7, g=(0, 0, 0), normal_model=oracle.NORMAL_JKR_ORIG)
+    for phase in range(2):
+        g = dem.Simulation(p, x, rr, v=v)
+        o = oracle.OracleSim(op, x, rr, v=v, bond_at_init=True)
+        sep_g = sep_o = None
+        for k in range(5000):
+            g.step(1)
+            o.step(1)
+            sg, so = g.state(), o.state()
+            fs = 3 * math.pi * 0.5 * Rs
+            assert np.max(np.abs(sg["F"] - so["F"])) <= 1e-10 * fs, k
+            if sep_g is None and sg["broken_bonds"] == 1:
+                sep_g = k
+            if sep_o is None and o.scalars()["broken_bonds"] == 1:
+                sep_o = k
+            if phase == 1 and np.linalg.norm(sg["x"][1] - sg["x"][0]) < 2 * r:
+                assert g.pairs()["bonded"][0] == 1 and o.pairs()["bonded"][0] == 1
+                assert -sg["F"][0, 0] == pytest.approx(-8.0 / 9.0 * fs, rel=1e-2)
+                break
+            if phase == 0 and sep_g is not None and sep_o is not None:
+                break
+        if phase == 0:
+            assert sep_g is not None and sep_g == sep_o
+            x, v = sg["x"], -sg["v"]          # back together from where it separated
+
+
+def test_original_jkr_box_fp64():
+    """the moving c0 box with the original cycle: contacts form, separate and
+    form again; 30 FP64 steps against the oracle"""
+    w, v = c0_moving(sigma=0.5, seed=8)
+    w = dict(w)
+    p = dem.params_from_workload(w, precision="fp64")
+    p.normal_model = dem.DEM_NORMAL_JKR_ORIG
+    g = dem.Simulation(p, w["x"], w["r"], v=v)
+    g.map_fluid(w["u_cell"], w["gradp_cell"])
+    m = cg.scale_material(w["material"], 1.0)
+    op = oracle.make_params(m, w["dt"], g=w["g"], walls=w["walls"], grid=w["grid"], fluid=w["fluid"],
+                            outlet=w["outlet"], normal_model=oracle.NORMAL_JKR_ORIG)
+    o = oracle.OracleSim(op, w["x"], w["r"], v=v, bond_at_init=True)
+    o.set_fluid(w["u_cell"], w["gradp_cell"])
+    for k in range(3):
+        g.step(10)
+        o.step(10)
+        gs, sc = compare_fp64(g, o, what="orig jkr step %d" % (10 * (k + 1)))
+    assert sc["broken_bonds"] > 0

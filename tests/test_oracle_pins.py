@@ -770,3 +770,111 @@ def test_porosity_interpolated_between_cell_centres():
     n_exp = 1.0 - (a0 + (probes - mid) @ bv) / vcell
     np.testing.assert_allclose(feat[nc:, 0], n_exp, rtol=1e-12)
     np.testing.assert_allclose(feat[:nc, 0], 1.0 - Vc / vcell, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# section 2.3, Fig. 1: the original JKR cycle (snap-in at A, separation at S)
+# ---------------------------------------------------------------------------
+def test_original_jkr_point_S_closed_forms():
+    """Point S, where the contact of the original JKR model breaks, is the
+    smallest overlap of eq 13: with X^3 = pi^2 gamma^2 R*/E*^2 and
+    a = sqrt(X R*) b^2, eq 13 reads delta = X (b^4 - 2 b), smallest at
+    b^3 = 1/2: delta_S = -3 2^(-4/3) X, a_S^3 = pi gamma R*^2 / (4 E*), and eq 12
+    (F = pi gamma R* (4/3 b^6 - 4 b^3)) gives F_S = -5/3 pi gamma R* = -5/9 F_C.
+    The contact holds at delta_S and separates just below it; the modified
+    model's bond breaks earlier, at C."""
+    X = X_of()
+    dS = -3.0 * 2.0 ** (-4.0 / 3.0) * X
+    aS = (math.pi * GAM * RS ** 2 / (4.0 * ES)) ** (1.0 / 3.0)
+    assert oracle.jkr_force_of_a(aS, RS, ES, GAM) == pytest.approx(-5.0 / 3.0 * math.pi * GAM * RS, rel=1e-13)
+    assert oracle.jkr_delta_of_a(aS, RS, ES, GAM) == pytest.approx(dS, rel=1e-13)
+    # the inversion reaches S (ill-conditioned there: d delta / d a = 0)
+    assert oracle.jkr_a_of_delta(dS, RS, ES, GAM) == pytest.approx(aS, rel=1e-6)
+    r1 = r2 = 2 * RS
+    c = r1 + r2
+    for frac, holds in [(0.999999, True), (1.000001, False), (0.5, True)]:
+        dist = c - frac * dS
+        assert oracle.contact_holds_to_S(dist * dist, c, RS, ES, GAM) == holds, frac
+    dist = c - 0.6 * dS          # between C and S: the bond of the modified model is gone
+    assert oracle.contact_holds_to_S(dist * dist, c, RS, ES, GAM)
+    assert not oracle.bond_holds(dist * dist, c, RS, ES, GAM)
+
+
+def test_original_jkr_work_of_separation():
+    """The work to separate an original JKR contact from A (delta = 0) to S:
+    with delta = X (b^4 - 2 b) and F = pi gamma R* (4/3 b^6 - 4 b^3),
+    F d(delta) = pi gamma R* X (16/3 b^9 - 56/3 b^6 + 8 b^3) db, whose
+    antiderivative is 8/15 b^10 - 8/3 b^7 + 2 b^4, from b_S = 2^(-1/3) to
+    b_A = 2^(1/3): W = 3.34129 pi gamma R* X.  The oracle's force-overlap curve
+    (the inversion of eq 13 on its whole branch A..C..S) integrated over overlap
+    gives the same."""
+    X = X_of()
+    dS = -3.0 * 2.0 ** (-4.0 / 3.0) * X
+
+    def P(b):
+        return 8.0 / 15.0 * b ** 10 - 8.0 / 3.0 * b ** 7 + 2.0 * b ** 4
+
+    W_exact = math.pi * GAM * RS * X * (P(2.0 ** (1.0 / 3.0)) - P(2.0 ** (-1.0 / 3.0)))
+    assert W_exact / (math.pi * GAM * RS * X) == pytest.approx(-3.34129, abs=1e-5)
+
+    def F(d):
+        return oracle.jkr_force_of_a(oracle.jkr_a_of_delta(d, RS, ES, GAM), RS, ES, GAM)
+
+    W, _ = integrate.quad(F, dS * (1 - 1e-12), 0.0, epsabs=0, epsrel=1e-10, limit=400)
+    assert W == pytest.approx(W_exact, rel=1e-6)
+
+
+def test_original_jkr_pull_off_separation_and_snap_in():
+    """Two spheres in the original JKR model pulled apart quasi-statically: the
+    tensile force peaks at F_C = 3 pi gamma R* (point C) and the contact keeps
+    holding past C (force falling towards -5/9 F_C) until the overlap passes
+    delta_S, where it separates (counted once); brought back together, the
+    contact forms again at touch with the force of point A, -8/9 F_C."""
+    r = 7.5e-5
+    Rs = r / 2
+    X = X_of(Rs, ES, GAM)
+    dC = -(3.0 / 16.0) ** (1 / 3) * X
+    dS = -3.0 * 2.0 ** (-4.0 / 3.0) * X
+    FC = 3 * math.pi * GAM * Rs
+    mat = scenes.material(e=1.0, mu=0.0, rho=1e9)
+    dt = 1e-7
+    x, rr, v = scenes.two_spheres(r, r, -0.5 * X, -2e-3)
+    p = _params(mat, dt, g=(0, 0, 0), normal_model=oracle.NORMAL_JKR_ORIG)
+    sim = oracle.OracleSim(p, x, rr, v=v, bond_at_init=True)
+    fmin, sep, last_before = 0.0, None, None
+    prev = None
+    for k in range(4000):
+        sim.step(1)
+        st = sim.state()
+        delta = 2 * r - np.linalg.norm(st["x"][1] - st["x"][0])
+        Fel = -st["F"][0, 0]
+        if sim.scalars()["broken_bonds"] == 1:
+            sep = (prev, delta)
+            assert Fel == 0.0
+            break
+        fmin = min(fmin, Fel)
+        last_before = (delta, Fel)
+        prev = delta
+    assert sep is not None and sep[1] < dS <= sep[0]
+    assert fmin == pytest.approx(-FC, rel=1e-6)
+    assert last_before[0] < dC                            # held past point C
+    # the force-overlap curve is vertical at S (d delta / d a = 0), so one step
+    # before separating (overlap 2e-10 m from S against X = 4e-7 m) the force
+    # is still a few percent from F_S
+    assert last_before[1] == pytest.approx(-5.0 / 9.0 * FC, rel=5e-2)
+    # back together: snap-in at touch
+    st = sim.state()
+    sim2 = oracle.OracleSim(p, st["x"], rr, v=-st["v"], bond_at_init=False)
+    for k in range(4000):
+        sim2.step(1)
+        s2 = sim2.state()
+        d = np.linalg.norm(s2["x"][1] - s2["x"][0])
+        Fel = -s2["F"][0, 0]
+        if d >= 2 * r:
+            assert Fel == 0.0
+            continue
+        assert Fel == pytest.approx(-8.0 / 9.0 * FC, rel=1e-2)
+        assert sim2.pairs()["bonded"][0] == 1
+        break
+    else:
+        raise AssertionError("no contact")
