@@ -218,6 +218,34 @@ dem_status dem_step(dem_ctx* ctx, int64_t nsteps);
 dem_status dem_map_fluid(dem_ctx* ctx, const double* u_cell, const double* gradp_cell,
                          double* eps_solid_out, double* fdrag_out);
 
+/* The fluid side of the coupling (section 2.2, eq 6, model A) in its
+ * drag-dominated limit: with the unsteady, advective and viscous terms small
+ * against the pressure gradient and the particle-fluid force (the packed bed
+ * at low particle Reynolds number), eq 6 reduces to n grad(p) = -beta u and,
+ * with the bed at rest relative to the fluid, div(n u) = 0 to the pressure
+ * equation div(K grad p) = 0 with K = n^2 / beta.  beta per cell is the drag
+ * coefficient of the latest coupling evaluation (|eq 7 drag source| /
+ * |interstitial velocity|) plus 12 mu_f / h_min^2, the viscous resistance of
+ * flow between plates one cell apart (particle-free cells); n is that
+ * evaluation's porosity.  Cell-centred finite volumes on each sample's grid
+ * (face coefficient: harmonic mean of K), solved by conjugate gradients with
+ * the diagonal as preconditioner to |r| <= rel_tol |b| or max_iter iterations,
+ * warm-started from the previous solution.  cell_kind (int8, ncell):
+ * DEM_CELL_OPEN unknown pressure, DEM_CELL_PRESSURE pressure p_fixed (the
+ * outlets and inlets), DEM_CELL_SOLID no flow (walls); the outer boundary of
+ * the grid carries no flow.  Each connected set of open cells must reach a
+ * fixed-pressure cell.  Outputs (host, device or NULL): p_out (ncell, dynamic
+ * pressure), u_out (3 ncell, superficial velocity n u: the mean of each axis's
+ * two face fluxes) and gradp_out (3 ncell, mean one-sided differences): the
+ * fields dem_map_fluid takes for the next evaluations (with u_superficial 1),
+ * which closes the two-way coupling.  iters, rel_residual: host (may be NULL).
+ * DEM_E_INVAL for a missing input, a kind outside 0..2, max_iter < 0 or
+ * rel_tol <= 0; DEM_E_STATE without fluid cells.  Synchronises. */
+enum { DEM_CELL_OPEN = 0, DEM_CELL_PRESSURE = 1, DEM_CELL_SOLID = 2 };
+dem_status dem_fluid_solve(dem_ctx* ctx, const int8_t* cell_kind, const double* p_fixed, int32_t max_iter,
+                           double rel_tol, double* p_out, double* u_out, double* gradp_out, int32_t* iters,
+                           double* rel_residual);
+
 /* Copy the state out in the caller's particle order (see dem_state): the
  * Newton-Euler state of eq 1-2 (x, v, omega), the forces and torques of the
  * latest evaluation, the alive flags, the held fluid force and wall history,

@@ -7,8 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdem.so")
-SOURCES = ["dem_sort.hip", "dem_rebuild.hip", "dem_step.hip", "dem_fluid.hip", "dem_misc.hip", "dem_mlp.hip",
-           "dem_api.hip"]
+SOURCES = ["dem_sort.hip", "dem_rebuild.hip", "dem_step.hip", "dem_fluid.hip", "dem_cfd.hip", "dem_misc.hip",
+           "dem_mlp.hip", "dem_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

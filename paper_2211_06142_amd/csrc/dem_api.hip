@@ -85,6 +85,11 @@ struct dem_ctx {
   int64_t fixed_capacity = 0;   // half-pair capacity given without DEM_FLAG_AUTO_REGROW (0: grows)
   int64_t rec_cap = 0;          // slots of the half-pair records d.rec
   double* stage_aux = nullptr;   // read-back of the held fluid force and wall history
+  // fluid solver: cell kinds, fixed pressures, work vectors (the solution kept
+  // for warm starts), output staging, pinned scalars
+  int8_t* cfd_kind = nullptr;
+  double *cfd_pfix = nullptr, *cfd_work = nullptr, *cfd_out = nullptr, *cfd_scal = nullptr;
+  int cfd_warm = 0;
   std::vector<void*> allocs;
   // kernel-class timing
   int prof = 0;
@@ -1150,6 +1155,46 @@ dem_status dem_read_pairs(dem_ctx* c, int32_t which, int64_t cap, int64_t* pair_
   return DEM_OK;
 }
 
+dem_status dem_fluid_solve(dem_ctx* c, const int8_t* cell_kind, const double* p_fixed, int32_t max_iter,
+                           double rel_tol, double* p_out, double* u_out, double* gradp_out, int32_t* iters,
+                           double* rel_residual) {
+  if (!c || !cell_kind || !p_fixed || max_iter < 0 || !(rel_tol > 0.0)) return DEM_E_INVAL;
+  const int64_t nc = c->d.ncell;
+  if (nc <= 0) return DEM_E_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  std::vector<int8_t> kd;
+  std::vector<double> pf;
+  if (fetch(kd, cell_kind, nc) != hipSuccess || fetch(pf, p_fixed, nc) != hipSuccess) return DEM_E_DEVICE;
+  for (int64_t k = 0; k < nc; ++k)
+    if (kd[k] < 0 || kd[k] > 2 || !std::isfinite(pf[k])) return DEM_E_INVAL;
+  const int64_t nw = cfd_work_doubles(nc);
+  if (!c->cfd_work) {
+    bool ok = dalloc(c, &c->cfd_kind, nc) == hipSuccess && dalloc(c, &c->cfd_pfix, nc) == hipSuccess;
+    ok &= dalloc(c, &c->cfd_work, nw) == hipSuccess && dalloc(c, &c->cfd_out, 7 * nc) == hipSuccess;
+    if (!ok) return DEM_E_NOMEM;
+    if (hipHostMalloc((void**)&c->cfd_scal, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) return DEM_E_NOMEM;
+  }
+  hipStream_t s = c->stream;
+  HIPCHK(hipMemcpyAsync(c->cfd_kind, kd.data(), nc, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->cfd_pfix, pf.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+  double* P = c->cfd_out;
+  double* U = P + nc;
+  double* GP = U + 3 * nc;
+  int it = 0;
+  double rel = 0.0;
+  dem_status st = cfd_solve(c->d, c->cfd_kind, c->cfd_pfix, c->cfd_work, nw, c->cfd_warm, max_iter, rel_tol, P, U, GP,
+                            &it, &rel, c->cfd_scal, s);
+  if (st != DEM_OK) return st;
+  c->cfd_warm = 1;
+  if (p_out) HIPCHK(hipMemcpyAsync(p_out, P, sizeof(double) * nc, hipMemcpyDefault, s));
+  if (u_out) HIPCHK(hipMemcpyAsync(u_out, U, sizeof(double) * 3 * nc, hipMemcpyDefault, s));
+  if (gradp_out) HIPCHK(hipMemcpyAsync(gradp_out, GP, sizeof(double) * 3 * nc, hipMemcpyDefault, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (iters) *iters = it;
+  if (rel_residual) *rel_residual = rel;
+  return DEM_OK;
+}
+
 dem_status dem_set_size_classes(dem_ctx* c, int32_t n_edges, const double* edges) {
   if (!c) return DEM_E_INVAL;
   if (n_edges != 0 && (!edges || n_edges < 2 || n_edges > DEM_MAX_SIZE_CLASSES + 1)) return DEM_E_INVAL;
@@ -1338,6 +1383,7 @@ void dem_destroy(dem_ctx* c) {
   if (c->stage) (void)hipFree(c->stage);
   if (c->stage_alive) (void)hipFree(c->stage_alive);
   if (c->stage_aux) (void)hipFree(c->stage_aux);
+  if (c->cfd_scal) (void)hipHostFree(c->cfd_scal);
   if (c->h_flags) (void)hipHostFree(c->h_flags);
   if (c->h_tot) (void)hipHostFree(c->h_tot);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

@@ -205,6 +205,10 @@ template <typename R> void launch_unpermute(DevState& d, double* x, double* v, d
                                             double* T, uint8_t* alive, double* fluid_force, hipStream_t s);
 template <typename R> void launch_unpermute_walls(DevState& d, double* wall_dt, hipStream_t s);
 int64_t aggregate_scratch_doubles(int nsamples);
+int64_t cfd_work_doubles(int64_t ncell);
+dem_status cfd_solve(DevState& d, const int8_t* kind, const double* pfix, double* work, int64_t nwork, int warm,
+                     int max_iter, double rel_tol, double* P, double* U, double* GP, int* iters, double* rel_res,
+                     double* h_scal, hipStream_t s);
 void launch_aggregate_impl(DevState& d, const int64_t* soff, double* produced, double* kinetic,
                            long long* contacts, long long* nalive, double* partial, int fp64, hipStream_t s);
 

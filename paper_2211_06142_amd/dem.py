@@ -25,6 +25,7 @@ DEM_FLAG_AUTO_REGROW = 1
 DEM_MAX_SIZE_CLASSES = 16
 
 DEM_PAIRS_FULL_ROWS, DEM_PAIRS_HALF = 0, 1
+DEM_CELL_OPEN, DEM_CELL_PRESSURE, DEM_CELL_SOLID = 0, 1, 2
 DEM_PROF_PROLOGUE, DEM_PROF_REBUILD, DEM_PROF_FLUID, DEM_PROF_STEP, DEM_PROF_N = 0, 1, 2, 3, 4
 PROF_NAMES = ["prologue", "rebuild", "fluid", "step"]
 
@@ -33,7 +34,7 @@ EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "de
                   "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile",
                   "dem_read_fault", "dem_mlp_create", "dem_mlp_destroy", "dem_mlp_set_params", "dem_mlp_get_params",
                   "dem_mlp_forward", "dem_mlp_grad", "dem_mlp_train_step", "dem_set_closure", "dem_read_closure", "dem_set_graphs", "dem_set_lanes",
-                  "dem_set_size_classes", "dem_read_produced_classes", "dem_mlp_train_step_noalloc", "dem_set_pair_mode"])
+                  "dem_set_size_classes", "dem_read_produced_classes", "dem_mlp_train_step_noalloc", "dem_set_pair_mode", "dem_fluid_solve"])
 MLP_NPARAMS = 8898
 MLP_NOALLOC_MAX_BATCH = 4096
 
@@ -148,6 +149,8 @@ def lib():
         L.dem_mlp_train_step_noalloc.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp]
         L.dem_set_lanes.restype = i32
         L.dem_set_lanes.argtypes = [vp, i32]
+        L.dem_fluid_solve.restype = i32
+        L.dem_fluid_solve.argtypes = [vp, vp, vp, i32, d, vp, vp, vp, vp, vp]
         L.dem_set_pair_mode.restype = i32
         L.dem_set_pair_mode.argtypes = [vp, i32]
         L.dem_set_graphs.restype = i32
@@ -618,6 +621,22 @@ class Simulation:
 
     def set_lanes(self, lanes):
         _check(lib().dem_set_lanes(self.ctx, int(lanes)), "dem_set_lanes")
+
+    def fluid_solve(self, cell_kind, p_fixed, max_iter=2000, rel_tol=1e-10):
+        """model-A pressure solve on the latest coupling evaluation; returns
+        (p, superficial u, grad p, iterations, relative residual)"""
+        kd = np.ascontiguousarray(np.asarray(cell_kind, dtype=np.int8))
+        pf = np.ascontiguousarray(np.asarray(p_fixed, dtype=np.float64))
+        nc = self.ncell
+        p = np.zeros(nc)
+        u = np.zeros((nc, 3))
+        gp = np.zeros((nc, 3))
+        it = ctypes.c_int32()
+        rr = ctypes.c_double()
+        _check(lib().dem_fluid_solve(self.ctx, kd.ctypes.data, pf.ctypes.data, int(max_iter), float(rel_tol),
+                                     p.ctypes.data, u.ctypes.data, gp.ctypes.data, ctypes.byref(it),
+                                     ctypes.byref(rr)), "dem_fluid_solve")
+        return p, u, gp, it.value, rr.value
 
     def set_pair_mode(self, mode):
         """DEM_PAIRS_FULL_ROWS or DEM_PAIRS_HALF (or "full" / "half")"""

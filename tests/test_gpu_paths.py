@@ -346,3 +346,67 @@ def test_original_jkr_box_fp64():
         o.step(10)
         gs, sc = compare_fp64(g, o, what="orig jkr step %d" % (10 * (k + 1)))
     assert sc["broken_bonds"] > 0
+
+
+# ---------------------------------------------------------------------------
+# the fluid side of the coupling (eq 6, model A, drag-dominated limit)
+# ---------------------------------------------------------------------------
+def _box_column_kinds(w, p_in=2.0e3):
+    lo, hi, nn = w["grid"]
+    nc = int(np.prod(nn))
+    iz = np.arange(nc) // (nn[0] * nn[1])
+    kind = np.where(iz == 0, dem.DEM_CELL_PRESSURE, np.where(iz == nn[2] - 1, dem.DEM_CELL_PRESSURE,
+                                                              dem.DEM_CELL_OPEN)).astype(np.int8)
+    pf = np.where(iz == 0, p_in, 0.0)
+    return kind, pf
+
+
+def test_fluid_solve_matches_oracle():
+    """the pressure solve on the GPU (conjugate gradients) against the direct
+    solve of the same discrete equations, with K from the GPU's own coupling
+    evaluation (porosity, drag source, interstitial velocity): pressure, cell
+    velocity and gradient"""
+    from oracle import cfd
+    w = synth.c0()
+    g = gpu_for(w, "fp64")
+    g.step(1)
+    eps, fd = g.fluid_out()
+    n = np.clip(1.0 - eps, w["fluid"]["n_min"], 1.0)
+    u = w["u_cell"] / n[:, None]
+    lo, hi, nn = w["grid"]
+    h = [(hi[c] - lo[c]) / nn[c] for c in range(3)]
+    K = cfd.cell_coefficient(n, fd, u, w["fluid"]["mu_f"], h)
+    kind, pf = _box_column_kinds(w)
+    p, U, GP, it, rr = g.fluid_solve(kind, pf, max_iter=5000, rel_tol=1e-13)
+    assert rr <= 1e-13 and 0 < it < 5000
+    po = cfd.solve(w["grid"], K, kind, pf)
+    np.testing.assert_allclose(p, po, rtol=0, atol=1e-10 * pf.max())
+    Uo, Go = cfd.cell_fields(w["grid"], K, kind, po)
+    np.testing.assert_allclose(U, Uo, rtol=0, atol=1e-9 * np.abs(Uo).max())
+    np.testing.assert_allclose(GP, Go, rtol=0, atol=1e-9 * np.abs(Go).max())
+    # warm start: the same system again converges at once
+    p2, _, _, it2, _ = g.fluid_solve(kind, pf, max_iter=5000, rel_tol=1e-13)
+    assert it2 <= 16 and np.allclose(p2, p, rtol=0, atol=1e-10 * pf.max())
+    with pytest.raises(dem.DemError):
+        g.fluid_solve(np.full(len(kind), 3, np.int8), pf)
+
+
+def test_two_way_coupling_loop_conserves_flux():
+    """the closed loop: coupling evaluation -> pressure solve -> fields for the
+    next evaluations; in every solve the superficial flux through each layer of
+    the column is the same (continuity), and the bed's porosity shapes it"""
+    w = synth.c0()
+    g = gpu_for(w, "mixed")
+    kind, pf = _box_column_kinds(w, p_in=500.0)
+    lo, hi, nn = w["grid"]
+    iz = np.arange(int(np.prod(nn))) // (nn[0] * nn[1])
+    for k in range(4):
+        g.step(10)
+        p, U, GP, it, rr = g.fluid_solve(kind, pf, max_iter=5000, rel_tol=1e-12)
+        assert np.all(np.isfinite(U)) and rr <= 1e-12
+        layer = np.array([U[iz == z, 2].sum() for z in range(1, nn[2] - 1)])
+        np.testing.assert_allclose(layer, layer[0], rtol=1e-8)
+        assert layer[0] > 0.0                  # upward, from the high pressure at the bottom
+        g.map_fluid(U, GP)
+    st = g.state()
+    assert np.all(np.isfinite(st["F"]))

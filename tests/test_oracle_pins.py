@@ -878,3 +878,87 @@ def test_original_jkr_pull_off_separation_and_snap_in():
         break
     else:
         raise AssertionError("no contact")
+
+
+# ---------------------------------------------------------------------------
+# section 2.2 eq 6 in the drag-dominated limit: the pressure equation of the
+# fluid side (oracle/cfd.py)
+# ---------------------------------------------------------------------------
+def test_cfd_layered_column_is_exact():
+    """A column of cells in series, K changing layer by layer at cell faces,
+    fixed pressures at both ends: the flux is the same through every face and
+    equals the pressure drop over the sum of the face resistances, and p is
+    linear inside each layer (the harmonic face mean is exact for layered
+    media)"""
+    from oracle import cfd
+    nx = 12
+    grid = ((0.0, 0.0, 0.0), (6e-3, 0.5e-3, 0.5e-3), (nx, 1, 1))
+    K = np.array([1e-9] * 4 + [3e-10] * 5 + [2e-9] * 3)
+    kind = np.zeros(nx, int)
+    kind[0] = kind[-1] = cfd.KIND_PRESSURE
+    pf = np.zeros(nx)
+    pf[0], pf[-1] = 7.0e3, 1.0e3
+    p = cfd.solve(grid, K, kind, pf)
+    h = 0.5e-3
+    R = [h / (2 * K[i] * K[i + 1] / (K[i] + K[i + 1])) for i in range(nx - 1)]
+    q = (pf[0] - pf[-1]) / sum(R)
+    expect = pf[0] - q * np.concatenate([[0.0], np.cumsum(R)])
+    np.testing.assert_allclose(p, expect, rtol=1e-12)
+    fl = cfd.face_flux(grid, K, kind, p)
+    np.testing.assert_allclose(list(fl.values()), q, rtol=1e-10)
+
+
+def test_cfd_uniform_medium_linear_pressure():
+    """uniform K with the pressure fixed on every boundary cell to a linear
+    function: the interior solution is that function (the 7-point operator
+    annihilates linear fields), the velocity is -K grad p everywhere"""
+    from oracle import cfd
+    nn = (6, 5, 4)
+    grid = ((0.0, 0.0, 0.0), (3e-3, 2e-3, 1e-3), nn)
+    cen = _centres(grid)
+    a = np.array([2e5, -1e5, 3e5])
+    plin = cen @ a + 50.0
+    ijk = np.stack([np.arange(len(cen)) % nn[0], (np.arange(len(cen)) // nn[0]) % nn[1],
+                    np.arange(len(cen)) // (nn[0] * nn[1])], 1)
+    edge = np.any((ijk == 0) | (ijk == np.array(nn) - 1), axis=1)
+    kind = np.where(edge, cfd.KIND_PRESSURE, cfd.KIND_OPEN)
+    K = np.full(len(cen), 4e-10)
+    p = cfd.solve(grid, K, kind, np.where(edge, plin, 0.0))
+    np.testing.assert_allclose(p, plin, rtol=1e-12)
+    U, G = cfd.cell_fields(grid, K, kind, p)
+    inner = ~edge
+    np.testing.assert_allclose(G[inner], np.tile(a, (inner.sum(), 1)), rtol=1e-9)
+    np.testing.assert_allclose(U[inner], -4e-10 * np.tile(a, (inner.sum(), 1)), rtol=1e-9)
+
+
+def test_cfd_radial_inflow_conserves_and_approaches_log_profile():
+    """the cylinder's annulus with uniform K between a fixed-pressure outer ring
+    and a fixed-pressure cavity: the flux leaving through the cavity equals the
+    flux entering at the ring (mass conservation, to round-off), the pressure
+    stays between the two fixed values (maximum principle), and approaches the
+    radial solution p_in + dp ln(rho/r_in)/ln(R/r_in) as the grid is refined"""
+    from oracle import cfd
+    errs = []
+    for m in (24, 48):
+        grid = ((-12e-3, -12e-3, 0.0), (12e-3, 12e-3, 1e-3), (m, m, 1))
+        cen = _centres(grid)
+        rho = np.hypot(cen[:, 0], cen[:, 1])
+        kind = np.where(rho < 2e-3, cfd.KIND_PRESSURE, np.where(rho > 11e-3, cfd.KIND_PRESSURE, cfd.KIND_OPEN))
+        pf = np.where(rho > 11e-3, 1e4, 0.0)
+        K = np.full(len(cen), 1e-9)
+        p = cfd.solve(grid, K, kind, pf)
+        assert p.min() >= -1e-9 and p.max() <= 1e4 * (1 + 1e-12)
+        fl = cfd.face_flux(grid, K, kind, p)
+        into_cav = sum(f if kind[a] != cfd.KIND_PRESSURE or rho[a] > 11e-3 else -f
+                       for (a, b), f in fl.items() if (kind[a] == cfd.KIND_PRESSURE) != (kind[b] == cfd.KIND_PRESSURE)
+                       and min(rho[a], rho[b]) < 2e-3)
+        from_ring = sum(f if rho[a] > 11e-3 else -f for (a, b), f in fl.items()
+                        if (kind[a] == cfd.KIND_PRESSURE) != (kind[b] == cfd.KIND_PRESSURE) and max(rho[a], rho[b]) > 11e-3)
+        assert into_cav == pytest.approx(from_ring, rel=1e-9)
+        band = (rho > 4e-3) & (rho < 9e-3)
+        r_in = 2e-3 + 0.5 * 24e-3 / m        # the fixed cells reach half a cell beyond the radii
+        r_out = 11e-3 - 0.5 * 24e-3 / m
+        exact = 1e4 * np.log(rho[band] / r_in) / np.log(r_out / r_in)
+        errs.append(np.abs(p[band] - exact).max() / 1e4)
+    # staircase circles: the error halves with the cell size (first order)
+    assert errs[1] < 0.6 * errs[0] and errs[1] < 0.08
