@@ -29,7 +29,8 @@ SKIN_FACTOR = {"c1": 1.2, "c0": 0.4, "c3": 0.4}
 LANES = 4           # lanes per particle of the step kernel (the library default)
 
 
-KERNEL_SOURCES = {"step": ["dem_step.hip", "dem_device.h", "dem_internal.h"]}
+KERNEL_SOURCES = {"step": ["dem_step.hip", "dem_device.h", "dem_internal.h"],
+                  "fluid": ["dem_fluid.hip", "dem_device.h", "dem_internal.h"]}
 
 
 def source_hash(files=None):
@@ -194,6 +195,28 @@ def learned_cg_block(horizon, ks=(2, 3), c4=False):
     return out
 
 
+def calibrate_pmc(gib=2):
+    """Known traffic for the HBM counters: three device copies of a buffer of
+    `gib` GiB (far beyond the 256 MB Infinity Cache, so every byte crosses HBM:
+    the buffer size read and written once each) and three read-only passes
+    (a sum: the buffer read once).  Run under rocprofv3 --pmc FETCH_SIZE, then
+    WRITE_SIZE; the counters of these kernels divided by the known bytes give the
+    factors that turn the DEM kernels' counters into bytes."""
+    import torch
+    n = gib * 1024 ** 3 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    acc = 0.0
+    for _ in range(3):
+        acc += float(src.sum())
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "pmc", "bytes": 4 * n, "copies": 3, "reads": 3, "check": acc}), flush=True)
+
+
 def build_sim(ws, skin_factor, lanes, graphs, pair_mode=None):
     from paper_2211_06142_amd import dem
     rmin = min(float(np.min(w["r"])) for w in ws)
@@ -235,7 +258,12 @@ def main():
     ap.add_argument("--cg-horizon", type=int, default=20000, help="steps of the fine/coarse comparison")
     ap.add_argument("--cg-c4", action="store_true", help="the comparison on c4 (2 000 000 fine grains against "
                     "k = 3 parcels) instead of c1 against c2 (needs the c4 packings, about an hour to generate)")
+    ap.add_argument("--calibrate-pmc", action="store_true", help="only run the counter calibration kernels "
+                    "(a 2 GiB copy and read, run under rocprofv3 --pmc)")
     args = ap.parse_args()
+    if args.calibrate_pmc:
+        calibrate_pmc()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: measures one GPU only; sharding the DEM step over several GPUs is designed but not "
               "implemented", file=sys.stderr)
@@ -308,7 +336,8 @@ def main():
         kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
                        "avg_us": round(1e3 * v[0] / max(v[1], 1), 3),
                        "alg_GBs": round(alg_bytes(k, n_alive, inf["n_pairs"], inf["ncell"], rsz) /
-                                        (v[0] * 1e-3 / max(v[1], 1)) / 1e9, 1) if v[1] else None}
+                                        (v[0] * 1e-3 / max(v[1], 1)) / 1e9, 1) if v[1] else None,
+                       "traffic": load_traffic(k, args.workload)}
                    for k, v in prof.items()}
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(dom, args.workload),
