@@ -302,10 +302,12 @@ dem_status dem_request_rebuild(dem_ctx* ctx);
  * runtime refuses it. */
 dem_status dem_set_graphs(dem_ctx* ctx, int32_t enable);
 
-/* Lanes of the step kernel that share one particle's neighbour row: 1, 2, 4
- * (default), 8 or 16; anything else is DEM_E_INVAL.  A tuning knob: forces are
- * summed in a fixed tree within the group, so results differ between settings
- * by rounding only, and are reproducible for each. */
+/* Lanes of the step kernel that share one particle's neighbour row: 1, 2, 4,
+ * 8 or 16; anything else is DEM_E_INVAL.  Until it is called, the pair mode
+ * picks it: 2 for DEM_PAIRS_HALF (the row gather), 4 for DEM_PAIRS_FULL_ROWS (the
+ * row evaluation).  A tuning knob: forces are summed in a fixed tree within the
+ * group, so results differ between settings by rounding only, and are
+ * reproducible for each. */
 dem_status dem_set_lanes(dem_ctx* ctx, int32_t lanes);
 
 /* How the step evaluates the contact law of a pair (a tuning knob; results
@@ -313,10 +315,11 @@ dem_status dem_set_lanes(dem_ctx* ctx, int32_t lanes);
  * full neighbour row and evaluates every contact itself, in the pair's
  * canonical orientation, so each pair is evaluated twice and no force record
  * is written (one launch per step).  DEM_PAIRS_HALF: a first launch evaluates
- * every half pair once and writes its force record (force, n x F_t and rolling
- * torque on the owner); a second adds the records of each particle's row in
- * the same order (two launches per step; the default, faster at 200 000
- * spheres).  Anything else is DEM_E_INVAL. */
+ * every half pair once and writes the force record of each pair in contact
+ * (force, n x F_t and rolling torque on the owner); a second adds the records
+ * of each particle's row in the same order (two launches per step; the
+ * default, faster at 200 000 spheres).  With the same lanes the two modes give
+ * bit-identical results.  Anything else is DEM_E_INVAL. */
 enum { DEM_PAIRS_FULL_ROWS = 0, DEM_PAIRS_HALF = 1 };
 dem_status dem_set_pair_mode(dem_ctx* ctx, int32_t mode);
 

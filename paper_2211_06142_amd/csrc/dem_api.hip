@@ -84,6 +84,7 @@ struct dem_ctx {
   double* agg_buf = nullptr;  // aggregate outputs and slice partials
   int64_t fixed_capacity = 0;   // half-pair capacity given without DEM_FLAG_AUTO_REGROW (0: grows)
   int64_t rec_cap = 0;          // slots of the half-pair records d.rec
+  int lanes_set = 0;             // lanes chosen by the caller (else the pair mode's default)
   double* stage_aux = nullptr;   // read-back of the held fluid force and wall history
   // fluid solver: cell kinds, fixed pressures, work vectors (the solution kept
   // for warm starts), output staging, pinned scalars
@@ -406,9 +407,10 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   ws.n = tot[2];
   c->last_overflow_rows = tot[3];
   if (ns.slot_cap > c->rec_cap) {   // half-pair records follow the largest slot capacity
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 2; ++q) {
       dfree(c, d.rec[q]);
-      if (dalloc_bytes(c, &d.rec[q], ns.slot_cap * 4 * (int64_t)c->rsz) != hipSuccess) return DEM_E_NOMEM;
+      if (dalloc_bytes(c, &d.rec[q], ns.slot_cap * (q == 0 ? 6 : 4) * (int64_t)c->rsz) != hipSuccess)
+        return DEM_E_NOMEM;
     }
     c->rec_cap = ns.slot_cap;
   }
@@ -417,7 +419,7 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
   launch_wall_fill(d, s);
   // 5. carry history
   launch_hist_carry<R>(d, s, first ? 0 : 1);
-  if (mark_bonds) launch_mark_bonds(d, s);
+  if (mark_bonds) launch_mark_bonds<R>(d, s);
   launch_set_xref(d, s);
   c->rebuilds++;
   return DEM_OK;
@@ -788,7 +790,9 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.totals, 4) == hipSuccess;
   ok &= dalloc_bytes(c, (void**)&c->d_dev, sizeof(DevState)) == hipSuccess;
   d.self = c->d_dev;
-  d.group = 4;   // tuned on the 200 000-sphere cylinder (4 beat 8 and 16 at every skin)
+  // tuned on the 200 000-sphere cylinder: the gather of the half-pair mode (the
+  // default) is fastest with 2 lanes per particle, full rows with 4
+  d.group = 2;
   d.pair_mode = DEM_PAIRS_HALF;   // 48.6 against 55.9 us per step at 200 000 spheres
   int64_t scan_n = std::max<int64_t>(nbk, n + 1);
   d.scan_tmp_n = scan_n / 256 + 4096;
@@ -905,6 +909,8 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
       if (params[0].normal_model != DEM_NORMAL_JKR_MOD && params[0].normal_model != DEM_NORMAL_JKR_ORIG) pfl[q] = 0;
       double t3[3] = {0, 0, 0};
       if (!hdt.empty()) for (int e = 0; e < 3; ++e) t3[e] = sg * hdt[3 * k + e];
+      // a clear flag stands for a zero elongation: a given elongation sets the touching bit
+      if (t3[0] != 0.0 || t3[1] != 0.0 || t3[2] != 0.0) pfl[q] |= 2;
       if (c->fp64) ((double4*)ph.data())[q] = make_double4(t3[0], t3[1], t3[2], 0.0);
       else ((float4*)ph.data())[q] = make_float4((float)t3[0], (float)t3[1], (float)t3[2], 0.f);
     }
@@ -1138,8 +1144,9 @@ dem_status dem_read_pairs(dem_ctx* c, int32_t which, int64_t cap, int64_t* pair_
     if (a > b) { std::swap(a, b); sg = -1.0; }
     oi.push_back(a);
     oi.push_back(b);
-    double t3[3];
-    if (c->fp64) { double4 q = ((double4*)h.data())[p]; t3[0] = q.x; t3[1] = q.y; t3[2] = q.z; }
+    double t3[3] = {0, 0, 0};   // a clear flag stands for a zero elongation
+    if (!fl[p]) {
+    } else if (c->fp64) { double4 q = ((double4*)h.data())[p]; t3[0] = q.x; t3[1] = q.y; t3[2] = q.z; }
     else { float4 q = ((float4*)h.data())[p]; t3[0] = q.x; t3[1] = q.y; t3[2] = q.z; }
     for (int e = 0; e < 3; ++e) odt.push_back(sg * t3[e]);
     ob.push_back(fl[p] & 1);
@@ -1344,6 +1351,7 @@ dem_status dem_set_lanes(dem_ctx* c, int32_t lanes) {
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   c->d.group = lanes;
+  c->lanes_set = 1;
   return DEM_OK;
 }
 
@@ -1353,6 +1361,7 @@ dem_status dem_set_pair_mode(dem_ctx* c, int32_t mode) {
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   c->d.pair_mode = mode;
+  if (!c->lanes_set) c->d.group = mode == DEM_PAIRS_HALF ? 2 : 4;
   return DEM_OK;
 }
 

@@ -54,6 +54,26 @@ __device__ inline float4 gld(gptr<const float4> p) {
 __device__ inline void gst(gptr<double4> p, const double4& v) { *(gptr<gd4>)p = gd4{v.x, v.y, v.z, v.w}; }
 __device__ inline void gst(gptr<float4> p, const float4& v) { *(gptr<gf4>)p = gf4{v.x, v.y, v.z, v.w}; }
 
+// Pair record of the half-pair mode: the force on the owner and n x F_t, six R
+// packed in three 2-vectors (24 B per slot in mixed precision).
+template <typename R> struct V2T;
+template <> struct V2T<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct V2T<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <typename R> __device__ inline void rec_put(void* base, int64_t p, const R (&f)[3], const R (&t)[3]) {
+  using V = typename V2T<R>::type;
+  const gptr<V> q = (gptr<V>)base + 3 * p;
+  q[0] = V{f[0], f[1]};
+  q[1] = V{f[2], t[0]};
+  q[2] = V{t[1], t[2]};
+}
+template <typename R> __device__ inline void rec_get(const void* base, int64_t p, R (&f)[3], R (&t)[3]) {
+  using V = typename V2T<R>::type;
+  const gptr<const V> q = (gptr<const V>)base + 3 * p;
+  const V a = q[0], b = q[1], c = q[2];
+  f[0] = a.x; f[1] = a.y; f[2] = b.x;
+  t[0] = b.y; t[1] = c.x; t[2] = c.y;
+}
+
 // The per-sample constants do not change while a kernel runs.  Reading them
 // through the constant address space lets the compiler use scalar loads for a
 // wave-uniform sample and hoist the loads out of loops that store.

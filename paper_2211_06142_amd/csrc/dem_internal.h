@@ -17,6 +17,8 @@
 //   half-pair slots: hdt[b][p] R4 tangential elongation (owner -> partner),
 //   pfl[b][p] uint8 bit0 bonded, bit1 touching; double-buffered like the
 //   particles because both partners read slot p while its owner writes it.
+//   A clear flag stands for a zero elongation: hdt[b][p] is read and written
+//   only where the flag is set (a pair out of contact costs one byte).
 // Wall entries: CSR by particle, private to the particle (single buffer).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -86,8 +88,9 @@ struct DevState {
   int rolling;                     // any sample with mu_roll > 0
   int group;                       // lanes per particle of the step kernel (1, 2, 4, 8, 16)
   int pair_mode;                   // DEM_PAIRS_FULL_ROWS or DEM_PAIRS_HALF
-  void* rec[3];                    // half-pair mode: per slot R4 force on the owner, n x F_t,
-                                   // rolling torque on the owner (written and read in one step)
+  void* rec[2];                    // half-pair mode, per slot (written and read in one step):
+                                   // [0] 6 R: force on the owner, n x F_t; [1] R4 rolling torque
+                                   // on the owner; written only for slots whose new flag is set
   int cur;                         // buffer holding the current particle state and history
   // double-buffered particle state
   double4 *xr[2], *vel[2];
@@ -188,7 +191,7 @@ void launch_nbr_fill(DevState& d, int novf, hipStream_t s);
 void launch_wall_count(DevState& d, hipStream_t s);
 void launch_wall_fill(DevState& d, hipStream_t s);
 template <typename R> void launch_hist_carry(DevState& d, hipStream_t s, int check_lost);
-void launch_mark_bonds(DevState& d, hipStream_t s);
+template <typename R> void launch_mark_bonds(DevState& d, hipStream_t s);
 void launch_set_xref(DevState& d, hipStream_t s);
 
 // stepping

@@ -418,16 +418,16 @@ void launch_wall_fill(DevState& d, hipStream_t s) {
 // history carry: every half pair and wall entry of the previous list keeps its
 // elongation and flags in the new list (found through the permutation)
 // ---------------------------------------------------------------------------
+// (a clear flag stands for a zero elongation, so the elongations are not cleared)
 template <typename R>
 __global__ void k_zero_slots(DevState d) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.nslots) return;
-  ((R4<R>*)d.hdt[d.cur])[p] = mk4<R>(0, 0, 0, 0);
   d.pfl[d.cur][p] = 0;
 }
 
 // one thread per half pair of the previous list; pairs with no state (not
-// touching, not bonded, zero elongation) have nothing to carry.  A bonded pair
+// touching, not bonded: the flag clear, the elongation zero) have nothing to carry.  A bonded pair
 // whose partners are both alive must be in the new list: the candidate margin
 // covers the largest pull-off separation, so a miss means the margin failed.
 template <typename R>
@@ -435,8 +435,8 @@ __global__ void k_carry_pairs(DevState d, int check_lost) {
   int64_t so = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (so >= d.nslots_o) return;
   const uint8_t fl = d.pfl_o[so];
+  if (fl == 0) return;
   R4<R> h = ((const R4<R>*)d.hdt_o)[so];
-  if (fl == 0 && h.x == (R)0 && h.y == (R)0 && h.z == (R)0) return;
   const int32_t A = d.inv_order[d.sown_o[so]], B = d.inv_order[d.spart_o[so]];
   const uint8_t* al = d.alive[d.cur];
   if (!al[A] || !al[B]) return;
@@ -484,7 +484,9 @@ template <typename R> void launch_hist_carry(DevState& d, hipStream_t s, int che
 template void launch_hist_carry<double>(DevState&, hipStream_t, int);
 template void launch_hist_carry<float>(DevState&, hipStream_t, int);
 
-// bond every touching pair (initial state of the modified JKR model)
+// bond every touching pair (initial state of the JKR models); a pair that had
+// no flag gets its zero elongation written (a clear flag stood for it)
+template <typename R>
 __global__ void k_mark_bonds(DevState d) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.nslots) return;
@@ -495,10 +497,14 @@ __global__ void k_mark_bonds(DevState d) {
   double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
   double d2 = (dx * dx + dy * dy) + dz * dz;
   double cs = a.w + b.w;
-  if (d2 < cs * cs) d.pfl[d.cur][p] = 1;
+  if (!(d2 < cs * cs)) return;
+  if (d.pfl[d.cur][p] == 0) ((R4<R>*)d.hdt[d.cur])[p] = mk4<R>(0, 0, 0, 0);
+  d.pfl[d.cur][p] = 1;
 }
-void launch_mark_bonds(DevState& d, hipStream_t s) {
-  if (d.nslots > 0) hipLaunchKernelGGL(k_mark_bonds, dim3(nblk(d.nslots)), dim3(kBlock), 0, s, d);
+template <typename R> void launch_mark_bonds(DevState& d, hipStream_t s) {
+  if (d.nslots > 0) hipLaunchKernelGGL(k_mark_bonds<R>, dim3(nblk(d.nslots)), dim3(kBlock), 0, s, d);
 }
+template void launch_mark_bonds<double>(DevState&, hipStream_t);
+template void launch_mark_bonds<float>(DevState&, hipStream_t);
 
 }  // namespace dem

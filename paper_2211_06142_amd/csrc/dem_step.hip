@@ -30,9 +30,10 @@ __device__ inline void count_removal(const DevState& d, const SampleConst& c, in
   }
 }
 
+// (xref: the particle's position at the last rebuild)
 template <typename R>
 __device__ inline void finish_drift(const DevState& d, const SampleConst& c, int s, int64_t i, int out,
-                                    int64_t next_step, double4 p, double4 v, R4<R> w) {
+                                    int64_t next_step, double4 p, double4 v, R4<R> w, const double4& xref) {
   const double dt = d.dt;
   double sx = dt * v.x, sy = dt * v.y, sz = dt * v.z;
   p.x += sx; p.y += sy; p.z += sz;
@@ -57,7 +58,7 @@ __device__ inline void finish_drift(const DevState& d, const SampleConst& c, int
   }
   G(d.alive[out])[i] = alive;
   if (alive) {
-    double4 q = gld(G((const double4*)d.xref) + i);
+    const double4& q = xref;
     double ux = p.x - q.x, uy = p.y - q.y, uz = p.z - q.z;
     if ((ux * ux + uy * uy) + uz * uz > hs * hs) {
       atomicOr(d.abort, 1);
@@ -93,7 +94,7 @@ __global__ void k_prologue(DevState d, StepArgs a) {
   w.x += hdtR * T.x * w.w;
   w.y += hdtR * T.y * w.w;
   w.z += hdtR * T.z * w.w;
-  finish_drift<R>(d, c, s, i, out, a.step, p, v, w);
+  finish_drift<R>(d, c, s, i, out, a.step, p, v, w, d.xref[i]);
 }
 
 template <typename R> void launch_prologue(DevState& d, StepArgs a, hipStream_t s) {
@@ -145,6 +146,24 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// What the end of a particle's step reads besides its own state: its wall
+// entries and the held fluid force, loaded at the start of the step together
+// with the particle's own state (their loads do not wait for the row walk).
+template <typename R> struct FinishIn {
+  int32_t w0, w1;   // wall entries [w0, w1)
+  R4<R> fd;         // held fluid force (zero without fluid)
+  double4 xref;     // position at the last rebuild
+};
+template <typename R>
+__device__ __forceinline__ FinishIn<R> finish_in(const DevState& d, const SampleConst& c, int64_t i) {
+  FinishIn<R> q;
+  q.w0 = G((const int32_t*)d.wrow)[i];
+  q.w1 = G((const int32_t*)d.wrow)[i + 1];
+  q.fd = c.fluid_on ? gld(G((const R4<R>*)d.fdr) + i) : mk4<R>(0, 0, 0, 0);
+  q.xref = gld(G((const double4*)d.xref) + i);
+  return q;
+}
+
 // Walls, the group's fixed-order sum, gravity, the held fluid force, the
 // second half kick and - unless the step ends the call - the next step's
 // first half kick, drift and outlet (every lane of the group calls it with its
@@ -152,15 +171,15 @@ __device__ inline void wave_lds_sync() {
 template <typename R, int kGroup>
 __device__ __forceinline__ void particle_finish(const DevState& d, const StepArgs& a, const SampleConst& c,
                                                 const LawK<R>& lk, int64_t i, int sub, int s, const double4& pi,
-                                                double4 v, R4<R> w, R F[3], R T[3]) {
+                                                double4 v, R4<R> w, R F[3], R T[3], const FinishIn<R>& fin) {
   const int out = a.out;
   const R r = (R)pi.w;
   // walls: Hertz with R* = r and m* = m (rigid, static); entries private to i
   const double m = c.rho * (4.0 / 3.0) * M_PI * pi.w * pi.w * pi.w;
   const auto WDT = G((R4<R>*)d.wdt);
   const auto WFL = G((uint8_t*)d.wfl);
-  const int32_t w1 = G((const int32_t*)d.wrow)[i + 1];
-  for (int32_t e = G((const int32_t*)d.wrow)[i] + sub; e < w1; e += kGroup) {
+  const int32_t w1 = fin.w1;
+  for (int32_t e = fin.w0 + sub; e < w1; e += kGroup) {
     R4<R> h4 = gld((gptr<const R4<R>>)(WDT + e));
     double sd, nw[3];
     const Wall& wl = c.walls[G((const int32_t*)d.wid)[e]];
@@ -195,8 +214,7 @@ __device__ __forceinline__ void particle_finish(const DevState& d, const StepArg
   F[1] += (R)(m * c.g[1]);
   F[2] += (R)(m * c.g[2]);
   if (c.fluid_on) {
-    const R4<R> fd = gld(G((const R4<R>*)d.fdr) + i);
-    F[0] += fd.x; F[1] += fd.y; F[2] += fd.z;
+    F[0] += fin.fd.x; F[1] += fin.fd.y; F[2] += fin.fd.z;
   }
   if (!isfinite(F[0] + F[1] + F[2] + T[0] + T[1] + T[2])) {
     atomicOr(d.status, (int)kStNonFinite);
@@ -227,7 +245,7 @@ __device__ __forceinline__ void particle_finish(const DevState& d, const StepArg
   w.x += hdtR * T[0] * w.w;
   w.y += hdtR * T[1] * w.w;
   w.z += hdtR * T[2] * w.w;
-  finish_drift<R>(d, c, s, i, out, a.step + 1, pi, v, w);
+  finish_drift<R>(d, c, s, i, out, a.step + 1, pi, v, w, fin.xref);
 }
 
 // Everything of one live particle; `s` is its sample, uniform over the active
@@ -299,10 +317,7 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
         const double d2 = (dx * dx + dy * dy) + dz * dz;
         const double cs = pi.w + pj.w;
         act = (alj != 0) & ((d2 < cs * cs) | ((fp & 1) != 0));
-        if (!act && j > (int32_t)i) {
-          gst(Hout + p, mk4<R>(0, 0, 0, 0));
-          Fout[p] = 0;
-        }
+        if (!act && j > (int32_t)i) Fout[p] = 0;   // a clear flag: zero history, not written
       }
       const uint64_t b = __ballot(act);
       const int n = __popcll(b);
@@ -330,8 +345,8 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
       const double4 pa = Q.sx[la], pj = gld(X + j);
       const double4 va = Q.sv[la], vj = gld(V + j);
       const R4<R> wa = Q.sw[la], wj = gld(W + j);
-      const R4<R> hp = gld(Hin + p);
       const uint8_t fp = Fin[p];
+      const R4<R> hp = fp ? gld(Hin + p) : mk4<R>(0, 0, 0, 0);
       double gam = c.gamma;
       if (d.ccoh) gam = c.gamma * sqrt(CC[ia] * CC[j]);
       const bool own = j > (int32_t)ia;
@@ -341,7 +356,7 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
       const R4<R> WA = own ? wa : wj, WB = own ? wj : wa;
       pair_eval<R>(lk, c.Es, d.dt, rolling, PA, PB, VA, VB, WA, WB, gam, hp, fp, po);
       if (own) {
-        gst(Hout + p, po.h);
+        if (po.fl) gst(Hout + p, po.h);
         Fout[p] = po.fl;
         if (po.broke) atomicAdd(&d.broken[s], 1ull);
       }
@@ -376,7 +391,7 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
   const double4 pi = Q.sx[li];
   double4 v = Q.sv[li];
   R4<R> w = Q.sw[li];
-  particle_finish<R, kGroup>(d, a, c, lk, i, sub, s, pi, v, w, F, T);
+  particle_finish<R, kGroup>(d, a, c, lk, i, sub, s, pi, v, w, F, T, finish_in<R>(d, c, i));
 }
 
 // A launch exits at entry when a rebuild is due at or before its step: the
@@ -425,139 +440,206 @@ __global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, S
 // ---------------------------------------------------------------------------
 // Half-pair mode: every contact law is evaluated once.  k_pairs takes one lane
 // per half-pair slot (owner = lower sorted index, so the pair is in its
-// canonical orientation), writes the new history and the pair's record: the
-// force on the owner, n x F_t and the rolling torque on the owner.  k_gather
-// then walks each particle's full row in the lane layout of k_step and adds the
-// records of its slots with the owner's sign (force and rolling torque) and its
-// own radius (n x F_t), the very terms k_step adds, in the same order, so the two
-// modes agree bit for bit; then it finishes the particle (walls, gravity, fluid
-// force, kicks, drift).  Measured at 200 000 spheres the records (32 B per
-// slot, read back through the row) cost less than the second evaluation.
+// canonical orientation), writes the new flag and, for a pair in contact, the
+// new history and the pair's record: the force on the owner and n x F_t (and the
+// rolling torque on the owner).  A pair out of contact writes its flag byte
+// alone.  k_gather then walks each particle's full row in the lane layout of
+// k_step and adds the records of the slots whose new flag is set, with the
+// owner's sign (force and rolling torque) and its own radius (n x F_t): the very
+// terms k_step adds, in the same order (the pairs out of contact add +0 there,
+// which leaves a sum that starts at +0 unchanged), so the two modes agree bit
+// for bit; then it finishes the particle (walls, gravity, fluid force, kicks,
+// drift).  Measured at 200 000 spheres the records (24 B per slot in contact,
+// read back through the row) cost less than the second evaluation.
 // ---------------------------------------------------------------------------
+// Both kernels are latency-bound (a few loads per lane, each depending on the
+// one before), so every load whose address is known is issued in the same
+// round trip as the others, ahead of the test that may make it unnecessary: the
+// abort step with the slot (or the particle's own state), then everything the
+// pair (or the row) needs.  An empty asm that takes the values keeps the
+// compiler from sinking the loads below the early exits.
+template <typename R> struct PairIn {
+  double4 A, B, VA, VB;
+  R4<R> WA, WB, h;
+  uint8_t fl, alo, alj;
+  double gam;
+};
+
 template <typename R>
-__device__ __forceinline__ void half_pair(const DevState& d, const StepArgs& a, int64_t p, int32_t o, int32_t j,
+__device__ __forceinline__ void half_pair(const DevState& d, const StepArgs& a, int64_t p, const PairIn<R>& q,
                                           int s) {
-  const int in = a.in, out = a.out;
+  const int out = a.out;
   const SampleConst& c = sample_const(d.sc, s);
-  const auto X = G((const double4*)d.xr[in]);
-  const auto AL = G((const uint8_t*)d.alive[in]);
   const auto Hout = G((R4<R>*)d.hdt[out]);
   const auto Fout = G((uint8_t*)d.pfl[out]);
-  const auto RF = G((R4<R>*)d.rec[0]);
-  const auto RT = G((R4<R>*)d.rec[1]);
   const bool rolling = d.rolling != 0;
-  const double4 A = gld(X + o), B = gld(X + j);
-  const uint8_t fl = G((const uint8_t*)d.pfl[in])[p];
-  const uint8_t alo = AL[o], alj = AL[j];
-  const double dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
+  const double dx = q.B.x - q.A.x, dy = q.B.y - q.A.y, dz = q.B.z - q.A.z;
   const double d2 = (dx * dx + dy * dy) + dz * dz;
-  const double cs = A.w + B.w;
-  const R4<R> zero = mk4<R>(0, 0, 0, 0);
-  if (!(alo && alj && ((d2 < cs * cs) || (fl & 1)))) {
+  const double cs = q.A.w + q.B.w;
+  if (!(q.alo && q.alj && ((d2 < cs * cs) || (q.fl & 1)))) {
     // neither touching nor bonded, or a partner gone: no force, no history
-    gst(Hout + p, zero);
     Fout[p] = 0;
-    gst(RF + p, zero);
-    gst(RT + p, zero);
-    if (rolling) gst(G((R4<R>*)d.rec[2]) + p, zero);
     return;
   }
   const LawK<R> lk = law_k<R>(c);
-  const double4 VA = gld(G((const double4*)d.vel[in]) + o), VB = gld(G((const double4*)d.vel[in]) + j);
-  const auto W = G((const R4<R>*)d.omg[in]);
-  const R4<R> WA = gld(W + o), WB = gld(W + j);
-  const R4<R> hp = gld(G((const R4<R>*)d.hdt[in]) + p);
-  double gam = c.gamma;
-  if (d.ccoh) gam = c.gamma * sqrt(G((const double*)d.ccoh)[o] * G((const double*)d.ccoh)[j]);
+  const double gam = d.ccoh ? c.gamma * q.gam : c.gamma;
   PairOut<R> po;
-  pair_eval<R>(lk, c.Es, d.dt, rolling, A, B, VA, VB, WA, WB, gam, hp, fl, po);
-  gst(Hout + p, po.h);
+  pair_eval<R>(lk, c.Es, d.dt, rolling, q.A, q.B, q.VA, q.VB, q.WA, q.WB, gam, q.h, q.fl, po);
   Fout[p] = po.fl;
   if (po.broke) atomicAdd(&d.broken[s], 1ull);
-  // a broken bond contributes +0 (as in k_step)
-  gst(RF + p, po.active ? mk4<R>(po.o.F[0], po.o.F[1], po.o.F[2], (R)0) : zero);
-  gst(RT + p, po.active ? mk4<R>(po.o.c[0], po.o.c[1], po.o.c[2], (R)0) : zero);
-  if (rolling) gst(G((R4<R>*)d.rec[2]) + p, po.active ? mk4<R>(po.o.Tr[0], po.o.Tr[1], po.o.Tr[2], (R)0) : zero);
+  // a bond that broke apart leaves the pair out of contact (clear flag, no record)
+  if (!po.fl) return;
+  gst(Hout + p, po.h);
+  rec_put<R>(d.rec[0], p, po.o.F, po.o.c);
+  if (rolling) gst(G((R4<R>*)d.rec[1]) + p, mk4<R>(po.o.Tr[0], po.o.Tr[1], po.o.Tr[2], (R)0));
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_pairs(const DevState* __restrict__ dp, StepArgs a) {
   const DevState& d = *dp;
-  if (*d.abort_step <= a.step) return;
   const int64_t p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (p >= d.nslots) return;
-  const int32_t o = G((const int32_t*)d.sown)[p], j = G((const int32_t*)d.spart)[p];
-  // serve the wave's samples in turn (constants in scalar registers; see k_step)
+  const bool has = p < d.nslots;
+  const int64_t ps = has ? p : 0;   // the launch covers at least one slot
+  const int in = a.in;
+  // round trip 1: the abort step and the slot
+  const int32_t abort_at = *G((const int32_t*)d.abort_step);
+  const int32_t o = G((const int32_t*)d.sown)[ps], j = G((const int32_t*)d.spart)[ps];
+  PairIn<R> q;
+  q.fl = G((const uint8_t*)d.pfl[in])[ps];
+  asm volatile("" ::"v"(o), "v"(j), "v"((int)q.fl), "s"(abort_at));
+  if (abort_at <= a.step || !has) return;
+  // round trip 2: both particles, the history, the sample
+  const auto X = G((const double4*)d.xr[in]);
+  const auto V = G((const double4*)d.vel[in]);
+  const auto W = G((const R4<R>*)d.omg[in]);
+  const auto AL = G((const uint8_t*)d.alive[in]);
   const int sl = G((const int32_t*)d.sample)[o];
+  q.A = gld(X + o);
+  q.B = gld(X + j);
+  q.VA = gld(V + o);
+  q.VB = gld(V + j);
+  q.WA = gld(W + o);
+  q.WB = gld(W + j);
+  q.alo = AL[o];
+  q.alj = AL[j];
+  q.h = q.fl ? gld(G((const R4<R>*)d.hdt[in]) + p) : mk4<R>(0, 0, 0, 0);
+  q.gam = d.ccoh ? sqrt(G((const double*)d.ccoh)[o] * G((const double*)d.ccoh)[j]) : 1.0;
+  // serve the wave's samples in turn (constants in scalar registers; see k_step)
   uint64_t todo = __ballot(1);
   while (todo) {
     const int first = __builtin_ctzll(todo);
     const bool mine = sl == __builtin_amdgcn_readlane(sl, first);
-    if (mine) half_pair<R>(d, a, p, o, j, opaque_readlane(sl, first));
+    if (mine) half_pair<R>(d, a, p, q, opaque_readlane(sl, first));
     todo &= ~__ballot(mine);
   }
 }
 
+// a particle's own inputs of the gather, loaded in one round trip
+template <typename R> struct OwnIn {
+  double4 x, v;
+  R4<R> w;
+  int32_t e0, e1, h0, h1;
+  FinishIn<R> fin;
+};
+
 template <typename R, int kGroup>
-__device__ __forceinline__ void particle_gather(const DevState& d, const StepArgs& a, int64_t i, int sub, int s) {
-  const int in = a.in;
+__device__ __forceinline__ void particle_gather(const DevState& d, const StepArgs& a, int64_t i, int sub, int s,
+                                                const OwnIn<R>& own_in) {
   const SampleConst& c = sample_const(d.sc, s);
   const LawK<R> lk = law_k<R>(c);
-  const double4 pi = gld(G((const double4*)d.xr[in]) + i);
-  const double4 v = gld(G((const double4*)d.vel[in]) + i);
-  const R4<R> w = gld(G((const R4<R>*)d.omg[in]) + i);
+  const double4 pi = own_in.x;
   const auto NSL = G((const int32_t*)d.nslot);
-  const auto RF = G((const R4<R>*)d.rec[0]);
-  const auto RT = G((const R4<R>*)d.rec[1]);
-  const auto RR = G((const R4<R>*)d.rec[2]);
+  const auto FL = G((const uint8_t*)d.pfl[a.out]);
+  const auto RR = G((const R4<R>*)d.rec[1]);
   const bool rolling = d.rolling != 0;
   const R ra = (R)pi.w;
   // the row's owned entries (partners above i) are its tail, their slots consecutive
-  const int32_t e1 = G((const int32_t*)d.nrow)[i + 1];
-  const int32_t h0 = G((const int32_t*)d.hrow)[i], h1 = G((const int32_t*)d.hrow)[i + 1];
-  const int32_t eo = e1 - (h1 - h0);
+  const int32_t e1 = own_in.e1, h0 = own_in.h0;
+  const int32_t eo = e1 - (own_in.h1 - h0);
   R F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  for (int32_t e = G((const int32_t*)d.nrow)[i] + sub; e < e1; e += kGroup) {
-    const bool own = e >= eo;
-    const int32_t q = own ? h0 + (e - eo) : NSL[e];
-    const R4<R> f = gld(RF + q), t = gld(RT + q);
-    const R sg = own ? (R)1 : (R)-1;
-    R tr[3] = {0, 0, 0};
-    if (rolling) {
-      const R4<R> u = gld(RR + q);
-      tr[0] = u.x; tr[1] = u.y; tr[2] = u.z;
+  // four row positions per round: the slots, then the flags and the records
+  // together (a record whose flag is clear was not written this step and is not
+  // used), then the slots in contact added in row order
+  constexpr int kU = 4;
+  for (int32_t e0 = own_in.e0 + sub; e0 < e1; e0 += kU * kGroup) {
+    int32_t q[kU];
+    bool own[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int32_t e = e0 + u * kGroup;
+      own[u] = e >= eo;
+      q[u] = e < e1 ? (own[u] ? h0 + (e - eo) : NSL[e]) : -1;
     }
-    F[0] += sg * f.x; F[1] += sg * f.y; F[2] += sg * f.z;
-    T[0] += ra * t.x + sg * tr[0];
-    T[1] += ra * t.y + sg * tr[1];
-    T[2] += ra * t.z + sg * tr[2];
+    uint8_t fl[kU];
+    R f[kU][3], t[kU][3], tr[kU][3];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int32_t qs = q[u] >= 0 ? q[u] : 0;
+      fl[u] = q[u] >= 0 ? FL[qs] : 0;
+      rec_get<R>(d.rec[0], qs, f[u], t[u]);
+      tr[u][0] = tr[u][1] = tr[u][2] = (R)0;
+      if (rolling) {
+        const R4<R> v = gld(RR + qs);
+        tr[u][0] = v.x; tr[u][1] = v.y; tr[u][2] = v.z;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (!fl[u]) continue;
+      const R sg = own[u] ? (R)1 : (R)-1;
+      F[0] += sg * f[u][0]; F[1] += sg * f[u][1]; F[2] += sg * f[u][2];
+      T[0] += ra * t[u][0] + sg * tr[u][0];
+      T[1] += ra * t[u][1] + sg * tr[u][1];
+      T[2] += ra * t[u][2] + sg * tr[u][2];
+    }
   }
-  particle_finish<R, kGroup>(d, a, c, lk, i, sub, s, pi, v, w, F, T);
+  particle_finish<R, kGroup>(d, a, c, lk, i, sub, s, pi, own_in.v, own_in.w, F, T, own_in.fin);
 }
 
 template <typename R, int kGroup>
 __global__ __launch_bounds__(256) void k_gather(const DevState* __restrict__ dp, StepArgs a) {
   const DevState& d = *dp;
-  if (*d.abort_step <= a.step) return;
   const int sub = threadIdx.x & (kGroup - 1);
   const int64_t i = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / kGroup;
   if (i >= d.n) return;   // whole group
   const int in = a.in, out = a.out;
-  if (!G((const uint8_t*)d.alive[in])[i]) {   // whole group
+  // round trip 1: the abort step and everything of the particle's own
+  const int32_t abort_at = *G((const int32_t*)d.abort_step);
+  const uint8_t alive = G((const uint8_t*)d.alive[in])[i];
+  const int sl = G((const int32_t*)d.sample)[i];
+  OwnIn<R> q;
+  q.x = gld(G((const double4*)d.xr[in]) + i);
+  q.v = gld(G((const double4*)d.vel[in]) + i);
+  q.w = gld(G((const R4<R>*)d.omg[in]) + i);
+  q.e0 = G((const int32_t*)d.nrow)[i];
+  q.e1 = G((const int32_t*)d.nrow)[i + 1];
+  q.h0 = G((const int32_t*)d.hrow)[i];
+  q.h1 = G((const int32_t*)d.hrow)[i + 1];
+  q.fin.w0 = G((const int32_t*)d.wrow)[i];
+  q.fin.w1 = G((const int32_t*)d.wrow)[i + 1];
+  q.fin.fd = d.fdr ? gld(G((const R4<R>*)d.fdr) + i) : mk4<R>(0, 0, 0, 0);
+  q.fin.xref = gld(G((const double4*)d.xref) + i);
+  asm volatile("" ::"v"((int)alive), "v"(sl), "v"(q.e0), "v"(q.e1), "v"(q.h0), "v"(q.h1), "s"(abort_at));
+  if (abort_at <= a.step) return;
+  if (!alive) {   // whole group
     if (sub == 0) {
-      gst(G(d.xr[out]) + i, gld(G((const double4*)d.xr[in]) + i));
-      gst(G(d.vel[out]) + i, gld(G((const double4*)d.vel[in]) + i));
-      gst(G((R4<R>*)d.omg[out]) + i, gld(G((const R4<R>*)d.omg[in]) + i));
+      gst(G(d.xr[out]) + i, q.x);
+      gst(G(d.vel[out]) + i, q.v);
+      gst(G((R4<R>*)d.omg[out]) + i, q.w);
       G(d.alive[out])[i] = 0;
     }
     return;
   }
-  const int sl = G((const int32_t*)d.sample)[i];
   uint64_t todo = __ballot(1);
   while (todo) {
     const int first = __builtin_ctzll(todo);
     const bool mine = sl == __builtin_amdgcn_readlane(sl, first);
-    if (mine) particle_gather<R, kGroup>(d, a, i, sub, opaque_readlane(sl, first));
+    if (mine) {
+      const int s = opaque_readlane(sl, first);
+      // the held fluid force counts only in a sample with fluid
+      if (!sample_const(d.sc, s).fluid_on) q.fin.fd = mk4<R>(0, 0, 0, 0);
+      particle_gather<R, kGroup>(d, a, i, sub, s, q);
+    }
     todo &= ~__ballot(mine);
   }
 }
