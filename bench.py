@@ -1,6 +1,6 @@
 """Benchmark: DEM + fluid-coupling steps on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c3] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c3|c3k] [--no-cpu]
                 [--skin-factor F] [--lanes L] [--graphs 0|1] [--tune]
 
 Workload c1: 200 000 polydisperse spheres in the hollow cylinder with the radial
@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # neighbour skin / smallest radius: c1 tuned over its 5 000-step run (the cavity face erodes and
 # particles speed up, so a wider skin pays); the boxes keep the library default
-SKIN_FACTOR = {"c1": 1.2, "c0": 0.4, "c3": 0.4}
+SKIN_FACTOR = {"c1": 1.2, "c0": 0.4, "c3": 0.4, "c3k": 0.4}
 LANES = 2           # lanes per particle of the row gather (the library default in half-pair mode)
 
 
@@ -83,8 +83,24 @@ def load_traffic(kernel, workload):
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle on the same workload, single thread, bounded sample."""
+def host_cpu():
+    """The host's CPU model and the logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(w, budget_s=25.0):
+    """The FP64 oracle on the same workload, single thread, bounded sample
+    (about 1.5 s per step at 200 000 spheres on a 2.7 GHz Xeon core, so the
+    budget holds some 15-20 steps, one or two coupling evaluations)."""
     import oracle
     from oracle import cg
     mat = cg.scale_material(w["material"], w.get("k", 1.0))
@@ -103,10 +119,38 @@ def cpu_baseline(w, budget_s=15.0):
         if el > budget_s or steps >= 200:
             break
     nal = int(sim.state()["alive"].sum())
-    return {"value": nal * steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+    return {"value": nal * steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
             "sample": "%s: %d particles, first %d steps from the initial packing (incl. one coupling "
                       "evaluation per %d steps), %.1f s; setup %.1f s excluded"
                       % (w["name"], len(w["r"]), steps, w["fluid"]["couple_every"], el, t_init)}
+
+
+def cpu_baseline_ensemble(ws, budget_s=25.0, steps=20):
+    """The FP64 oracle on the ensemble's samples in order, one at a time, each
+    for `steps` steps from its initial packing, single thread, until the budget
+    is spent."""
+    import oracle
+    from oracle import cg
+    done, el, t_init, n_s = 0.0, 0.0, 0.0, 0
+    for w in ws:
+        mat = cg.scale_material(w["material"], w.get("k", 1.0))
+        op = oracle.make_params(mat, w["dt"], g=w["g"], walls=w["walls"], grid=w["grid"], fluid=w["fluid"],
+                                outlet=w["outlet"])
+        t0 = time.perf_counter()
+        sim = oracle.OracleSim(op, w["x"], w["r"], bond_at_init=True)
+        sim.set_fluid(w["u_cell"], w["gradp_cell"])
+        t_init += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sim.step(steps)
+        el += time.perf_counter() - t0
+        done += float(sim.state()["alive"].sum()) * steps
+        n_s += 1
+        if el > budget_s:
+            break
+    return {"value": done / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
+            "sample": "the first %d of %d samples, %d steps each from their initial packings (incl. coupling "
+                      "evaluations every %d steps), %.1f s; setup %.1f s excluded"
+                      % (n_s, len(ws), steps, ws[0]["fluid"]["couple_every"], el, t_init)}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -241,13 +285,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c0", "c3"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c0", "c3", "c3k"],
+                    help="c3k: the ensemble with per-sample coarse-graining k = 1, 2, 3")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of oracle stepping (cpu_baseline)")
     ap.add_argument("--skin-factor", type=float, default=None,
                     help="neighbour skin as a multiple of the smallest radius (default per workload)")
     ap.add_argument("--lanes", type=int, default=LANES, help="lanes per particle of the step kernel")
-    ap.add_argument("--graphs", type=int, default=0, help="replay recorded step windows (timing off)")
+    ap.add_argument("--graphs", type=int, default=None, help="replay recorded step windows in the timed "
+                    "region (default: on for the ensembles, off for one sample)")
     ap.add_argument("--pair-mode", default=None, choices=["full", "half"],
                     help="contact evaluation: full rows (each pair twice) or half pairs with force records")
     ap.add_argument("--tune", action="store_true", help="autotune skin and lanes before the timed run")
@@ -278,8 +324,10 @@ def main():
     elif args.workload == "c0":
         ws = [synth.c0()]
     else:
-        ws = synth.c3()
+        ws = synth.c3(k_sweep=args.workload == "c3k")
     w = ws[0]
+    if args.graphs is None:
+        args.graphs = 1 if len(ws) > 1 else 0
     if args.skin_factor is None:
         args.skin_factor = SKIN_FACTOR[args.workload]
     tuned = None
@@ -312,14 +360,13 @@ def main():
     print("bench: %d timed steps done in %.1f ms" % (args.steps, ms), file=sys.stderr, flush=True)
     # instrumented pass for the kernel breakdown: HIP events recorded on the
     # context's stream around every launch of each kernel class
-    prof = None
+    # (timing launches one by one: with graphs on, these steps run without them)
     prof_steps = max(200, args.steps // 5)
-    if not args.graphs:
-        sim.profile(1)
-        sim.step(prof_steps)
-        prof = sim.read_profile()
-        sim.profile(0)
-        print("bench: %d instrumented steps done" % prof_steps, file=sys.stderr, flush=True)
+    sim.profile(1)
+    sim.step(prof_steps)
+    prof = sim.read_profile()
+    sim.profile(0)
+    print("bench: %d instrumented steps done" % prof_steps, file=sys.stderr, flush=True)
     st = sim.state()
     inf = sim.info()
     n_alive = 0.5 * (n0 + n1)
@@ -347,6 +394,16 @@ def main():
                 "spheres each, surface energy 0.1-1.0 J/m^2, own walls and 8-16^3 fluid grid), %d spheres in "
                 "total, dt 1e-7 s, coupling every %d steps" % (len(ws), n_total, w["fluid"]["couple_every"]))
         metric = "particle-steps/s, batched ensemble of 256 samples, 1 GPU"
+    elif args.workload == "c3k":
+        desc = ("c3k: batched ensemble of %d independent samples with coarse-graining k = 1, 2, 3 by turns "
+                "(crops of the settled C1 bed and of its k = 2 and k = 3 parcel beds, 500-20 000 fine-equivalent "
+                "grains each, surface energy 0.1-1.0 J/m^2, own walls and 8-16^3 fluid grid), %d spheres and "
+                "parcels in total, dt 1e-7 s, coupling every %d steps" % (len(ws), n_total, w["fluid"]["couple_every"]))
+        metric = "particle-steps/s, batched ensemble of 256 samples with k = 1, 2, 3, 1 GPU"
+    elif args.workload == "c0":
+        desc = ("c0: %d spheres settled in a 3 mm box (six walls), 8^3 fluid grid, uniform upward flow, FP64, "
+                "dt 1e-7 s, coupling every %d steps" % (len(w["r"]), w["fluid"]["couple_every"]))
+        metric = "particle-steps/s at %d particles, 1 GPU" % len(w["r"])
     else:
         desc = ("%s: %d polydisperse spheres (lognormal d, median 0.15 mm), hollow cylinder R 12 mm / cavity "
                 "2 mm, 48x48x24 fluid grid, radial Darcy inflow, dt 1e-7 s, coupling every %d steps"
@@ -383,8 +440,9 @@ def main():
     if not args.no_learned_cg and args.workload == "c1":
         out["learned_cg"] = (learned_cg_block(args.cg_horizon, ks=(3,), c4=True) if args.cg_c4
                              else learned_cg_block(args.cg_horizon))
-    if not args.no_cpu and args.workload != "c3":
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    if not args.no_cpu:
+        out["cpu_baseline"] = (cpu_baseline(w, args.cpu_budget) if len(ws) == 1
+                               else cpu_baseline_ensemble(ws, args.cpu_budget))
     print(json.dumps(out), flush=True)
 
 

@@ -333,7 +333,8 @@ def c3_crop(s, n_s, gamma, base=None):
     2 pi s / 37 in the annulus; shifted to the origin, with six walls one
     largest radius outside the box (no initial wall overlap), a grid of 8-16
     cells per side and a uniform upward flow.  Dense, settled and cheap: no
-    packing run per sample."""
+    packing run per sample.  A coarse-grained base (c2) gives a sample of its
+    parcels, with the base's k and scheme."""
     base = base if base is not None else c1()
     x, r = base["x"], base["r"]
     z0, z1 = 0.05e-3, 2.4e-3
@@ -352,19 +353,31 @@ def c3_crop(s, n_s, gamma, base=None):
     u, gp = uniform_field(grid, (0.0, 0.0, 0.02))
     mat = dict(MATERIAL)
     mat["gamma"] = gamma
-    return dict(name="c3_s%d_n%d" % (s, n_s), x=xs, r=rs, material=mat, k=1.0, scheme="ssw",
+    k = float(base.get("k", 1.0))
+    return dict(name="c3_s%d_n%d_k%g" % (s, n_s, k), x=xs, r=rs, material=mat, k=k,
+                scheme=base.get("scheme", "ssw"),
                 walls=box_walls(tuple(wlo), tuple(whi)), grid=grid, u_cell=u, gradp_cell=gp,
                 fluid=dict(WATER, n_min=N_MIN, voidfrac=0, u_superficial=1, couple_every=COUPLE_EVERY),
                 outlet=None, dt=DT, g=GRAV, sha256=base["sha256"], precision="mixed", steps=2000,
-                n_fine=len(rs))
+                n_fine=int(round(len(rs) * k ** 3)))
 
 
-def c3(n_samples=256, seed=SEED0 + 3):
+def c3(n_samples=256, seed=SEED0 + 3, k_sweep=False):
     """The batched ensemble: n_samples crops with sizes 500-20 000 and surface
-    energies 0.1-1.0 J/m^2 (c3_sizes)."""
+    energies 0.1-1.0 J/m^2 (c3_sizes).  k_sweep: sample s is coarse-grained
+    with k = 1 + (s mod 3), a crop of the k-scaled bed (c1, c2(2), c2(3))
+    holding the sample's size in fine-equivalent grains (size / k^3 parcels, at
+    least 60)."""
     ns, gam = c3_sizes(n_samples, seed)
-    base = c1()
-    return [c3_crop(s, int(ns[s]), float(gam[s]), base) for s in range(n_samples)]
+    if not k_sweep:
+        base = c1()
+        return [c3_crop(s, int(ns[s]), float(gam[s]), base) for s in range(n_samples)]
+    bases = {1: c1(), 2: c2(2), 3: c2(3)}
+    out = []
+    for s in range(n_samples):
+        k = 1 + s % 3
+        out.append(c3_crop(s, max(60, int(round(ns[s] / k ** 3))), float(gam[s]), bases[k]))
+    return out
 
 
 def c1_ring(r_crop=2.8e-3, U_cav=2.0, outlet_shift=0.06e-3, v_in=0.3, precision="fp64"):

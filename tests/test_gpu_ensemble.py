@@ -109,3 +109,59 @@ def test_c3_full_size_sampled_against_oracle():
         assert err.max() < 1e-5, s
         mine = pairs[(pairs[:, 0] >= a) & (pairs[:, 0] < b)] - a
         np.testing.assert_array_equal(mine, o.pairs()["pairs"])
+
+
+# (sample index, size in parcels, surface energy, coarse-graining factor k)
+K_SIZES = [(0, 900, 0.2, 1), (4, 400, 0.8, 2), (8, 150, 0.5, 3), (13, 1200, 0.35, 1), (17, 260, 0.6, 3),
+           (22, 500, 0.95, 2)]
+
+
+def _k_samples(precision):
+    bases = {1: synth.c1(), 2: synth.c2(2), 3: synth.c2(3)}
+    ws = [synth.c3_crop(s, n, g, bases[k]) for s, n, g, k in K_SIZES]
+    for w in ws:
+        w["precision"] = precision
+    return ws
+
+
+def test_ensemble_per_sample_k_matches_oracle():
+    """Samples with their own coarse-graining factor (k = 1, 2, 3: gamma x k,
+    drag k^3 f(d/k)) in one context: each reproduces the FP64 oracle run of that
+    sample alone with its grain-scale material."""
+    ws = _k_samples("fp64")
+    assert sorted({w["k"] for w in ws}) == [1.0, 2.0, 3.0]
+    sim, offs = _batched(ws, "fp64")
+    nsteps = 2 * ws[0]["fluid"]["couple_every"] + 3
+    sim.step(nsteps)
+    st = sim.state()
+    pairs = sim.pairs()["pairs"]
+    agg = sim.aggregates()
+    for s, w in enumerate(ws):
+        o = _oracle(w)
+        o.step(nsteps)
+        os_ = o.state()
+        a, b = offs[s], offs[s + 1]
+        err = np.linalg.norm(st["F"][a:b] - os_["F"], axis=1) / (os_["fscale"] + 1e-300)
+        assert err.max() < 1e-12, (s, w["k"])
+        terr = np.linalg.norm(st["T"][a:b] - os_["T"], axis=1) / (os_["tscale"] + 1e-300)
+        assert terr.max() < 1e-12, (s, w["k"])
+        np.testing.assert_allclose(st["x"][a:b], os_["x"], rtol=0, atol=1e-16)
+        mine = pairs[(pairs[:, 0] >= a) & (pairs[:, 0] < b)] - a
+        np.testing.assert_array_equal(mine, o.pairs()["pairs"])
+        assert agg["broken_bonds"][s] == o.scalars()["broken_bonds"]
+
+
+def test_ensemble_graph_windows_identical_to_direct_launches():
+    """The mixed-k ensemble with recorded step windows replayed (as the bench
+    times it) gives the states of direct launches bit for bit, over several
+    calls and coupling evaluations."""
+    ws = _k_samples("mixed")
+    out = []
+    for graphs in (False, True):
+        sim, _ = _batched(ws, "mixed")
+        sim.set_graphs(graphs)
+        for k in (23, 5, 31, 1):
+            sim.step(k)
+        out.append(sim.state())
+    for key in ("x", "v", "w", "F", "T"):
+        np.testing.assert_array_equal(out[0][key], out[1][key], err_msg=key)
