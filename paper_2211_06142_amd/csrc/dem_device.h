@@ -54,6 +54,15 @@ __device__ inline float4 gld(gptr<const float4> p) {
 __device__ inline void gst(gptr<double4> p, const double4& v) { *(gptr<gd4>)p = gd4{v.x, v.y, v.z, v.w}; }
 __device__ inline void gst(gptr<float4> p, const float4& v) { *(gptr<gf4>)p = gf4{v.x, v.y, v.z, v.w}; }
 
+// LDS written by some lanes of a wave and read by others: keep the compiler
+// from moving the accesses across this point (the LDS executes the accesses
+// of one wave in order).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Pair record of the half-pair mode: the force on the owner and n x F_t, six R
 // packed in three 2-vectors (24 B per slot in mixed precision).
 template <typename R> struct V2T;

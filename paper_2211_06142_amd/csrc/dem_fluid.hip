@@ -24,12 +24,15 @@ __global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
   const DevState& d = *dp;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
+  if (*d.abort) return;
   const SampleConst& c = sample_const(d.sc, d.sample[i]);
   int64_t nd = (int64_t)c.dn[0] * c.dn[1] * c.dn[2];
   const int32_t skip = (int32_t)(c.dual_base + nd);
-  if (*d.abort || !d.alive[buf][i] || !c.fluid_on) { d.dkey[i] = skip; return; }
   const double4 p = d.xr[buf][i];
-  if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) { d.dkey[i] = skip; return; }
+  if (!d.alive[buf][i] || !c.fluid_on || !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) {
+    d.dkey[i] = skip;
+    return;
+  }
   const double xs[3] = {p.x, p.y, p.z};
   int b[3];
   double f[3];
@@ -143,6 +146,34 @@ __device__ inline void group8_reduce_scatter(const double (&v)[M], int u, double
   }
 }
 
+// Lane u of bucket b's group: call fn(q) for every member q among the
+// candidates it takes (every 8th, starting at u) in scan order.
+template <typename Fn>
+__device__ inline void scan_members(const DevState& d, const SampleConst& c, int64_t b, int u, Fn&& fn) {
+  const int64_t l = b - c.dual_base;
+  const int D[3] = {(int)(l % c.dn[0]), (int)((l / c.dn[0]) % c.dn[1]), (int)(l / ((int64_t)c.dn[0] * c.dn[1]))};
+  const int cen = c.voidfrac == DEM_VOID_CENTROID;
+  int q0[3], q1[3];
+  for (int k = 0; k < 3; ++k) member_bins(c, k, D[k], cen, q0[k], q1[k]);
+  const auto KEY = G((const int32_t*)d.dkey);
+  const auto CS = G((const int32_t*)d.cell_start);
+  for (int bz = q0[2]; bz <= q1[2]; ++bz)
+    for (int by = q0[1]; by <= q1[1]; ++by) {
+      const int64_t row = c.bin_base + ((int64_t)bz * c.bn[1] + by) * c.bn[0];
+      const int32_t m1 = CS[row + q1[0] + 1];
+      // four candidates per lane and round: all key loads before any use
+      constexpr int kU = 4;
+      for (int32_t m0 = CS[row + q0[0]] + u; m0 < m1; m0 += 8 * kU) {
+        int32_t ks[kU];
+#pragma unroll
+        for (int v = 0; v < kU; ++v) ks[v] = m0 + 8 * v < m1 ? KEY[m0 + 8 * v] : -1;
+#pragma unroll
+        for (int v = 0; v < kU; ++v)
+          if (ks[v] == (int32_t)b) fn(m0 + 8 * v);
+      }
+    }
+}
+
 template <int kKind>
 __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restrict__ dp) {
   const DevState& d = *dp;
@@ -153,7 +184,7 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
   const int u = (int)(gid & 7);
   if (b >= d.ndual) return;   // whole group
   const auto OCC = G((uint8_t*)d.docc);
-  const auto PART = G(d.dpart);
+  const auto PART = G(d.dpart + (kKind == 0 ? 0 : 8 * (d.ndual + 1)));
   if (!OCC[b]) {   // no member: zero partials (lane u writes outputs u, u + 8, ...)
 #pragma unroll
     for (int j = 0; j < m / 8; ++j) PART[m * b + 8 * j + u] = 0.0;
@@ -170,34 +201,12 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
       for (int v = 0; v < listed; ++v) add_member<kKind>(d, LM[v], acc);
     } else {
       const SampleConst& c = sample_const(d.sc, G((const int32_t*)d.dual_sample)[b]);
-      const int64_t l = b - c.dual_base;
-      const int D[3] = {(int)(l % c.dn[0]), (int)((l / c.dn[0]) % c.dn[1]), (int)(l / ((int64_t)c.dn[0] * c.dn[1]))};
-      const int cen = c.voidfrac == DEM_VOID_CENTROID;
-      int q0[3], q1[3];
-      for (int k = 0; k < 3; ++k) member_bins(c, k, D[k], cen, q0[k], q1[k]);
-      const auto KEY = G((const int32_t*)d.dkey);
-      const auto CS = G((const int32_t*)d.cell_start);
       int found = 0;
-      for (int bz = q0[2]; bz <= q1[2]; ++bz)
-        for (int by = q0[1]; by <= q1[1]; ++by) {
-          const int64_t row = c.bin_base + ((int64_t)bz * c.bn[1] + by) * c.bn[0];
-          const int32_t m1 = CS[row + q1[0] + 1];
-          // four candidates per lane and round: all key loads before any use
-          constexpr int kU = 4;
-          for (int32_t m0 = CS[row + q0[0]] + u; m0 < m1; m0 += 8 * kU) {
-            int32_t ks[kU];
-#pragma unroll
-            for (int v = 0; v < kU; ++v) ks[v] = m0 + 8 * v < m1 ? KEY[m0 + 8 * v] : -1;
-#pragma unroll
-            for (int v = 0; v < kU; ++v) {
-              if (ks[v] != (int32_t)b) continue;
-              const int32_t q = m0 + 8 * v;
-              add_member<kKind>(d, q, acc);
-              if (kKind == 0 && found < kLaneMem) LM[found] = q;
-              ++found;
-            }
-          }
-        }
+      scan_members(d, c, b, u, [&](int32_t q) {
+        add_member<kKind>(d, q, acc);
+        if (kKind == 0 && found < kLaneMem) LM[found] = q;
+        ++found;
+      });
       if (kKind == 0) LN[gid] = (uint8_t)(found < 255 ? found : 255);
     }
   }
@@ -209,15 +218,23 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
   if (kKind == 1 && u == 0) OCC[b] = 0;
 }
 
-// per fluid cell: fixed-order sum of the corner partials of the adjacent buckets
+// Per fluid cell: the sum of the corner partials of the (up to 8) adjacent
+// buckets.  A group of 8 lanes serves a cell, lane u = (dz dy dx) the bucket at
+// offset (dx, dy, dz) from the lowest adjacent one; the lanes' values are added
+// in a fixed xor tree (partners 4, 2, 1), which leaves every lane with the same
+// total (each stage adds the same two values in either order).  Kind 0: solid
+// volume (d.dpart, 8 per bucket) -> porosity and fluid velocity; kind 1: drag
+// (d.dpart + 8 (ndual + 1), 24 per bucket) -> the cell's drag source (eq 7).
 template <int kKind>
-__global__ void k_fluid_cells(const DevState* __restrict__ dp) {
+__global__ __launch_bounds__(256) void k_fluid_cells(const DevState* __restrict__ dp) {
   const DevState& d = *dp;
   if (*d.abort) return;
-  int64_t C = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (C >= d.ncell) return;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t C = gid >> 3;
+  const int u = (int)(gid & 7);
+  if (C >= d.ncell) return;   // whole group
   const SampleConst& c = sample_const(d.sc, d.cell_sample[C]);
-  int64_t l = C - c.cell_base;
+  const int64_t l = C - c.cell_base;
   const int cc[3] = {(int)(l % c.gn[0]), (int)((l / c.gn[0]) % c.gn[1]), (int)(l / ((int64_t)c.gn[0] * c.gn[1]))};
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
   int lo[3], hi[3];
@@ -226,36 +243,37 @@ __global__ void k_fluid_cells(const DevState* __restrict__ dp) {
     else if (c.gn[k] == 1) { lo[k] = hi[k] = 0; }
     else { lo[k] = cc[k] - 1 < 0 ? 0 : cc[k] - 1; hi[k] = cc[k] > c.gn[k] - 2 ? c.gn[k] - 2 : cc[k]; }
   }
-  double s[3] = {0, 0, 0};
-  for (int Dz = lo[2]; Dz <= hi[2]; ++Dz)
-    for (int Dy = lo[1]; Dy <= hi[1]; ++Dy)
-      for (int Dx = lo[0]; Dx <= hi[0]; ++Dx) {
-        int64_t key = c.dual_base + ((int64_t)Dz * c.dn[1] + Dy) * c.dn[0] + Dx;
-        // corner of this cell in the bucket; a direction of one cell folds
-        // both trilinear weights onto the only cell
-        int kx = (cen || c.gn[0] == 1) ? -1 : cc[0] - Dx;
-        int ky = (cen || c.gn[1] == 1) ? -1 : cc[1] - Dy;
-        int kz = (cen || c.gn[2] == 1) ? -1 : cc[2] - Dz;
-        for (int cz = 0; cz < 2; ++cz) {
-          if (kz >= 0 ? cz != kz : (cen && cz != 0)) continue;
-          for (int cy = 0; cy < 2; ++cy) {
-            if (ky >= 0 ? cy != ky : (cen && cy != 0)) continue;
-            for (int cx = 0; cx < 2; ++cx) {
-              if (kx >= 0 ? cx != kx : (cen && cx != 0)) continue;
-              int corner = (cz << 2) | (cy << 1) | cx;
-              if (kKind == 0) {
-                s[0] += d.dpart[8 * key + corner];
-              } else {
-                s[0] += d.dpart[24 * key + 3 * corner];
-                s[1] += d.dpart[24 * key + 3 * corner + 1];
-                s[2] += d.dpart[24 * key + 3 * corner + 2];
-              }
-            }
-          }
+  constexpr int m = kKind == 0 ? 8 : 24, nv = m / 8;
+  const double* part = d.dpart + (kKind == 0 ? 0 : 8 * (d.ndual + 1));
+  const int Dx = lo[0] + (u & 1), Dy = lo[1] + ((u >> 1) & 1), Dz = lo[2] + (u >> 2);
+  double s[nv];
+  for (int v = 0; v < nv; ++v) s[v] = 0.0;
+  if (Dx <= hi[0] && Dy <= hi[1] && Dz <= hi[2]) {
+    const int64_t key = c.dual_base + ((int64_t)Dz * c.dn[1] + Dy) * c.dn[0] + Dx;
+    // corner of this cell in the bucket; a direction of one cell folds both
+    // trilinear weights onto the only cell
+    const int kx = (cen || c.gn[0] == 1) ? -1 : cc[0] - Dx;
+    const int ky = (cen || c.gn[1] == 1) ? -1 : cc[1] - Dy;
+    const int kz = (cen || c.gn[2] == 1) ? -1 : cc[2] - Dz;
+    for (int cz = 0; cz < 2; ++cz) {
+      if (kz >= 0 ? cz != kz : (cen && cz != 0)) continue;
+      for (int cy = 0; cy < 2; ++cy) {
+        if (ky >= 0 ? cy != ky : (cen && cy != 0)) continue;
+        for (int cx = 0; cx < 2; ++cx) {
+          if (kx >= 0 ? cx != kx : (cen && cx != 0)) continue;
+          const int corner = (cz << 2) | (cy << 1) | cx;
+          for (int v = 0; v < nv; ++v) s[v] += part[m * key + nv * corner + v];
         }
       }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < nv; ++v)
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) s[v] += __shfl_xor(s[v], off, 8);
+  if (u != 0) return;
   if (kKind == 0) {
-    double eps = s[0] / c.vcell;
+    const double eps = s[0] / c.vcell;
     d.eps[C] = eps;
     double nn = 1.0 - eps;
     if (nn < c.n_min) nn = c.n_min;
@@ -267,9 +285,7 @@ __global__ void k_fluid_cells(const DevState* __restrict__ dp) {
   }
 }
 
-// Di Felice drag (eq 8-11) with the coarse-grained rule, buoyancy and the
-// dynamic pressure gradient; trilinear interpolation of n, u, grad p
-// porosity, fluid velocity and dynamic pressure gradient at particle i, with
+// Porosity, fluid velocity and dynamic pressure gradient at particle i, with
 // the weights of its deposition (trilinear over the 8 surrounding cell centres,
 // or its own cell for centroid deposition)
 __device__ inline void particle_fluid(const DevState& d, const SampleConst& c, int64_t i, double& np, double u[3],
@@ -367,6 +383,27 @@ __global__ void k_closure_features(const DevState* __restrict__ dp, int buf) {
   f[5] = cnt;
 }
 
+// Di Felice drag of one particle (eq 8-11, coarse-grained k^3 f(d/k), closure
+// factor cdr) and buoyancy with the dynamic pressure gradient (eq 1), from the
+// porosity, fluid velocity and pressure gradient at the particle.
+__device__ inline void drag_force(const SampleConst& c, double np, const double u[3], const double gp[3],
+                                  const double4& v, double r, double V, double cdr, double fd[3], double fb[3]) {
+  double s[3] = {u[0] - v.x, u[1] - v.y, u[2] - v.z};
+  double sm = sqrt((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
+  fd[0] = fd[1] = fd[2] = 0.0;
+  if (sm > 0.0) {
+    double de = 2.0 * r / c.kcg;
+    double Re = c.rho_f * de * sm / c.mu_f;
+    double cd = 0.63 + 4.8 / sqrt(Re);
+    double Cd = cd * cd;
+    double lg = 1.5 - log10(Re);
+    double chi = 3.7 - 0.65 * exp(-(lg * lg) / 2.0);
+    double coef = 0.125 * Cd * c.rho_f * M_PI * de * de * sm * pow(np, -chi);
+    for (int k = 0; k < 3; ++k) fd[k] = c.k3 * coef * s[k] * cdr;
+  }
+  for (int k = 0; k < 3; ++k) fb[k] = -V * (gp[k] + c.rho_f * c.g[k]);
+}
+
 template <typename R>
 __global__ void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
   const DevState& d = *dp;
@@ -382,25 +419,8 @@ __global__ void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
   double np, u[3], gp[3];
   particle_fluid(d, c, i, np, u, gp);
   const double4 fr = d.dfr[i];
-  const double4 v = d.vel[buf][i];
-  const double r = d.xr[buf][i].w;
-  double s[3] = {u[0] - v.x, u[1] - v.y, u[2] - v.z};
-  double sm = sqrt((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
-  double fd[3] = {0, 0, 0};
-  if (sm > 0.0) {
-    double de = 2.0 * r / c.kcg;
-    double Re = c.rho_f * de * sm / c.mu_f;
-    double cd = 0.63 + 4.8 / sqrt(Re);
-    double Cd = cd * cd;
-    double lg = 1.5 - log10(Re);
-    double chi = 3.7 - 0.65 * exp(-(lg * lg) / 2.0);
-    double coef = 0.125 * Cd * c.rho_f * M_PI * de * de * sm * pow(np, -chi);
-    double cdr = d.cdrag ? d.cdrag[i] : 1.0;
-    for (int k = 0; k < 3; ++k) fd[k] = c.k3 * coef * s[k] * cdr;
-  }
-  const double V = fr.w;
-  double fb[3];
-  for (int k = 0; k < 3; ++k) fb[k] = -V * (gp[k] + c.rho_f * c.g[k]);
+  double fd[3], fb[3];
+  drag_force(c, np, u, gp, d.vel[buf][i], d.xr[buf][i].w, fr.w, d.cdrag ? d.cdrag[i] : 1.0, fd, fb);
   d.fpart[i] = make_double4(fd[0], fd[1], fd[2], 0.0);
   ((R4<R>*)d.fdr)[i] = mk4<R>((R)(fd[0] + fb[0]), (R)(fd[1] + fb[1]), (R)(fd[2] + fb[2]), (R)0);
 }
@@ -408,14 +428,14 @@ __global__ void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
 template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
   hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
   hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
-  if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
+  if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell * 8)), dim3(kBlock), 0, s, d.self);
   if (d.closure_on) {
     hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
     launch_closure_infer(d, s);
   }
   hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
   hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
-  if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell)), dim3(kBlock), 0, s, d.self);
+  if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell * 8)), dim3(kBlock), 0, s, d.self);
 }
 template void launch_fluid<double>(DevState&, int, hipStream_t);
 template void launch_fluid<float>(DevState&, int, hipStream_t);

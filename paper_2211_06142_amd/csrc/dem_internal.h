@@ -145,7 +145,8 @@ struct DevState {
   double *u_in, *gp_in;            // 3*ncell
   double *cell_n, *cell_u;         // ncell, 3*ncell
   double *eps, *fdc;               // ncell, 3*ncell (latest evaluation)
-  double* dpart;                   // 8 * ndual corner partial sums (reused for 3 * 8 drag partials)
+  double* dpart;                   // per bucket: 8 solid-volume corner partials, then (from
+                                   // 8 * (ndual + 1) on) 24 drag corner partials
   int32_t* dkey;
   uint8_t* docc;                   // ndual: bucket named by some particle's key in this evaluation
   int32_t* dlmem;                  // 8 * ndual * 4: members found by each lane of a bucket's group

@@ -137,15 +137,6 @@ template <typename R, int kGroup> struct WaveQueue {
   int32_t base[kKCap];    // queue slot of the first of them
 };
 
-// LDS written by some lanes of a wave and read by others: keep the compiler
-// from moving the accesses across this point (the LDS executes the accesses
-// of one wave in order).
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // What the end of a particle's step reads besides its own state: its wall
 // entries and the held fluid force, loaded at the start of the step together
 // with the particle's own state (their loads do not wait for the row walk).
