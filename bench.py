@@ -192,7 +192,9 @@ def closure_block(w, torch):
     flop_f = MLP_FLOP_FWD * n
     out = {"batch": n, "forward_us": ms_f * 1e3, "forward_tflops": flop_f / (ms_f * 1e-3) / 1e12,
            "train_step_us": ms_t * 1e3, "train_tflops": 3 * flop_f / (ms_t * 1e-3) / 1e12,
-           "mfma_peak_tflops": MFMA_BF16_PEAK_TFLOPS}
+           "mfma_peak_tflops": MFMA_BF16_PEAK_TFLOPS, "forward_frac": flop_f / (ms_f * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
+           "mfma": "v_mfma_f32_16x16x32_bf16 (hidden and output layers, weight gradients), "
+                   "v_mfma_f32_16x16x16_bf16 (the 6 inputs, the 2 outputs backward)"}
     # closure inside the coupling: instrumented coupling class with and without
     norm = np.array([0.6, 0.05, 2.0, 1.0, 0.01, 4.0, 0.2, 0.05, 2.0, 1.0, 0.02, 3.0])
     per = {}

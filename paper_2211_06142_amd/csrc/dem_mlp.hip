@@ -2,15 +2,22 @@
 // of the method; not in arXiv:2211.06142).
 //
 // Network 6 -> 64 -> 64 -> 64 -> 2, GELU (erf form) on the hidden layers,
-// BF16 operands with FP32 accumulation on v_mfma_f32_16x16x16_bf16.  Flat
+// BF16 operands with FP32 accumulation on the matrix cores: gfx950's
+// v_mfma_f32_16x16x32_bf16 for every contraction over 64 features and over the
+// samples, v_mfma_f32_16x16x16_bf16 where the contraction has at most 16 terms
+// (the 6 inputs of layer 1, the 2 outputs in the backward pass).  Flat
 // parameter layout (FP32 master, BF16 copy at the same offsets):
 //   W1 6x64 | b1 | W2 64x64 | b2 | W3 64x64 | b3 | W4 64x2 | b4,  W[k][m] row-major
 //
 // Transposed evaluation.  One wavefront takes 16 samples and computes
 // Z^T = W^T H^T: the 16x16 output fragment of one MFMA holds features
-// 4(lane/16)+i of sample lane%16, which is exactly the layout of the B operand
-// of the next layer, so activations never leave the registers between layers
-// (no LDS transposes).  The backward pass runs the same way with W in place of
+// 4(lane/16)+i of sample lane%16.  The K = 32 MFMA pairs element j of lane group
+// q of A with element j of lane group q of B; a contraction is a sum, so any
+// assignment of the 32 features of a K tile to (q, j) serves if A and B share
+// it.  Taking j < 4 from output tile 2t and j >= 4 from tile 2t + 1 (feature
+// 32t + 4q + (j mod 4) + 16 (j div 4)) makes the B operand of the next layer
+// the two output fragments side by side, so activations never leave the
+// registers between layers (no LDS transposes, no lane exchange).  The backward pass runs the same way with W in place of
 // W^T.  Weight gradients contract over the samples: a split-K MFMA product per
 // chunk of samples, then a fixed-order sum over chunks, so every result is
 // bitwise reproducible.
@@ -47,6 +54,19 @@ __device__ inline f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+// D += A B over K = 32: lane l holds A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16]
+// (j = 0 .. 7) and receives D[4 (l / 16) + i][l % 16]
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
+}
+// two output fragments side by side: the B operand of a K = 32 tile
+__device__ inline bf16x8 cat8(bf16x4 a, bf16x4 b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); }
+// feature of element j of lane group q in K tile t (the assignment above)
+__device__ inline int kperm(int t, int q, int j) { return 32 * t + 4 * q + (j & 3) + 16 * (j >> 2); }
+
 // A fragment of W^T (rows = outputs m, columns = inputs k) for output tile mt
 // and input tile kt of a K x M layer: lane holds W[16kt + 4q + i][16mt + r]
 __device__ inline bf16x4 wt_frag(const short* wb, int off, int K, int M, int mt, int kt, int q, int r) {
@@ -58,6 +78,29 @@ __device__ inline bf16x4 wt_frag(const short* wb, int off, int K, int M, int mt,
   }
   return a;
 }
+// K = 32 fragment of W^T for output tile mt and K tile t: lane holds
+// W[kperm(t, q, j)][16mt + r]
+__device__ inline bf16x8 wt_frag32(const short* wb, int off, int K, int M, int mt, int t, int q, int r) {
+  bf16x8 a;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    int k = kperm(t, q, j), m = 16 * mt + r;
+    a[j] = (k < K && m < M) ? wb[off + k * M + m] : (short)0;
+  }
+  return a;
+}
+// K = 32 fragment of W (contraction over the outputs m) for input tile kt and
+// K tile t: lane holds W[16kt + r][kperm(t, q, j)]
+__device__ inline bf16x8 w_frag32(const short* wb, int off, int K, int M, int kt, int t, int q, int r) {
+  bf16x8 a;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    int k = 16 * kt + r, m = kperm(t, q, j);
+    a[j] = (k < K && m < M) ? wb[off + k * M + m] : (short)0;
+  }
+  return a;
+}
+
 // A fragment of W (rows = inputs k, columns = outputs m) for input tile kt and
 // output tile mt: lane holds W[16kt + r][16mt + 4q + i]
 __device__ inline bf16x4 w_frag(const short* wb, int off, int K, int M, int kt, int mt, int q, int r) {
@@ -89,10 +132,37 @@ struct MlpTrainBuf {
   float* err;    // B: squared error of the sample
 };
 
+// The lane's fragments of every weight and bias (about 90 registers), loaded
+// once per wavefront and kept across the tiles it evaluates.
+struct WeightFrags {
+  bf16x4 w1[4];
+  bf16x8 w2[4][2], w3[4][2], w4[2];
+  f32x4 b1[4], b2[4], b3[4], b4;
+};
+__device__ inline WeightFrags load_frags(const short* wb, const float* pf, int q, int r) {
+  WeightFrags W;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    W.w1[mt] = wt_frag(wb, kW1, 6, 64, mt, 0, q, r);
+    W.b1[mt] = bias_frag(pf, kB1, 64, mt, q);
+    W.b2[mt] = bias_frag(pf, kB2, 64, mt, q);
+    W.b3[mt] = bias_frag(pf, kB3, 64, mt, q);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      W.w2[mt][t] = wt_frag32(wb, kW2, 64, 64, mt, t, q, r);
+      W.w3[mt][t] = wt_frag32(wb, kW3, 64, 64, mt, t, q, r);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) W.w4[t] = wt_frag32(wb, kW4, 64, 2, 0, t, q, r);
+  W.b4 = bias_frag(pf, kB4, 2, 0, q);
+  return W;
+}
+
 // One tile of 16 samples (rows s0 .. s0+15; rows >= B are padding).  Returns
 // the output fragment: lanes 0-15, items 0-1 hold y0, y1 of sample lane.
 template <bool kTrain>
-__device__ f32x4 forward_tile(const short* wb, const float* pf, bf16x4 a0, int q, int r, int64_t s0, int64_t B,
+__device__ f32x4 forward_tile(const WeightFrags& W, bf16x4 a0, int q, int r, int64_t s0, int64_t B,
                               const MlpTrainBuf& tb) {
   const int64_t s = s0 + r;
   const bool valid = s < B;
@@ -105,8 +175,7 @@ __device__ f32x4 forward_tile(const short* wb, const float* pf, bf16x4 a0, int q
   // layer 1: 6 -> 64
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = bias_frag(pf, kB1, 64, mt, q);
-    acc = mfma16(wt_frag(wb, kW1, 6, 64, mt, 0, q, r), a0, acc);
+    f32x4 acc = mfma16(W.w1[mt], a0, W.b1[mt]);
 #pragma unroll
     for (int i = 0; i < 4; ++i) h[mt][i] = f2bf(gelu_f(acc[i]));
     if (kTrain && valid) {
@@ -117,13 +186,13 @@ __device__ f32x4 forward_tile(const short* wb, const float* pf, bf16x4 a0, int q
   // layers 2 and 3: 64 -> 64
 #pragma unroll
   for (int l = 1; l < 3; ++l) {
-    const int offW = l == 1 ? kW2 : kW3, offB = l == 1 ? kB2 : kB3;
     bf16x4 hn[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-      f32x4 acc = bias_frag(pf, offB, 64, mt, q);
+      f32x4 acc = l == 1 ? W.b2[mt] : W.b3[mt];
 #pragma unroll
-      for (int kt = 0; kt < 4; ++kt) acc = mfma16(wt_frag(wb, offW, 64, 64, mt, kt, q, r), h[kt], acc);
+      for (int t = 0; t < 2; ++t)
+        acc = mfma32(l == 1 ? W.w2[mt][t] : W.w3[mt][t], cat8(h[2 * t], h[2 * t + 1]), acc);
 #pragma unroll
       for (int i = 0; i < 4; ++i) hn[mt][i] = f2bf(gelu_f(acc[i]));
       if (kTrain && valid) {
@@ -135,9 +204,9 @@ __device__ f32x4 forward_tile(const short* wb, const float* pf, bf16x4 a0, int q
     for (int mt = 0; mt < 4; ++mt) h[mt] = hn[mt];
   }
   // layer 4: 64 -> 2 (one padded output tile)
-  f32x4 y = bias_frag(pf, kB4, 2, 0, q);
+  f32x4 y = W.b4;
 #pragma unroll
-  for (int kt = 0; kt < 4; ++kt) y = mfma16(wt_frag(wb, kW4, 64, 2, 0, kt, q, r), h[kt], y);
+  for (int t = 0; t < 2; ++t) y = mfma32(W.w4[t], cat8(h[2 * t], h[2 * t + 1]), y);
   return y;
 }
 
@@ -159,9 +228,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const short* wb, const floa
   const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   MlpTrainBuf none{};
+  const WeightFrags W = load_frags(wb, pf, q, r);
   for (int64_t t = w0; t < nt; t += nw) {
     const int64_t s = t * 16 + r;
-    f32x4 out = forward_tile<false>(wb, pf, input_frag(x, 6, s, B, q), q, r, t * 16, B, none);
+    f32x4 out = forward_tile<false>(W, input_frag(x, 6, s, B, q), q, r, t * 16, B, none);
     if (q == 0 && s < B) {
       y[2 * s] = out[0];
       y[2 * s + 1] = out[1];
@@ -178,9 +248,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const float scale = 2.0f / (2.0f * (float)B);
+  const WeightFrags W = load_frags(wb, pf, q, r);
   for (int64_t t = w0; t < nt; t += nw) {
     const int64_t s = t * 16 + r;
-    f32x4 out = forward_tile<true>(wb, pf, input_frag(x, 6, s, B, q), q, r, t * 16, B, tb);
+    f32x4 out = forward_tile<true>(W, input_frag(x, 6, s, B, q), q, r, t * 16, B, tb);
     if (q == 0 && s < B) {
       float e0 = out[0] - tgt[2 * s], e1 = out[1] - tgt[2 * s + 1];
       tb.g4[2 * s] = scale * e0;
@@ -225,7 +296,8 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const short* wb, int64_t B
       for (int mt = 0; mt < 4; ++mt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) acc = mfma16(w_frag(wb, offW, 64, 64, mt, kt, q, r), g[kt], acc);
+        for (int t = 0; t < 2; ++t)
+          acc = mfma32(w_frag32(wb, offW, 64, 64, mt, t, q, r), cat8(g[2 * t], g[2 * t + 1]), acc);
         f32x4 z = valid ? *(const f32x4*)(tb.z[l] + s * 64 + 16 * mt + 4 * q) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < 4; ++i) gn[mt][i] = f2bf(acc[i] * gelu_df(z[i]));
@@ -284,15 +356,15 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(int64_t B, MlpTrainBuf tb, fl
       const bool bias = j >= KT * MT;
       const int kt = bias ? 0 : j / MT, mt = bias ? j - KT * MT : j % MT;
 #pragma unroll
-      for (int t = 0; t < kSub / 16; ++t) {
-        bf16x4 a, b;
+      for (int t = 0; t < kSub / 32; ++t) {
+        bf16x8 a, b;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int sr = 16 * t + 4 * q + i;
-          a[i] = bias ? (short)0x3F80 : Hs[sr][16 * kt + r];   // 0x3F80 = 1.0
-          b[i] = Gs[sr][16 * mt + r];
+        for (int j = 0; j < 8; ++j) {
+          const int sr = 32 * t + 8 * q + j;
+          a[j] = bias ? (short)0x3F80 : Hs[sr][16 * kt + r];   // 0x3F80 = 1.0
+          b[j] = Gs[sr][16 * mt + r];
         }
-        acc[u] = mfma16(a, b, acc[u]);
+        acc[u] = mfma32(a, b, acc[u]);
       }
     }
     __syncthreads();
@@ -383,6 +455,7 @@ __global__ __launch_bounds__(256) void k_closure_infer(const DevState* __restric
   const float* pf = d.cl_pf;
   MlpTrainBuf none{};
   const float L2 = 0.69314718055994531f;
+  const WeightFrags W = load_frags(wb, pf, q, r);
   for (int64_t t = w0; t < nt; t += nw) {
     const int64_t s = t * 16 + r;
     bf16x4 a;
@@ -392,7 +465,7 @@ __global__ __launch_bounds__(256) void k_closure_infer(const DevState* __restric
       a[i] = (s < d.n && k < 6) ? f2bf((float)((d.cfeat[6 * s + k] - d.cl_norm[k]) / d.cl_norm[6 + k]))
                                 : (short)0;
     }
-    f32x4 y = forward_tile<false>(wb, pf, a, q, r, t * 16, d.n, none);
+    f32x4 y = forward_tile<false>(W, a, q, r, t * 16, d.n, none);
     if (q == 0 && s < d.n) {
       float y0 = fminf(fmaxf(y[0], -L2), L2), y1 = fminf(fmaxf(y[1], -L2), L2);
       d.cdrag[s] = (double)expf(y0);
@@ -401,11 +474,17 @@ __global__ __launch_bounds__(256) void k_closure_infer(const DevState* __restric
   }
 }
 
-void launch_closure_infer(DevState& d, hipStream_t s) {
-  int64_t tiles = (d.n + 15) / 16;
+// blocks of 4 wavefronts, a tile of 16 samples per wavefront and round; at
+// most 4 wavefronts per SIMD, so that each keeps its weight fragments over
+// several tiles
+inline int mlp_grid(int64_t B) {
+  int64_t tiles = (B + 15) / 16;
   int64_t blocks = (tiles + 3) / 4;
-  if (blocks > 2048) blocks = 2048;
-  if (blocks > 0) hipLaunchKernelGGL(k_closure_infer, dim3((unsigned)blocks), dim3(256), 0, s, d.self);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 1024));
+}
+
+void launch_closure_infer(DevState& d, hipStream_t s) {
+  if (d.n > 0) hipLaunchKernelGGL(k_closure_infer, dim3((unsigned)mlp_grid(d.n)), dim3(256), 0, s, d.self);
 }
 
 }  // namespace dem
@@ -464,11 +543,7 @@ dem_status ensure_batch(dem_mlp* n, int64_t B) {
   n->part_chunks = nch;
   return DEM_OK;
 }
-int grid_for(int64_t B) {
-  int64_t tiles = (B + 15) / 16;
-  int64_t blocks = (tiles + 3) / 4;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 2048));
-}
+int grid_for(int64_t B) { return mlp_grid(B); }
 // forward + backward + chunk gradients + fixed-order reduction (+ Adam), with
 // the batch buffers tb and the chunk partials `part` given (every location
 // read is written earlier in the same pass: nothing needs clearing)
