@@ -13,7 +13,7 @@ Targets, per CFD cell c and time window w:
            unit solid volume, averaged over the couplings of the window;
   y_coh  = ln( A_fine / (k A_coarse) ),  A = the pull-off forces 3 pi gamma R*
            of the bonded contacts whose contact point lies in c (the adhesion
-           the bonds can hold, Table 1 point B), per unit solid volume, at the
+           the bonds can hold, Table 1 point C), per unit solid volume, at the
            end of the window; k A_coarse is what the coarse-graining law
            (gamma_g = k gamma, section 2.4) predicts for A_fine, so y_coh is
            the law's residual.
@@ -23,10 +23,15 @@ solid (eps_s above a floor) and, for y_coh, bonds.  Every coarse parcel that
 sits in such a cell at the end of the window gets the cell's targets, with its
 closure features of the window's last coupling.
 
-Gain test: produced mass M(t) of the fine run (the truth), of the plain coarse
-run and of the coarse run with the trained closure; the error at the horizon is
-|M_cg - M_fine| / M_fine.  The closure is kept only if its error is not larger
-than the plain coarse model's (else the plain model, c = 1, is the fallback).
+Gain test, on three packings of the same configuration (different seeds, so
+that no judged run shares its grains with the training data): the dataset
+comes from the training pair; on the judging pair the produced mass M(t) of
+the fine run (the truth), of the plain coarse run and of the coarse run with
+the trained closure give the error at the horizon |M_cg - M_fine| / M_fine,
+and the closure is kept only if its error is not larger than the plain coarse
+model's (else the plain model, c = 1, is the fallback); the reporting pair,
+seen by neither step, gives the errors that are reported (with the RMSRE of
+eq 41 over M(t)).
 """
 import math
 import time
@@ -206,7 +211,7 @@ def he_params(seed, scale=1.0):
     return np.concatenate(out).astype(np.float32).astype(np.float64)
 
 
-def train(X, Y, norm, epochs=30, batch=4096, lr=2e-3, seed=0, init_scale=0.5):
+def train_net(X, Y, norm, epochs=30, batch=4096, lr=2e-3, seed=0, init_scale=0.5):
     """Adam on the GPU with the library's BF16 forward/backward kernels over
     shuffled minibatches; returns the network and the loss of every step"""
     net = dem.Mlp(he_params(seed, init_scale))
@@ -239,51 +244,65 @@ def _timed_run(w, steps, closure=None, norm=None):
     return wall, m
 
 
-def gain_test(wf, wc, horizon=20000, window=500, train_frac=0.5, epochs=40, batch=4096, lr=2e-3, seed=0,
+def _mass_series(w, steps, window, closure=None, norm=None):
+    """produced mass at the end of every window of a run from the initial packing"""
+    rec = Recorder(w, make_sim(w, closure, norm))
+    for _ in range(steps // window):
+        rec.run_window(window, keep=False)
+    rec.sim.close()
+    return np.array([m for _, m in rec.mass])
+
+
+def _errors(mf, m):
+    """error at the horizon and RMSRE over the windows where the fine run has produced mass"""
+    e = abs(m[-1] - mf[-1]) / mf[-1] if mf[-1] > 0 else float("nan")
+    ok = mf > 0
+    r = float(np.sqrt(np.mean(((m[ok] - mf[ok]) / mf[ok]) ** 2))) if ok.any() else float("nan")
+    return float(e), r
+
+
+def gain_test(train, judge, report, horizon=20000, window=500, epochs=40, batch=4096, lr=2e-3, seed=0,
               log=None):
-    """Paired fine/coarse runs, dataset, training, and the learned coarse run
-    against the plain one, both judged against the fine run's produced mass."""
+    """train, judge, report: (fine workload, coarse workload) pairs of three
+    packings.  Paired runs of the training pair give the dataset and the
+    network; the judging pair decides keep or fall back; the reporting pair
+    gives the reported errors of the plain and the learned coarse model."""
     say = log or (lambda *a: None)
     nwin = horizon // window
-    ntrain = max(1, int(round(train_frac * nwin)))
+    wf, wc = train
     fine = Recorder(wf, make_sim(wf))
     plain = Recorder(wc, make_sim(wc, zero_network(), np.r_[np.zeros(6), np.ones(6)]), features=True)
-    for k in range(nwin):
-        fine.run_window(window, keep=k < ntrain)
-        plain.run_window(window, keep=k < ntrain)
-    say("paired runs done: %d windows of %d steps, %d used for training" % (nwin, window, ntrain))
+    for _ in range(nwin):
+        fine.run_window(window)
+        plain.run_window(window)
+    fine.sim.close()
+    plain.sim.close()
     X, Y = build_dataset(fine, plain)
     norm = normaliser(X)
-    net, losses = train(X, Y, norm, epochs=epochs, batch=batch, lr=lr, seed=seed)
-    say("trained on %d samples, loss %.4g -> %.4g" % (len(X), losses[0], losses[-1]))
-    learned = Recorder(wc, make_sim(wc, net, norm))
-    for k in range(nwin):
-        learned.run_window(window, keep=False)
-    mf = np.array([m for _, m in fine.mass])
-    mp = np.array([m for _, m in plain.mass])
-    ml = np.array([m for _, m in learned.mass])
-
-    def err(m):
-        return abs(m[-1] - mf[-1]) / mf[-1] if mf[-1] > 0 else float("nan")
-
-    def rmsre(m):
-        ok = mf > 0
-        return float(np.sqrt(np.mean(((m[ok] - mf[ok]) / mf[ok]) ** 2))) if ok.any() else float("nan")
-
-    e_plain, e_learned = err(mp), err(ml)
-    accepted = bool(e_learned <= e_plain)
-    wall_fine, _ = _timed_run(wf, horizon)
-    wall_cg, _ = _timed_run(wc, horizon, net if accepted else None, norm if accepted else None)
-    say("errors at the horizon: plain %.4f learned %.4f" % (e_plain, e_learned))
-    return {
-        "n_fine": int(len(wf["r"])), "n_coarse": int(len(wc["r"])), "k": float(wc.get("k", 1.0)),
-        "scheme": wc.get("scheme", "ssw"), "horizon_steps": int(horizon), "window_steps": int(window),
-        "train_windows": int(ntrain), "train_samples": int(len(X)),
-        "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
-        "mass_fine": float(mf[-1]), "mass_plain_cg": float(mp[-1]), "mass_learned_cg": float(ml[-1]),
-        "err_plain_cg": float(e_plain), "err_learned_cg": float(e_learned),
-        "rmsre_plain_cg": rmsre(mp), "rmsre_learned_cg": rmsre(ml),
-        "closure_accepted": accepted,
-        "wall_fine_s": wall_fine, "wall_cg_s": wall_cg, "speedup_vs_fine": wall_fine / wall_cg,
-        "net": net, "norm": norm, "mass_series": {"fine": mf, "plain": mp, "learned": ml},
-    }
+    net, losses = train_net(X, Y, norm, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    say("trained on %d samples of %d windows, loss %.4g -> %.4g" % (len(X), nwin, losses[0], losses[-1]))
+    out = {"n_fine": int(len(wf["r"])), "n_coarse": int(len(wc["r"])), "k": float(wc.get("k", 1.0)),
+           "scheme": wc.get("scheme", "ssw"), "horizon_steps": int(horizon), "window_steps": int(window),
+           "train_samples": int(len(X)), "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+           "packings": {"train": wf["name"], "judge": judge[0]["name"], "report": report[0]["name"]}}
+    for role, (f, c) in (("judge", judge), ("report", report)):
+        mf = _mass_series(f, horizon, window)
+        mp = _mass_series(c, horizon, window)
+        ml = _mass_series(c, horizon, window, net, norm)
+        ep, rp = _errors(mf, mp)
+        el, rl = _errors(mf, ml)
+        out[role] = {"mass_fine": float(mf[-1]), "mass_plain_cg": float(mp[-1]), "mass_learned_cg": float(ml[-1]),
+                     "err_plain_cg": ep, "err_learned_cg": el, "rmsre_plain_cg": rp, "rmsre_learned_cg": rl,
+                     "mass_series": {"fine": mf, "plain": mp, "learned": ml}}
+        say("%s packing: error plain %.4f learned %.4f, RMSRE plain %.4f learned %.4f" % (role, ep, el, rp, rl))
+    accepted = bool(out["judge"]["err_learned_cg"] <= out["judge"]["err_plain_cg"])
+    out["closure_accepted"] = accepted
+    rf, rc = report
+    wall_fine, _ = _timed_run(rf, horizon)
+    wall_cg, _ = _timed_run(rc, horizon, net if accepted else None, norm if accepted else None)
+    out.update(wall_fine_s=wall_fine, wall_cg_s=wall_cg, speedup_vs_fine=wall_fine / wall_cg, net=net, norm=norm)
+    # the model the rule keeps, on the reporting packing
+    r = out["report"]
+    out["err_kept_cg"] = r["err_learned_cg"] if accepted else r["err_plain_cg"]
+    out["rmsre_kept_cg"] = r["rmsre_learned_cg"] if accepted else r["rmsre_plain_cg"]
+    return out

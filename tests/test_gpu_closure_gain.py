@@ -1,11 +1,14 @@
 """What the trained closure gains over the plain coarse-grained model (an
-extension; not in arXiv:2211.06142): paired fine (200 000 grains) and coarse
-(k = 2, SSW) runs of the cylinder, the dataset from them, training on the GPU,
-and the produced mass of the plain and of the learned coarse model against
-the fine run.  The closure is kept only when it is not worse than the plain
-model (the fallback); the test checks that this rule is applied, that the
-training lowers its loss, and that the coarse model (whichever is kept) is
-faster than the fine one."""
+extension; not in arXiv:2211.06142), measured out of sample: three packings of
+the cylinder (seeds 0, 1, 2; 200 000 grains fine, k = 2 SSW coarse).  The
+closure is trained on the paired runs of seed 0, kept or dropped on seed 1
+(kept only when it is not worse than the plain model), and both coarse models
+are judged against the fine run on seed 2, which neither step saw.  The test
+checks that the training lowers its loss, that the keep rule is applied on the
+judging packing, that the reported error is the kept model's on the reporting
+packing, and that the kept coarse model is faster than the fine one.  It does
+not assert that the closure beats the plain model out of sample: at this
+horizon it is not shown to (the measured errors are printed)."""
 import math
 
 import numpy as np
@@ -22,18 +25,24 @@ if not torch.cuda.is_available():
 from paper_2211_06142_amd import closure_train as ct  # noqa: E402
 
 
-def test_closure_gain_k2():
-    res = ct.gain_test(synth.c1(), synth.c2(2), horizon=6000, window=500, epochs=10,
-                       log=lambda *a: print(*a, flush=True))
-    print({k: v for k, v in res.items() if k not in ("net", "norm", "mass_series")})
+def test_closure_gain_k2_out_of_sample():
+    pairs = [(synth.c1(seed=s), synth.c2(2, seed=s)) for s in (0, 1, 2)]
+    names = [p[0]["name"] for p in pairs]
+    assert len(set(names)) == 3   # three different packings
+    res = ct.gain_test(*pairs, horizon=6000, window=500, epochs=10, log=lambda *a: print(*a, flush=True))
+    print({k: v for k, v in res.items() if k not in ("net", "norm", "judge", "report")})
+    for role in ("judge", "report"):
+        print(role, {k: v for k, v in res[role].items() if k != "mass_series"})
     assert res["train_samples"] > 10000
     assert res["loss_last"] < res["loss_first"]
-    assert res["mass_fine"] > 0.0
-    for k in ("err_plain_cg", "err_learned_cg"):
-        assert math.isfinite(res[k])
-    assert res["closure_accepted"] == (res["err_learned_cg"] <= res["err_plain_cg"])
-    kept = res["err_learned_cg"] if res["closure_accepted"] else res["err_plain_cg"]
-    assert kept == min(res["err_learned_cg"], res["err_plain_cg"])
+    j, r = res["judge"], res["report"]
+    assert j["mass_fine"] > 0.0 and r["mass_fine"] > 0.0
+    for d in (j, r):
+        for k in ("err_plain_cg", "err_learned_cg", "rmsre_plain_cg", "rmsre_learned_cg"):
+            assert math.isfinite(d[k])
+    assert res["closure_accepted"] == (j["err_learned_cg"] <= j["err_plain_cg"])
+    assert res["err_kept_cg"] == (r["err_learned_cg"] if res["closure_accepted"] else r["err_plain_cg"])
     assert res["speedup_vs_fine"] > 1.0
-    m = res["mass_series"]
-    assert np.all(np.diff(m["fine"]) >= 0.0) and np.all(np.diff(m["plain"]) >= 0.0)
+    for d in (j, r):
+        m = d["mass_series"]
+        assert np.all(np.diff(m["fine"]) >= 0.0) and np.all(np.diff(m["plain"]) >= 0.0)
