@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # neighbour skin / smallest radius: c1 tuned over its 5 000-step run (the cavity face erodes and
 # particles speed up, so a wider skin pays); the boxes keep the library default
-SKIN_FACTOR = {"c1": 1.2, "c0": 0.4, "c3": 0.4, "c3k": 0.4}
+SKIN_FACTOR = {"c1": 1.2, "c0": 0.4, "c3": 0.4, "c3k": 0.4, "f2": 0.4}
 LANES = 2           # lanes per particle of the row gather (the library default in half-pair mode)
 
 
@@ -246,6 +246,36 @@ def learned_cg_block(horizon, ks=(2, 3), c4=False):
     return out
 
 
+def f2_fluid_setup(sim, w, u_inject=1e-4):
+    """The paper's fluid run (section 3.1) on the f2 box: one coupling
+    evaluation, then model A's pressure solve with the paper's boundary
+    conditions (injection through the faces normal to y, top and bottom holes
+    at the reference pressure); the equation is linear in the pressure, so the
+    injection pressure is scaled to give the paper's injection velocity
+    1e-4 m/s (superficial, mean over the open cells next to the injection
+    face) and solved again; the fields go to the coupling."""
+    import synth
+    import torch
+    sim.step(w["fluid"]["couple_every"])
+    kind, pf = synth.f2_cell_kinds(w, 1.0)
+    lo, hi, nn = w["grid"]
+    nx, ny, nz = nn
+    layer = np.zeros(nx * ny * nz, bool)
+    for iz in range(nz):
+        for ix in range(nx):
+            layer[(iz * ny + 1) * nx + ix] = True
+    layer &= kind == 0
+    _, U, _, _, _ = sim.fluid_solve(kind, pf, max_iter=5000, rel_tol=1e-10)
+    scale = u_inject / float(U[layer, 1].mean())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p, U, GP, it, rr = sim.fluid_solve(kind, pf * scale, max_iter=5000, rel_tol=1e-10)
+    ms = (time.perf_counter() - t0) * 1e3
+    sim.map_fluid(U, GP)
+    return {"p_inject_pa": scale, "u_inject": float(U[layer, 1].mean()), "solve_iterations": it,
+            "solve_rel_residual": rr, "solve_ms": ms, "p_max_pa": float(p.max())}
+
+
 def calibrate_pmc(gib=2):
     """Known traffic for the HBM counters: three device copies of a buffer of
     `gib` GiB (far beyond the 256 MB Infinity Cache, so every byte crosses HBM:
@@ -292,8 +322,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c0", "c3", "c3k"],
-                    help="c3k: the ensemble with per-sample coarse-graining k = 1, 2, 3")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c0", "c3", "c3k", "f2"],
+                    help="c3k: the ensemble with per-sample coarse-graining k = 1, 2, 3; f2: the paper's own "
+                    "setting (18 x 18 x 9 mm box, Table 2 sand, Table 3 material, dt 1e-8 s, top outlet)")
+    ap.add_argument("--f2-k", type=int, default=1, help="coarse-graining factor of the f2 run (1 or 2, SSW)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of oracle stepping (cpu_baseline)")
     ap.add_argument("--skin-factor", type=float, default=None,
@@ -328,6 +360,8 @@ def main():
 
     if args.workload == "c1":
         ws = [synth.c1()]
+    elif args.workload == "f2":
+        ws = [synth.f2(args.f2_k)]
     elif args.workload == "c0":
         ws = [synth.c0()]
     else:
@@ -344,6 +378,7 @@ def main():
         args.skin_factor, args.lanes = best["skin"] / rmin, best["lanes"]
         tuned = {"skin_factor": args.skin_factor, "lanes": args.lanes, "trials": table}
     sim = build_sim(ws, args.skin_factor, args.lanes, args.graphs, args.pair_mode)
+    f2_fluid = f2_fluid_setup(sim, w) if args.workload == "f2" else None
     n_total = sum(len(x["r"]) for x in ws)
     print("bench: %s set up, %d particles in %d sample(s)" % (args.workload, n_total, len(ws)), file=sys.stderr,
           flush=True)
@@ -407,6 +442,13 @@ def main():
                 "grains each, surface energy 0.1-1.0 J/m^2, own walls and 8-16^3 fluid grid), %d spheres and "
                 "parcels in total, dt 1e-7 s, coupling every %d steps" % (len(ws), n_total, w["fluid"]["couple_every"]))
         metric = "particle-steps/s, batched ensemble of 256 samples with k = 1, 2, 3, 1 GPU"
+    elif args.workload == "f2":
+        desc = ("f2: the paper's setting after perforation, %d %s (Table 2 sand%s, Table 3 material) in an 18 x 18 x 9 mm "
+                "box with a 1.7 mm perforation tunnel and a 2.6 mm outlet hole in the top plate, 12x12x6 fluid grid, "
+                "injection 1e-4 m/s through the faces normal to y (model A pressure solve), dt 1e-8 s, coupling every "
+                "%d steps" % (len(w["r"]), "grains" if w["k"] == 1 else "SSW parcels",
+                              "" if w["k"] == 1 else ", k = %g" % w["k"], w["fluid"]["couple_every"]))
+        metric = "particle-steps/s at %d particles (paper setting), 1 GPU" % len(w["r"])
     elif args.workload == "c0":
         desc = ("c0: %d spheres settled in a 3 mm box (six walls), 8^3 fluid grid, uniform upward flow, FP64, "
                 "dt 1e-7 s, coupling every %d steps" % (len(w["r"]), w["fluid"]["couple_every"]))
@@ -441,6 +483,8 @@ def main():
     }
     if tuned:
         out["config"]["tuned"] = tuned
+    if f2_fluid:
+        out["config"]["fluid_solve"] = f2_fluid
     if not args.no_closure and len(ws) == 1:
         out["closure"] = closure_block(w, torch)
     sim.close()

@@ -57,7 +57,7 @@ typedef enum {
 
 #define DEM_MAX_WALLS 8
 
-enum { DEM_WALL_PLANE = 0, DEM_WALL_CYL_IN = 1, DEM_WALL_CYL_OUT = 2 };
+enum { DEM_WALL_PLANE = 0, DEM_WALL_CYL_IN = 1, DEM_WALL_CYL_OUT = 2, DEM_WALL_PLANE_HOLE = 3 };
 /* Normal laws.  JKR_MOD: the modified JKR model of section 2.3 (Fig. 2), bonds
  * set at init (bond_at_init or the given history) break at point C and never
  * re-form, other contacts are Hertz.  HERTZ: no cohesion.  LINEAR: eq 3, a test
@@ -69,7 +69,12 @@ enum { DEM_WALL_PLANE = 0, DEM_WALL_CYL_IN = 1, DEM_WALL_CYL_OUT = 2 };
  * touch. */
 enum { DEM_NORMAL_JKR_MOD = 0, DEM_NORMAL_HERTZ = 1, DEM_NORMAL_LINEAR = 2, DEM_NORMAL_JKR_ORIG = 3 };
 enum { DEM_VOID_CIC = 0, DEM_VOID_CENTROID = 1 };
-enum { DEM_OUTLET_NONE = 0, DEM_OUTLET_CAVITY = 1 };
+/* Outlets (section 3.3 eq 40: a particle that leaves is produced sand).  CAVITY:
+ * a centre inside the vertical cylinder outlet[0..1] axis, outlet[2] radius
+ * leaves (the workloads' cavity).  ABOVE: a centre above the level z =
+ * outlet[3] leaves (the paper's outlet on the top face of its box, with a
+ * PLANE_HOLE wall as the top plate: the only way up is through the hole). */
+enum { DEM_OUTLET_NONE = 0, DEM_OUTLET_CAVITY = 1, DEM_OUTLET_ABOVE = 2 };
 enum { DEM_PREC_FP64 = 0, DEM_PREC_MIXED = 1 };
 enum { DEM_CG_SSW = 0, DEM_CG_SSP = 1 };
 enum { DEM_FLAG_AUTO_REGROW = 1u };
@@ -78,9 +83,13 @@ enum { DEM_FLAG_AUTO_REGROW = 1u };
 /* A wall.  PLANE: p[0..2] unit normal pointing into the particle side, p[3]
  * offset (signed distance of a point x is n.x - p[3]).  CYL_IN: particles
  * inside a z-axis cylinder, p[0], p[1] axis position, p[2] radius.  CYL_OUT:
- * particles outside such a cylinder.  Walls are rigid, static, of the
- * particles' material; contact with them is Hertz with tangential history
- * (the particle-wall law of section 3.1). */
+ * particles outside such a cylinder.  PLANE_HOLE: the horizontal plane
+ * z = p[2] with particles on the side p[3] (+1 above, -1 below) and a circular
+ * hole of radius p[4] about the vertical axis through (p[0], p[1]): a particle
+ * whose centre lies within the hole radius of that axis does not touch the
+ * plane (the outlet in the top face of the paper's box, section 3.1).  Walls
+ * are rigid, static, of the particles' material; contact with them is Hertz
+ * with tangential history (the particle-wall law of section 3.1). */
 typedef struct {
   int32_t kind;
   int32_t reserved;
@@ -120,7 +129,7 @@ typedef struct {
   double dt_rayleigh_max_frac; /* > 0: reject dt above this fraction of eq 37       */
   int32_t outlet_kind;      /* DEM_OUTLET_*                                         */
   int32_t n_walls;          /* <= DEM_MAX_WALLS                                     */
-  double outlet[4];         /* CAVITY: axis x, axis y, radius; centres inside leave */
+  double outlet[4];         /* CAVITY: axis x, axis y, radius; ABOVE: [3] the level */
   dem_wall walls[DEM_MAX_WALLS];
   int32_t precision;        /* DEM_PREC_FP64 or DEM_PREC_MIXED (same for all samples) */
   int32_t bond_at_init;     /* 1: every touching pair starts bonded (JKR_MOD, ORIG) */

@@ -23,10 +23,10 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "dem_oracle.c")
 
 MAX_WALLS = 8
-WALL_PLANE, WALL_CYL_IN, WALL_CYL_OUT = 0, 1, 2
+WALL_PLANE, WALL_CYL_IN, WALL_CYL_OUT, WALL_PLANE_HOLE = 0, 1, 2, 3
 NORMAL_JKR_MOD, NORMAL_HERTZ, NORMAL_LINEAR, NORMAL_JKR_ORIG = 0, 1, 2, 3
 VOID_CIC, VOID_CENTROID = 0, 1
-OUTLET_NONE, OUTLET_CAVITY = 0, 1
+OUTLET_NONE, OUTLET_CAVITY, OUTLET_ABOVE = 0, 1, 2
 
 
 def build(force=True):
@@ -223,7 +223,7 @@ def make_params(mat, dt, g=(0.0, 0.0, -9.81), walls=(), grid=None, fluid=None, o
     walls: sequence of (kind, params[<=6])
     grid: (lo[3], hi[3], n[3]) or None
     fluid: dict rho_f, mu_f, n_min, voidfrac, u_superficial, couple_every or None
-    outlet: (x, y, radius) cavity or None
+    outlet: (x, y, radius) cavity, {"above": z} (centres above z leave) or None
     """
     p = OrParams()
     p.rho, p.E, p.nu, p.e = mat["rho"], mat["E"], mat["nu"], mat["e"]
@@ -256,7 +256,10 @@ def make_params(mat, dt, g=(0.0, 0.0, -9.81), walls=(), grid=None, fluid=None, o
     else:
         p.fluid_on = 0
         p.couple_every = 1
-    if outlet is not None:
+    if isinstance(outlet, dict):
+        p.outlet_kind = OUTLET_ABOVE
+        p.outlet[3] = outlet["above"]
+    elif outlet is not None:
         p.outlet_kind = OUTLET_CAVITY
         for c in range(3):
             p.outlet[c] = outlet[c]

@@ -752,6 +752,13 @@ static int wall_geom(const or_wall* wl, const double* x, double* sd, double* nw)
     *sd = dot3(nw, x) - wl->p[3];
     return 1;
   }
+  if (wl->kind == OR_WALL_PLANE_HOLE) {
+    double hx = x[0] - wl->p[0], hy = x[1] - wl->p[1];
+    if (hx * hx + hy * hy < wl->p[4] * wl->p[4]) return 0;   /* over the hole: no plane */
+    nw[0] = 0.0; nw[1] = 0.0; nw[2] = wl->p[3];
+    *sd = wl->p[3] * (x[2] - wl->p[2]);
+    return 1;
+  }
   double ex = x[0] - wl->p[0], ey = x[1] - wl->p[1];
   double rho = sqrt(ex * ex + ey * ey);
   if (rho == 0.0) return 0;
@@ -784,14 +791,16 @@ static void one_step(or_sim* s) {
     for (int c = 0; c < 3; ++c) s->x[3 * i + c] += dt * s->v[3 * i + c];
   }
 
-  /* 2. outlet: a centre inside the cavity leaves the sample as produced sand */
+  /* 2. outlet: a centre inside the cavity (or above the outlet level) leaves
+   *    the sample as produced sand */
   int removed = 0;
-  if (p->outlet_kind == OR_OUTLET_CAVITY) {
+  if (p->outlet_kind == OR_OUTLET_CAVITY || p->outlet_kind == OR_OUTLET_ABOVE) {
     double rc = p->outlet[2];
     for (int64_t i = 0; i < n; ++i) {
       if (!s->alive[i]) continue;
       double ex = s->x[3 * i + 0] - p->outlet[0], ey = s->x[3 * i + 1] - p->outlet[1];
-      if (ex * ex + ey * ey < rc * rc) {
+      int leaves = p->outlet_kind == OR_OUTLET_CAVITY ? ex * ex + ey * ey < rc * rc : s->x[3 * i + 2] > p->outlet[3];
+      if (leaves) {
         s->alive[i] = 0;
         s->produced += s->m[i];
         for (int c = 0; c < 3; ++c) { s->F[3 * i + c] = 0.0; s->T[3 * i + c] = 0.0; }

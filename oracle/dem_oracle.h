@@ -22,19 +22,25 @@
 
 #define OR_MAX_WALLS 8
 
-enum { OR_WALL_PLANE = 0, OR_WALL_CYL_IN = 1, OR_WALL_CYL_OUT = 2 };
+enum { OR_WALL_PLANE = 0, OR_WALL_CYL_IN = 1, OR_WALL_CYL_OUT = 2, OR_WALL_PLANE_HOLE = 3 };
 /* JKR_ORIG: the original JKR cycle of section 2.3 (Fig. 1): a contact snaps in
  * on touch (point A), follows eq 12-13 through C and separates at S, and may
  * form again on a later touch */
 enum { OR_NORMAL_JKR_MOD = 0, OR_NORMAL_HERTZ = 1, OR_NORMAL_LINEAR = 2, OR_NORMAL_JKR_ORIG = 3 };
 enum { OR_VOID_CIC = 0, OR_VOID_CENTROID = 1 };
-enum { OR_OUTLET_NONE = 0, OR_OUTLET_CAVITY = 1 };
+/* CAVITY: centres inside the vertical cylinder outlet[0..1], radius outlet[2]
+ * leave; ABOVE: centres above z = outlet[3] leave (the top outlet of the
+ * paper's box, section 3.1) */
+enum { OR_OUTLET_NONE = 0, OR_OUTLET_CAVITY = 1, OR_OUTLET_ABOVE = 2 };
 
 typedef struct {
   int kind;
   /* plane   : p[0..2] inward unit normal, p[3] offset  (signed distance = n.x - p[3])
    * cyl_in  : particles inside a z-axis cylinder, p[0],p[1] axis (x,y), p[2] radius
-   * cyl_out : particles outside a z-axis cylinder, same layout                       */
+   * cyl_out : particles outside a z-axis cylinder, same layout
+   * plane_hole: the plane z = p[2], particles on the side p[3] (+1 above, -1 below),
+   *           with a hole of radius p[4] about the vertical axis through (p[0], p[1]):
+   *           a centre within the hole radius of that axis does not touch it        */
   double p[6];
 } or_wall;
 

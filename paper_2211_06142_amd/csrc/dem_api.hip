@@ -166,8 +166,15 @@ dem_status validate(const dem_params& p) {
     if (p.couple_every < 1) return DEM_E_INVAL;
     if (p.voidfrac != DEM_VOID_CIC && p.voidfrac != DEM_VOID_CENTROID) return DEM_E_INVAL;
   }
-  for (int w = 0; w < p.n_walls; ++w)
-    if (p.walls[w].kind < 0 || p.walls[w].kind > 2) return DEM_E_INVAL;
+  for (int w = 0; w < p.n_walls; ++w) {
+    const dem_wall& wl = p.walls[w];
+    if (wl.kind < 0 || wl.kind > DEM_WALL_PLANE_HOLE) return DEM_E_INVAL;
+    if (wl.kind == DEM_WALL_PLANE_HOLE && ((wl.p[3] != 1.0 && wl.p[3] != -1.0) || !(wl.p[4] > 0.0)))
+      return DEM_E_INVAL;
+  }
+  if (p.outlet_kind < DEM_OUTLET_NONE || p.outlet_kind > DEM_OUTLET_ABOVE) return DEM_E_INVAL;
+  if (p.outlet_kind == DEM_OUTLET_CAVITY && !(p.outlet[2] > 0.0)) return DEM_E_INVAL;
+  if (p.outlet_kind == DEM_OUTLET_ABOVE && !std::isfinite(p.outlet[3])) return DEM_E_INVAL;
   return DEM_OK;
 }
 

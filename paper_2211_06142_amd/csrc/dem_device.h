@@ -120,11 +120,20 @@ __device__ inline int bin_coord(double x, double lo, double h, int n) {
 
 // signed distance from the wall surface (positive on the particle side) and
 // the unit normal pointing into the particle side
-__device__ inline bool wall_geom(const Wall& w, double x, double y, double z, double& sd, double nw[3]) {
+// (search: the candidate search of a rebuild, which ignores a plane's hole,
+// since a particle may move out of the hole before the next rebuild)
+__device__ inline bool wall_geom(const Wall& w, double x, double y, double z, double& sd, double nw[3],
+                                 bool search = false) {
   if (w.kind == DEM_WALL_PLANE) {
     nw[0] = w.p[0]; nw[1] = w.p[1]; nw[2] = w.p[2];
     sd = ((nw[0] * x + nw[1] * y) + nw[2] * z) - w.p[3];
     return true;
+  }
+  if (w.kind == DEM_WALL_PLANE_HOLE) {
+    nw[0] = 0.0; nw[1] = 0.0; nw[2] = w.p[3];
+    sd = w.p[3] * (z - w.p[2]);
+    const double ex = x - w.p[0], ey = y - w.p[1];
+    return search || !(ex * ex + ey * ey < w.p[4] * w.p[4]);
   }
   double ex = x - w.p[0], ey = y - w.p[1];
   double rho = sqrt(ex * ex + ey * ey);

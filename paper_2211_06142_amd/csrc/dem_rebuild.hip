@@ -399,7 +399,7 @@ __global__ void k_wall_search(DevState d) {
     int row = kFill ? d.wrow[i] : 0;
     for (int w = 0; w < c.n_walls; ++w) {
       double sd, nw[3];
-      if (wall_geom(c.walls[w], p.x, p.y, p.z, sd, nw) && sd < p.w + c.skin) {
+      if (wall_geom(c.walls[w], p.x, p.y, p.z, sd, nw, true) && sd < p.w + c.skin) {
         if (kFill) d.wid[row + cnt] = w;
         ++cnt;
       }

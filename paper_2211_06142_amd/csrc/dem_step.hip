@@ -46,15 +46,19 @@ __device__ inline void finish_drift(const DevState& d, const SampleConst& c, int
   gst(G(d.vel[out]) + i, v);
   gst(G((R4<R>*)d.omg[out]) + i, w);
   uint8_t alive = 1;
+  bool leaves = false;
   if (c.outlet_kind == DEM_OUTLET_CAVITY) {
     double ex = p.x - c.outlet[0], ey = p.y - c.outlet[1];
     double rc = c.outlet[2];
-    if (ex * ex + ey * ey < rc * rc) {
-      alive = 0;
-      count_removal(d, c, s, p.w);
-      gst(G((R4<R>*)d.frc) + i, mk4<R>(0, 0, 0, 0));
-      gst(G((R4<R>*)d.trq) + i, mk4<R>(0, 0, 0, 0));
-    }
+    leaves = ex * ex + ey * ey < rc * rc;
+  } else if (c.outlet_kind == DEM_OUTLET_ABOVE) {
+    leaves = p.z > c.outlet[3];
+  }
+  if (leaves) {
+    alive = 0;
+    count_removal(d, c, s, p.w);
+    gst(G((R4<R>*)d.frc) + i, mk4<R>(0, 0, 0, 0));
+    gst(G((R4<R>*)d.trq) + i, mk4<R>(0, 0, 0, 0));
   }
   G(d.alive[out])[i] = alive;
   if (alive) {

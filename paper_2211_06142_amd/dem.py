@@ -15,10 +15,10 @@ LIB_PATH = os.path.join(HERE, "libdem.so")
 
 DEM_OK, DEM_E_INVAL, DEM_E_NOMEM, DEM_E_CAPACITY, DEM_E_NONFINITE, DEM_E_DEVICE, DEM_E_STATE = 0, -1, -2, -3, -4, -5, -6
 DEM_MAX_WALLS = 8
-DEM_WALL_PLANE, DEM_WALL_CYL_IN, DEM_WALL_CYL_OUT = 0, 1, 2
+DEM_WALL_PLANE, DEM_WALL_CYL_IN, DEM_WALL_CYL_OUT, DEM_WALL_PLANE_HOLE = 0, 1, 2, 3
 DEM_NORMAL_JKR_MOD, DEM_NORMAL_HERTZ, DEM_NORMAL_LINEAR, DEM_NORMAL_JKR_ORIG = 0, 1, 2, 3
 DEM_VOID_CIC, DEM_VOID_CENTROID = 0, 1
-DEM_OUTLET_NONE, DEM_OUTLET_CAVITY = 0, 1
+DEM_OUTLET_NONE, DEM_OUTLET_CAVITY, DEM_OUTLET_ABOVE = 0, 1, 2
 DEM_PREC_FP64, DEM_PREC_MIXED = 0, 1
 DEM_CG_SSW, DEM_CG_SSP = 0, 1
 DEM_FLAG_AUTO_REGROW = 1
@@ -432,7 +432,10 @@ def make_params(material, dt, k=1.0, scheme="ssw", g=(0.0, 0.0, -9.81), walls=()
             p.grid.lo[c], p.grid.hi[c], p.grid.n[c] = lo[c], hi[c], nn[c]
     else:
         p.couple_every = 1
-    if outlet is not None:
+    if isinstance(outlet, dict):   # {"above": z}: centres above z leave
+        p.outlet_kind = DEM_OUTLET_ABOVE
+        p.outlet[3] = outlet["above"]
+    elif outlet is not None:       # (x, y, radius): the cavity
         p.outlet_kind = DEM_OUTLET_CAVITY
         for c in range(3):
             p.outlet[c] = outlet[c]

@@ -38,7 +38,7 @@ COUPLE_EVERY = 10                                 # CFD step 1e-6 s (section 3.1
 N_MIN = 0.3
 GRAV = (0.0, 0.0, -9.81)
 
-WALL_PLANE, WALL_CYL_IN, WALL_CYL_OUT = 0, 1, 2
+WALL_PLANE, WALL_CYL_IN, WALL_CYL_OUT, WALL_PLANE_HOLE = 0, 1, 2, 3
 
 
 def build(force=True):
@@ -378,6 +378,129 @@ def c3(n_samples=256, seed=SEED0 + 3, k_sweep=False):
         k = 1 + s % 3
         out.append(c3_crop(s, max(60, int(round(ns[s] / k ** 3))), float(gam[s]), bases[k]))
     return out
+
+
+# The paper's own setting (section 3.1): Table 2, mass fraction of each of the
+# eight diameters (mm) of the original particles; Table 3, the sand's material
+# (fine scale); the time step and the coupling interval of that run.
+TABLE2 = [(0.058, 0.15), (0.075, 0.18), (0.088, 0.20), (0.1216, 0.22), (0.2264, 0.25), (0.1705, 0.275),
+          (0.121, 0.30), (0.1395, 0.355)]
+PAPER_MATERIAL = dict(rho=2605.0, E=2.0e10, nu=0.3, e=0.8, mu=0.2, mu_roll=0.0, gamma=30.0)
+PAPER_DT = 1.0e-8
+PAPER_COUPLE_EVERY = 100                            # CFD step 1e-6 s / DEM 1e-8 s
+
+
+def table2_diameters(rng, n):
+    """n diameters from the eight classes of Table 2, drawn with probabilities
+    in proportion to mass fraction / d^3 (the number fraction of each class)."""
+    w = np.array([m for m, _ in TABLE2])
+    d = np.array([dd for _, dd in TABLE2]) * 1e-3
+    p = w / d ** 3
+    return d[rng.choice(d.size, size=n, p=p / p.sum())]
+
+
+def table2_mean_diameter():
+    """the mass-equivalent mean diameter of Table 2, (sum w / sum w / d^3)^(1/3)"""
+    w = np.array([m for m, _ in TABLE2])
+    d = np.array([dd for _, dd in TABLE2]) * 1e-3
+    return float(np.cbrt(w.sum() / np.sum(w / d ** 3)))
+
+
+def f2(k=1, scheme="ssw", n_fine=250000, seed=0):
+    """The paper's own setting (section 3.1) after its perforation stage: an
+    18 x 18 mm box of height 9 mm, sand of Table 2 (k = 1: n_fine grains; k > 1:
+    SSW parcels k times each sampled diameter, or SSP parcels of k times the
+    mean diameter, n_fine / k^3 of them) and Table 3, dt 1e-8 s, a 12 x 12 x 6
+    grid of 1.5 mm cells, a top plate with the 2.6 mm outlet hole over the
+    centre (outlet: centres above the plate's level), and the perforation, a
+    vertical tunnel of 1.7 mm diameter through the whole height under the
+    hole.  Stand-ins for the paper's stages: the grains are settled
+    geometrically (no generation with the original JKR law, no 1 MPa
+    compression, so the porosity is that of the geometric packing, not 41 %),
+    and the tunnel is carved (the grains whose centres lie within it are
+    removed) instead of pushed open by the penetrometer.  The fluid fields
+    start at rest; the run's own pressure solve (model A, dem_fluid_solve with
+    f2_cell_kinds) gives them."""
+    L, H = 18e-3, 9e-3
+    cx = cy = 0.5 * L
+    r_perf, r_hole = 0.85e-3, 1.3e-3
+    n = int(round(n_fine / k ** 3))
+    rng = np.random.default_rng(SEED0 + 5 + 10 * int(k) + (1 if scheme == "ssp" else 0) + 100 * seed)
+    name = "f2_k%d_%s_n%d_s%d" % (k, scheme, n_fine, seed)
+
+    def make():
+        if scheme == "ssp" and k > 1:
+            d = np.full(n, k * table2_mean_diameter())
+        else:
+            d = k * table2_diameters(rng, n)
+        r = 0.5 * d
+        x, worst = settle(r, 0, (0.0, 0.0, 0.0, L, L, 2.0 * H), rng, parallel=True, relax=0.7)
+        keep = (x[:, 2] + r <= H) & (np.hypot(x[:, 0] - cx, x[:, 1] - cy) >= r_perf)
+        return {"x": x[keep], "r": r[keep], "worst": np.array(worst)}
+
+    pk = cached(name, make)
+    walls = [(WALL_PLANE, (1.0, 0.0, 0.0, 0.0)), (WALL_PLANE, (-1.0, 0.0, 0.0, -L)),
+             (WALL_PLANE, (0.0, 1.0, 0.0, 0.0)), (WALL_PLANE, (0.0, -1.0, 0.0, -L)),
+             (WALL_PLANE, (0.0, 0.0, 1.0, 0.0)), (WALL_PLANE_HOLE, (cx, cy, H, -1.0, r_hole))]
+    grid = ((0.0, 0.0, 0.0), (L, L, H), (12, 12, 6))
+    ncell = 12 * 12 * 6
+    mat = dict(PAPER_MATERIAL)
+    return dict(name=name, x=pk["x"], r=pk["r"], material=mat, k=float(k), scheme=scheme, walls=walls,
+                grid=grid, u_cell=np.zeros((ncell, 3)), gradp_cell=np.zeros((ncell, 3)),
+                fluid=dict(WATER, n_min=N_MIN, voidfrac=0, u_superficial=1, couple_every=PAPER_COUPLE_EVERY),
+                outlet={"above": H}, dt=PAPER_DT, g=GRAV, sha256=str(pk["sha256"]), precision="mixed",
+                n_fine=n_fine, hole=(cx, cy, r_hole), steps=4000000)
+
+
+def f2_cell_kinds(w, p_in=1.0):
+    """Boundary conditions of the paper's fluid run (section 3.1) as cell kinds
+    of the pressure solve: the layers of cells next to the two faces normal to
+    y take the injection pressure p_in, the cells under the top and over the
+    bottom hole (centres within the hole radius of the axis) are outlets at the
+    reference pressure (dynamic pressure 0); every other cell is open and the
+    remaining faces carry no flow.  Returns (kind, p_fixed)."""
+    (lo, hi, nn) = w["grid"]
+    nx, ny, nz = nn
+    h = [(hi[c] - lo[c]) / nn[c] for c in range(3)]
+    cx, cy, rh = w["hole"]
+    kind = np.zeros(nx * ny * nz, np.int8)
+    p = np.zeros(nx * ny * nz)
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                c = (iz * ny + iy) * nx + ix
+                xc, yc = lo[0] + (ix + 0.5) * h[0], lo[1] + (iy + 0.5) * h[1]
+                if (iz == 0 or iz == nz - 1) and math.hypot(xc - cx, yc - cy) < rh:
+                    kind[c] = 1
+                elif iy == 0 or iy == ny - 1:
+                    kind[c], p[c] = 1, p_in
+    return kind, p
+
+
+def hole_box(v_up=2.0, r_hole=0.6e-3, depth=0.25e-3, precision="fp64"):
+    """c0's settled spheres under a top plate with a hole over the centre
+    (PLANE_HOLE a depth below the bed top) and the outlet at the plate's level,
+    without cohesion: the spheres that would cut the plate outside the hole are
+    left out, the column under the hole stands above the plate's level (its
+    centres above it leave at the first step) and starts upwards at v_up, so
+    spheres keep crossing the level and leaving while their neighbours are
+    pushed against the plate (the parity runs of the paper's top outlet)."""
+    base = c0()
+    x, r = base["x"], base["r"]
+    side = 3.0e-3
+    cx = cy = 0.5 * side
+    zp = float(np.max(x[:, 2] + r)) - depth
+    under = np.hypot(x[:, 0] - cx, x[:, 1] - cy) < r_hole
+    keep = (x[:, 2] + r <= zp) | under
+    x, r, under = x[keep], r[keep], under[keep]
+    walls = [wl for wl in base["walls"] if not (wl[0] == WALL_PLANE and wl[1][2] < 0.0)]
+    walls.append((WALL_PLANE_HOLE, (cx, cy, zp, -1.0, r_hole)))
+    mat = dict(MATERIAL)
+    mat["gamma"] = 0.0
+    v = np.zeros_like(x)
+    v[under, 2] = v_up
+    return dict(base, name="hole_box", x=x, r=r, material=mat, walls=walls, outlet={"above": zp}, v=v,
+                precision=precision, hole=(cx, cy, r_hole))
 
 
 def c1_ring(r_crop=2.8e-3, U_cav=2.0, outlet_shift=0.06e-3, v_in=0.3, precision="fp64"):

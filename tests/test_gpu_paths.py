@@ -158,6 +158,129 @@ def test_ring_walls_and_outlet_removal_across_rebuilds_fp64():
     compare_fp64(g, o2, what="ring, one re-seeded step", broken_before=s["broken_bonds"])
 
 
+def test_top_plate_with_hole_and_outlet_above_fp64():
+    """The paper's outlet (section 3.1): a top plate with a hole over the
+    centre and the outlet at the plate's level.  c0's spheres without cohesion
+    start upwards: those under the hole rise through it and leave, the others
+    are pushed back by the plate (wall entries are found for the plate even
+    over the hole, so a sphere that drifts out from under the hole meets it).
+    Every 60 steps alive flags, pair sets and contact counts exactly, produced
+    mass to rounding, forces to the per-step bar times the growth of rounding
+    differences along a violent trajectory (1e-9); at the end one step from one
+    identical state at 1e-12."""
+    w = synth.hole_box()
+    g = gpu_for(w, "fp64", v=w["v"])
+    o = oracle_for(w, v=w["v"], bond_at_init=True)
+    for k in range(5):
+        g.step(60)
+        o.step(60)
+        gs, sc = compare_fp64(g, o, tol=1e-9, what="hole box step %d" % (60 * (k + 1)))
+        assert gs["produced_mass"] == pytest.approx(sc["produced_mass"], rel=1e-13, abs=0)
+    al = gs["alive"]
+    gone = al == 0
+    assert 5 < int(gone.sum()) < len(al) // 4
+    # only spheres from under the hole left; the plate held the rest below its level
+    cx, cy, rh = w["hole"]
+    assert np.all(np.hypot(w["x"][gone, 0] - cx, w["x"][gone, 1] - cy) < rh + 2.0 * w["r"].max())
+    top = w["outlet"]["above"]
+    assert np.all(gs["x"][~gone, 2] <= top)
+    s = g.state(held=True)
+    pr = g.pairs(which=0)
+    nw = len(w["walls"])
+    o2 = oracle_for(w, x=s["x"], v=s["v"], w=s["w"], F=s["F"], T=s["T"], alive=s["alive"], pairs=pr["pairs"],
+                    pair_dt=pr["dt"], pair_bonded=pr["bonded"], bond_at_init=False,
+                    wall_dt=np.ascontiguousarray(s["wall_dt"][:, :nw, :]))
+    o2.set_held(s["step"], s["fluid_force"])
+    g.step(1)
+    o2.step(1)
+    compare_fp64(g, o2, what="hole box, one re-seeded step", broken_before=s["broken_bonds"])
+
+
+def test_paper_setting_f2_k2():
+    """The paper's own setting (section 3.1) at k = 2: SSW parcels of the
+    Table 2 sand, Table 3 material (surface energy x k), dt 1e-8 s, the
+    12 x 12 x 6 grid, the top plate with the 2.6 mm hole and the perforation
+    tunnel, mixed precision as the bench runs it.
+    1. The first coupling evaluation (porosity to 1e-12) and the pressure solve
+       with the paper's boundary conditions (injection through the faces normal
+       to y, top and bottom holes at the reference pressure) against the
+       oracle's own evaluation and direct solve; the flux that enters through
+       the injection faces leaves through the holes.
+    2. Three DEM steps, each from one identical state (the oracle seeded from
+       the GPU's), forces and torques within 1e-5 of each particle's force
+       scale, pair, bond and alive sets exact."""
+    from oracle import cfd
+    w = synth.f2(2)
+    g = gpu_for(w, "mixed")
+    o = oracle_for(w, bond_at_init=True)
+    g.step(1)
+    o.step(1)
+    eps, _ = g.fluid_out()
+    fo = o.fluid()
+    np.testing.assert_allclose(eps, fo["eps_s"], rtol=0, atol=1e-12)
+    kind, pf = synth.f2_cell_kinds(w, p_in=100.0)
+    p, U, _, it, rr = g.fluid_solve(kind, pf, max_iter=5000, rel_tol=1e-12)
+    assert rr <= 1e-12
+    n = np.clip(1.0 - fo["eps_s"], w["fluid"]["n_min"], 1.0)
+    lo, hi, nn = w["grid"]
+    h = [(hi[c] - lo[c]) / nn[c] for c in range(3)]
+    K = cfd.cell_coefficient(n, fo["fdrag_cell"], w["u_cell"] / n[:, None], w["fluid"]["mu_f"], h)
+    po = cfd.solve(w["grid"], K, kind, pf)
+    np.testing.assert_allclose(p, po, rtol=0, atol=1e-9 * pf.max())
+    q_in, q_out = _f2_fluxes(w, K, kind, po)
+    assert q_in > 0.0 and q_out == pytest.approx(q_in, rel=1e-9)
+    nw = len(w["walls"])
+    for k in range(3):
+        s = g.state(held=True)
+        pr = g.pairs(which=0)
+        ok = oracle_for(w, x=s["x"], v=s["v"], w=s["w"], F=s["F"], T=s["T"], alive=s["alive"], pairs=pr["pairs"],
+                        pair_dt=pr["dt"], pair_bonded=pr["bonded"], bond_at_init=False,
+                        wall_dt=np.ascontiguousarray(s["wall_dt"][:, :nw, :]))
+        ok.set_held(s["step"], s["fluid_force"])
+        g.step(1)
+        ok.step(1)
+        gs, os_ = g.state(), ok.state()
+        np.testing.assert_array_equal(gs["alive"], os_["alive"])
+        ef = scaled_err(gs["F"], os_["F"], os_["fscale"])
+        et = scaled_err(gs["T"], os_["T"], os_["tscale"])
+        print("f2 k=2 step %d: scaled force error %.2e, torque %.2e" % (k + 1, ef, et))
+        assert ef < 1e-5 and et < 1e-5
+        np.testing.assert_array_equal(g.pairs(which=0)["pairs"], ok.pairs()["pairs"])
+
+
+def _f2_fluxes(w, K, kind, p):
+    """flux into the open cells through the injection layers and out of them
+    through the hole cells, from the face transmissibilities of the pressure
+    equation (harmonic mean of K over the centre distance, times the face area)"""
+    lo, hi, nn = w["grid"]
+    nx, ny, nz = nn
+    h = [(hi[c] - lo[c]) / nn[c] for c in range(3)]
+    area = [h[1] * h[2], h[0] * h[2], h[0] * h[1]]
+    q_in = q_out = 0.0
+    idx = lambda ix, iy, iz: (iz * ny + iy) * nx + ix
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                a = idx(ix, iy, iz)
+                if kind[a] != 0:
+                    continue
+                for ax, (dx, dy, dz) in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
+                    for sg in (-1, 1):
+                        jx, jy, jz = ix + sg * dx, iy + sg * dy, iz + sg * dz
+                        if not (0 <= jx < nx and 0 <= jy < ny and 0 <= jz < nz):
+                            continue
+                        b = idx(jx, jy, jz)
+                        if kind[b] != 1:
+                            continue
+                        t = area[ax] / h[ax] * 2.0 * K[a] * K[b] / (K[a] + K[b])
+                        f = t * (p[b] - p[a])   # into the open cell
+                        if f > 0.0:
+                            q_in += f
+                        else:
+                            q_out -= f
+    return q_in, q_out
+
+
 def test_produced_mass_by_size_class_matches_oracle():
     """Fig. 11's observable: produced mass per class of diameter, counted at
     every removal; equals the masses of the oracle's removed spheres grouped by
@@ -362,15 +485,18 @@ def _box_column_kinds(w, p_in=2.0e3):
 
 
 def test_fluid_solve_matches_oracle():
-    """the pressure solve on the GPU (conjugate gradients) against the direct
-    solve of the same discrete equations, with K from the GPU's own coupling
-    evaluation (porosity, drag source, interstitial velocity): pressure, cell
-    velocity and gradient"""
+    """the pressure solve on the GPU (conjugate gradients) after its own
+    coupling evaluation, against the oracle's direct solve after the oracle's
+    evaluation of the same first step (porosity, drag source, interstitial
+    velocity): pressure, cell velocity and gradient"""
     from oracle import cfd
     w = synth.c0()
     g = gpu_for(w, "fp64")
     g.step(1)
-    eps, fd = g.fluid_out()
+    o = oracle_for(w, bond_at_init=True)
+    o.step(1)
+    fo = o.fluid()
+    eps, fd = fo["eps_s"], fo["fdrag_cell"]
     n = np.clip(1.0 - eps, w["fluid"]["n_min"], 1.0)
     u = w["u_cell"] / n[:, None]
     lo, hi, nn = w["grid"]

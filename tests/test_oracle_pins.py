@@ -962,3 +962,49 @@ def test_cfd_radial_inflow_conserves_and_approaches_log_profile():
         errs.append(np.abs(p[band] - exact).max() / 1e4)
     # staircase circles: the error halves with the cell size (first order)
     assert errs[1] < 0.6 * errs[0] and errs[1] < 0.08
+
+
+# ---------------------------------------------------------------------------
+# section 3.1: the top plate of the paper's box with its 2.6 mm outlet hole,
+# and the outlet on its top face (eq 40)
+# ---------------------------------------------------------------------------
+def test_plate_with_hole_hertz_force_and_open_hole():
+    """Spheres pressed by delta against the underside of a horizontal plate
+    (particles below it): away from the hole the Hertz force
+    4/3 E* sqrt(r) delta^(3/2) points down; a sphere whose centre lies over the
+    hole (inside its radius about the hole's axis, though overlapping the
+    plate's level) feels nothing; one just outside the hole radius is pushed
+    like the first."""
+    r, delta, zp, rh = 1e-4, 2e-6, 9e-3, 1.3e-3
+    cx, cy = 9e-3, 9e-3
+    z = zp - r + delta
+    x = np.array([[cx + 4e-3, cy - 3e-3, z],           # far from the hole
+                  [cx + 0.9 * rh, cy, z],             # over the hole
+                  [cx, cy - (rh + 1e-7), z]])         # just outside the hole
+    p = _params(scenes.material(gamma=0.0), 1e-9, g=(0, 0, 0),
+                walls=[(oracle.WALL_PLANE_HOLE, (cx, cy, zp, -1.0, rh))], normal_model=oracle.NORMAL_HERTZ)
+    sim = oracle.OracleSim(p, x, np.full(3, r), bond_at_init=False)
+    sim.step(1)
+    st = sim.state()
+    expect = 4.0 / 3.0 * ES * math.sqrt(r) * delta ** 1.5
+    for i in (0, 2):
+        assert st["F"][i][2] == pytest.approx(-expect, rel=1e-10)
+        assert st["F"][i][0] == 0.0 and st["F"][i][1] == 0.0
+    assert np.all(st["F"][1] == 0.0)
+
+
+def test_outlet_above_level_removes_and_counts_mass():
+    """Centres that rise above the outlet level leave as produced sand (eq 40):
+    of three spheres moving up, the one that crosses the level in the step
+    leaves, the one that stays just below and the one falling stay."""
+    r = np.array([5e-5, 6e-5, 7e-5])
+    zl = 9e-3
+    dt = 1e-6
+    x = np.array([[1e-3, 1e-3, zl - 0.5e-6], [3e-3, 1e-3, zl - 2e-6], [5e-3, 1e-3, zl - 1e-7]])
+    v = np.array([[0, 0, 1.0], [0, 0, 1.0], [0, 0, -1.0]])
+    p = _params(scenes.material(), dt, g=(0, 0, 0), outlet={"above": zl})
+    sim = oracle.OracleSim(p, x, r, v=v, bond_at_init=False)
+    sim.step(1)
+    st = sim.state()
+    assert list(st["alive"]) == [0, 1, 1]
+    assert sim.scalars()["produced_mass"] == pytest.approx(RHO * 4 / 3 * math.pi * r[0] ** 3, rel=1e-15)
