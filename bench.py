@@ -70,15 +70,18 @@ def alg_bytes(cls, n_alive, n_pairs, n_cells, rsz):
     return 0
 
 
-def load_traffic(kernel, workload):
+def load_traffic(kernel, workload, pair_mode="half"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+    was taken on the current kernel sources (and, for the step class, in the
+    same pair mode)."""
     path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
     if d.get("source_hash") != source_hash(d.get("sources")):
+        return None
+    if kernel == "step" and d.get("pair_mode", "half") != pair_mode:
         return None
     return d.get("traffic_bytes_per_launch")
 
@@ -424,10 +427,10 @@ def main():
                        "avg_us": round(1e3 * v[0] / max(v[1], 1), 3),
                        "alg_GBs": round(alg_bytes(k, n_alive, inf["n_pairs"], inf["ncell"], rsz) /
                                         (v[0] * 1e-3 / max(v[1], 1)) / 1e9, 1) if v[1] else None,
-                       "traffic": load_traffic(k, args.workload)}
+                       "traffic": load_traffic(k, args.workload, args.pair_mode or "half")}
                    for k, v in prof.items()}
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(dom, args.workload),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(dom, args.workload, args.pair_mode or "half"),
                     "alg_bytes_per_launch": ab, "avg_launch_us": avg_s * 1e6, "instrumented_steps": prof_steps}
     if args.workload == "c3":
         desc = ("c3: batched ensemble of %d independent samples (crops of the settled C1 bed, 500-20 000 "

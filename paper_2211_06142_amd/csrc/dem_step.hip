@@ -340,8 +340,10 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
       const double4 pa = Q.sx[la], pj = gld(X + j);
       const double4 va = Q.sv[la], vj = gld(V + j);
       const R4<R> wa = Q.sw[la], wj = gld(W + j);
+      // loaded together with the flag (a clear flag's history is stale and unused)
+      const R4<R> hraw = gld(Hin + p);
       const uint8_t fp = Fin[p];
-      const R4<R> hp = fp ? gld(Hin + p) : mk4<R>(0, 0, 0, 0);
+      const R4<R> hp = fp ? hraw : mk4<R>(0, 0, 0, 0);
       double gam = c.gamma;
       if (d.ccoh) gam = c.gamma * sqrt(CC[ia] * CC[j]);
       const bool own = j > (int32_t)ia;
@@ -394,7 +396,10 @@ __device__ __forceinline__ void particle_step(const DevState& d, const StepArgs&
 // earlier launch or by the launch that finds it due for the NEXT step, so every
 // block of one launch takes the same decision.
 template <typename R, int kGroup>
-__global__ __launch_bounds__(256) void k_step(const DevState* __restrict__ dp, StepArgs a) {
+// (at most 128 VGPRs, 4 waves per SIMD: 130 registers would leave 3, which
+// costs the kernel a sixth of its speed)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
+    const DevState* __restrict__ dp, StepArgs a) {
   __shared__ WaveQueue<R, kGroup> wq[kBlock / 64];
   const DevState& d = *dp;
   if (*d.abort_step <= a.step) return;
