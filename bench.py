@@ -219,6 +219,19 @@ def closure_block(w, torch):
     return out
 
 
+def parcel_layer_mass(wc):
+    """Mass of one layer of parcels on the cavity face of a coarse cylinder:
+    rho x solid fraction of the bed x cavity surface 2 pi r_cav h_bed x the
+    parcels' mass-mean diameter."""
+    r = wc["r"]
+    r_cav = wc["outlet"][2]
+    R = max(p[2] for kind, p in wc["walls"] if kind == 1)   # the outer cylinder wall
+    h = wc["bed_top"]
+    phi = float(np.sum(4.0 / 3.0 * np.pi * r ** 3)) / (np.pi * (R * R - r_cav * r_cav) * h)
+    d = 2.0 * float(np.cbrt(np.mean(r ** 3)))
+    return wc["material"]["rho"] * phi * 2.0 * np.pi * r_cav * h * d
+
+
 def learned_cg_block(horizon, ks=(2, 3), c4=False):
     """The coarse-grained model against the fine run (the metric's second
     part), on three packings of the cylinder (seeds 0, 1, 2): for each k the
@@ -226,7 +239,8 @@ def learned_cg_block(horizon, ks=(2, 3), c4=False):
     seed 0, kept or dropped on seed 1 (kept only where it is not worse than the
     plain model), and the errors of the plain and the learned coarse model are
     reported on seed 2 (with c4: on the 2 000 000-grain cylinder and its k = 3
-    parcels instead), with the RMSRE over M(t).  The speedup is the fine run's
+    parcels instead, run until the fine cylinder has produced ten layers of
+    parcels from its cavity face), with the RMSRE over M(t).  The speedup is the fine run's
     wall time over the kept coarse model's on the reporting packing, both from
     the initial packing over the whole horizon."""
     import synth
@@ -236,7 +250,11 @@ def learned_cg_block(horizon, ks=(2, 3), c4=False):
         train = (synth.c1(seed=0), synth.c2(k, seed=0))
         judge = (synth.c1(seed=1), synth.c2(k, seed=1))
         report = (synth.c4(1), synth.c4(k)) if c4 else (synth.c1(seed=2), synth.c2(k, seed=2))
-        res = ct.gain_test(train, judge, report, horizon=horizon, window=500, epochs=30)
+        layer = parcel_layer_mass(report[1]) if c4 else None
+        res = ct.gain_test(train, judge, report, horizon=horizon, window=500, epochs=30,
+                           report_mass=None if layer is None else 10.0 * layer)
+        if layer is not None:
+            res["parcel_layer_mass_kg"] = layer
         for key in ("net", "norm"):
             res.pop(key)
         for role in ("judge", "report"):

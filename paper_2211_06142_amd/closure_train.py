@@ -244,11 +244,20 @@ def _timed_run(w, steps, closure=None, norm=None):
     return wall, m
 
 
-def _mass_series(w, steps, window, closure=None, norm=None):
-    """produced mass at the end of every window of a run from the initial packing"""
+def _mass_series(w, steps, window, closure=None, norm=None, until_mass=None, max_steps=None):
+    """produced mass at the end of every window of a run from the initial
+    packing; with until_mass: windows until the produced mass reaches it (at
+    most max_steps), the horizon then being the steps taken"""
     rec = Recorder(w, make_sim(w, closure, norm))
-    for _ in range(steps // window):
-        rec.run_window(window, keep=False)
+    if until_mass is None:
+        for _ in range(steps // window):
+            rec.run_window(window, keep=False)
+    else:
+        while True:
+            rec.run_window(window, keep=False)
+            done = len(rec.mass) * window
+            if rec.mass[-1][1] >= until_mass or done >= max_steps:
+                break
     rec.sim.close()
     return np.array([m for _, m in rec.mass])
 
@@ -262,11 +271,13 @@ def _errors(mf, m):
 
 
 def gain_test(train, judge, report, horizon=20000, window=500, epochs=40, batch=4096, lr=2e-3, seed=0,
-              log=None):
+              log=None, report_mass=None, report_max_steps=400000):
     """train, judge, report: (fine workload, coarse workload) pairs of three
     packings.  Paired runs of the training pair give the dataset and the
     network; the judging pair decides keep or fall back; the reporting pair
-    gives the reported errors of the plain and the learned coarse model."""
+    gives the reported errors of the plain and the learned coarse model.
+    report_mass: the reporting runs last until the fine run has produced that
+    mass (at most report_max_steps) instead of `horizon` steps."""
     say = log or (lambda *a: None)
     nwin = horizon // window
     wf, wc = train
@@ -286,9 +297,14 @@ def gain_test(train, judge, report, horizon=20000, window=500, epochs=40, batch=
            "train_samples": int(len(X)), "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
            "packings": {"train": wf["name"], "judge": judge[0]["name"], "report": report[0]["name"]}}
     for role, (f, c) in (("judge", judge), ("report", report)):
-        mf = _mass_series(f, horizon, window)
-        mp = _mass_series(c, horizon, window)
-        ml = _mass_series(c, horizon, window, net, norm)
+        if role == "report" and report_mass is not None:
+            mf = _mass_series(f, 0, window, until_mass=report_mass, max_steps=report_max_steps)
+            out["report_horizon_steps"] = int(len(mf) * window)
+        else:
+            mf = _mass_series(f, horizon, window)
+        steps = len(mf) * window
+        mp = _mass_series(c, steps, window)
+        ml = _mass_series(c, steps, window, net, norm)
         ep, rp = _errors(mf, mp)
         el, rl = _errors(mf, ml)
         out[role] = {"mass_fine": float(mf[-1]), "mass_plain_cg": float(mp[-1]), "mass_learned_cg": float(ml[-1]),
@@ -298,8 +314,9 @@ def gain_test(train, judge, report, horizon=20000, window=500, epochs=40, batch=
     accepted = bool(out["judge"]["err_learned_cg"] <= out["judge"]["err_plain_cg"])
     out["closure_accepted"] = accepted
     rf, rc = report
-    wall_fine, _ = _timed_run(rf, horizon)
-    wall_cg, _ = _timed_run(rc, horizon, net if accepted else None, norm if accepted else None)
+    rsteps = out.get("report_horizon_steps", horizon)
+    wall_fine, _ = _timed_run(rf, rsteps)
+    wall_cg, _ = _timed_run(rc, rsteps, net if accepted else None, norm if accepted else None)
     out.update(wall_fine_s=wall_fine, wall_cg_s=wall_cg, speedup_vs_fine=wall_fine / wall_cg, net=net, norm=norm)
     # the model the rule keeps, on the reporting packing
     r = out["report"]
