@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # neighbour skin / smallest radius: c1 tuned over its 5 000-step run (the cavity face erodes and
 # particles speed up, so a wider skin pays); the boxes keep the library default
-SKIN_FACTOR = {"c1": 1.2, "c0": 0.4, "c3": 0.4, "c3k": 0.4, "f2": 0.4}
+SKIN_FACTOR = {"c1": 1.2, "c0": 0.4, "c3": 0.4, "c3k": 0.4, "f2": 0.4, "c4": 1.2}
 LANES = 2           # lanes per particle of the row gather (the library default in half-pair mode)
 
 
@@ -343,7 +343,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c0", "c3", "c3k", "f2"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c0", "c3", "c3k", "f2", "c4"],
                     help="c3k: the ensemble with per-sample coarse-graining k = 1, 2, 3; f2: the paper's own "
                     "setting (18 x 18 x 9 mm box, Table 2 sand, Table 3 material, dt 1e-8 s, top outlet)")
     ap.add_argument("--f2-k", type=int, default=1, help="coarse-graining factor of the f2 run (1 or 2, SSW)")
@@ -383,6 +383,8 @@ def main():
         ws = [synth.c1()]
     elif args.workload == "f2":
         ws = [synth.f2(args.f2_k)]
+    elif args.workload == "c4":
+        ws = [synth.c4(1)]
     elif args.workload == "c0":
         ws = [synth.c0()]
     else:
@@ -476,6 +478,10 @@ def main():
         desc = ("%s: %d polydisperse spheres (lognormal d, median 0.15 mm), hollow cylinder R 12 mm / cavity "
                 "2 mm, 48x48x24 fluid grid, radial Darcy inflow, dt 1e-7 s, coupling every %d steps"
                 % (w["name"], len(w["r"]), w["fluid"]["couple_every"]))
+        if args.workload == "c4":
+            desc = ("c4: %d polydisperse spheres (lognormal d, median 0.15 mm), the c1 cylinder scaled by 10^(1/3) "
+                    "(R 25.85 mm / cavity 4.31 mm), 103x103x52 fluid grid, radial Darcy inflow, dt 1e-7 s, coupling "
+                    "every %d steps" % (len(w["r"]), w["fluid"]["couple_every"]))
         metric = ("particle-steps/s at 200k particles, 1 GPU" if args.workload == "c1"
                   else "particle-steps/s at %d particles, 1 GPU" % len(w["r"]))
     out = {

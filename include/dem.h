@@ -292,6 +292,21 @@ dem_status dem_read_aggregates(dem_ctx* ctx, double* produced_mass, double* coor
 dem_status dem_set_size_classes(dem_ctx* ctx, int32_t n_edges, const double* edges);
 dem_status dem_read_produced_classes(dem_ctx* ctx, double* mass);
 
+/* Walls in motion (section 3.1: the top plate compresses the sample to its
+ * overburden stress before perforation).  dem_read_wall_forces: force[(s *
+ * DEM_MAX_WALLS + w) * 3 + c] (N, host or device, n_samples x DEM_MAX_WALLS x 3)
+ * is the total force the particles of sample s exert on its wall w at the last
+ * force evaluation (the negative of the wall's Hertz contact forces on them,
+ * summed in a fixed order); zero for walls a sample does not have.
+ * Synchronises.  dem_set_walls: replace the n_walls walls of `sample` (n_walls
+ * must equal its current count; the same validation as dem_init), from the
+ * next step on.  A wall moves only between calls, and its velocity does not
+ * enter the contact law (a quasi-static move, as a servo-controlled plate
+ * makes); the neighbour and wall lists are rebuilt at the next step.
+ * DEM_E_INVAL for a bad sample, count or wall. */
+dem_status dem_read_wall_forces(dem_ctx* ctx, double* force);
+dem_status dem_set_walls(dem_ctx* ctx, int32_t sample, int32_t n_walls, const dem_wall* walls);
+
 /* Query: total fluid cells, pair-list size and capacity, rebuild count, and
  * the candidate margin (skin plus the largest pull-off separation) used by
  * the neighbour list of sample 0. */

@@ -124,6 +124,10 @@ def lib():
         L.or_get_pairs.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.or_get_wall_dt.restype = None
         L.or_get_wall_dt.argtypes = [vp, vp]
+        L.or_get_wall_forces.restype = None
+        L.or_get_wall_forces.argtypes = [vp, vp]
+        L.or_set_walls.restype = ctypes.c_int
+        L.or_set_walls.argtypes = [vp, ctypes.c_int, vp]
         L.or_get_fluid.restype = None
         L.or_get_fluid.argtypes = [vp, vp, vp, vp, vp]
         _lib = L
@@ -385,6 +389,24 @@ class OracleSim:
         L.or_get_pairs(self.h, cnt, _ptr(pi), _ptr(pj), _ptr(pdt), _ptr(pb), _ptr(pt))
         return {"pairs": np.stack([pi[:cnt], pj[:cnt]], 1), "dt": pdt[:cnt], "bonded": pb[:cnt],
                 "touch": pt[:cnt]}
+
+    def wall_forces(self):
+        """(MAX_WALLS, 3): the particles' total force on each wall at the last evaluation"""
+        out = np.zeros((MAX_WALLS, 3))
+        lib().or_get_wall_forces(self.h, _ptr(out))
+        return out
+
+    def set_walls(self, walls):
+        """replace the walls, [(kind, params), ...] with the same count"""
+        arr = (OrWall * MAX_WALLS)()
+        for k, (kind, prm) in enumerate(walls):
+            arr[k].kind = kind
+            for q, val in enumerate(prm):
+                arr[k].p[q] = val
+        if lib().or_set_walls(self.h, len(walls), ctypes.cast(arr, ctypes.c_void_p)) != 0:
+            raise ValueError("set_walls: the wall count must stay the same")
+        for k in range(len(walls)):
+            self.params.walls[k] = arr[k]
 
     def wall_dt(self):
         nw = self.params.n_walls

@@ -268,6 +268,7 @@ struct or_sim {
   uint8_t* alive;
   hrec* h; int64_t nh;
   double* wall_dt;
+  double wall_force[3 * OR_MAX_WALLS];   /* the particles' force on each wall, last evaluation */
   double *fdrag, *fbuoy;          /* particle coupling forces held between coupling steps */
   double *u_cell, *gp_cell; int have_fluid;
   double *eps_cell, *fd_cell;
@@ -921,6 +922,7 @@ static void one_step(or_sim* s) {
   s->h = nh; s->nh = nnh;
 
   /* 5. walls: Hertz law with the wall as a body of infinite radius and mass */
+  for (int k = 0; k < 3 * OR_MAX_WALLS; ++k) s->wall_force[k] = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     if (!s->alive[i]) continue;
     for (int wi = 0; wi < nw; ++wi) {
@@ -942,6 +944,7 @@ static void one_step(or_sim* s) {
       for (int c = 0; c < 3; ++c) {
         s->F[3 * i + c] += o.F[c];
         s->T[3 * i + c] += ri * o.c[c] + o.Tr[c];
+        s->wall_force[3 * wi + c] -= o.F[c];   /* the particle pushes the wall back */
       }
       s->fscale[i] += o.scale;
       s->tscale[i] += ri * o.tscale_t + o.tscale_roll;
@@ -1024,6 +1027,17 @@ int64_t or_get_pairs(const or_sim* s, int64_t cap, int64_t* pi, int64_t* pj, dou
     if (ptouch) ptouch[k] = s->h[k].touch;
   }
   return s->nh;
+}
+
+void or_get_wall_forces(const or_sim* s, double* force) {
+  memcpy(force, s->wall_force, sizeof(double) * 3 * OR_MAX_WALLS);
+}
+
+/* replace the walls (same count): a wall moved between calls */
+int or_set_walls(or_sim* s, int n_walls, const or_wall* walls) {
+  if (n_walls != s->p.n_walls) return -1;
+  for (int w = 0; w < n_walls; ++w) s->p.walls[w] = walls[w];
+  return 0;
 }
 
 void or_get_wall_dt(const or_sim* s, double* wall_dt) {

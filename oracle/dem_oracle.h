@@ -126,6 +126,10 @@ void    or_get_scalars(const or_sim* s, double* produced_mass, int64_t* broken_b
 int64_t or_get_pairs(const or_sim* s, int64_t cap, int64_t* pi, int64_t* pj, double* pdt,
                      uint8_t* pbond, uint8_t* ptouch);
 void    or_get_wall_dt(const or_sim* s, double* wall_dt);
+/* the particles' total force on each wall at the last evaluation (3 x OR_MAX_WALLS) */
+void    or_get_wall_forces(const or_sim* s, double* force);
+/* replace the walls between steps (same count), e.g. a plate moved by a servo */
+int     or_set_walls(or_sim* s, int n_walls, const or_wall* walls);
 void    or_get_fluid(const or_sim* s, double* eps_s, double* fdrag_cell, double* f_part,
                      double* fb_part);
 

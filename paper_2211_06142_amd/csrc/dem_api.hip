@@ -84,6 +84,7 @@ struct dem_ctx {
   double* agg_buf = nullptr;  // aggregate outputs and slice partials
   int64_t fixed_capacity = 0;   // half-pair capacity given without DEM_FLAG_AUTO_REGROW (0: grows)
   int64_t rec_cap = 0;          // slots of the half-pair records d.rec
+  int64_t wfrc_cap = 0;         // wall entries of d.wfrc
   int lanes_set = 0;             // lanes chosen by the caller (else the pair mode's default)
   double* stage_aux = nullptr;   // read-back of the held fluid force and wall history
   // fluid solver: cell kinds, fixed pressures, work vectors (the solution kept
@@ -409,6 +410,11 @@ template <typename R> dem_status rebuild(dem_ctx* c, int first, int mark_bonds) 
     return fault(c, kStCapacity);
   if (grow_nbr(c, ns, tot[0], tot[1]) != hipSuccess) return DEM_E_NOMEM;
   if (grow_walls(c, ws, tot[2]) != hipSuccess) return DEM_E_NOMEM;
+  if (ws.cap > c->wfrc_cap) {   // wall forces follow the largest wall capacity
+    dfree(c, d.wfrc);
+    if (dalloc_bytes(c, &d.wfrc, ws.cap * 4 * (int64_t)c->rsz) != hipSuccess) return DEM_E_NOMEM;
+    c->wfrc_cap = ws.cap;
+  }
   ns.nent = tot[0];
   ns.nslots = tot[1];
   ws.n = tot[2];
@@ -1105,6 +1111,55 @@ dem_status dem_read_aggregates(dem_ctx* c, double* produced_mass, double* coordi
     if (broken_bonds) broken_bonds[q] = (int64_t)br[q];
     if (n_alive) n_alive[q] = na[q];
   }
+  return DEM_OK;
+}
+
+dem_status dem_read_wall_forces(dem_ctx* c, double* force) {
+  if (!c || !force) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const DevState& d = c->d;
+  const int ns = d.nsamples;
+  std::vector<double> out((size_t)ns * DEM_MAX_WALLS * 3, 0.0);
+  const int64_t ne = d.nwall;
+  if (ne > 0 && d.wfrc) {
+    std::vector<int32_t> wrow(d.n + 1), wid(ne), smp(d.n);
+    std::vector<char> fr(ne * 4 * c->rsz);
+    HIPCHK(hipMemcpy(wrow.data(), d.wrow, sizeof(int32_t) * (d.n + 1), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(wid.data(), d.wid, sizeof(int32_t) * ne, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(smp.data(), d.sample, sizeof(int32_t) * d.n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(fr.data(), d.wfrc, fr.size(), hipMemcpyDeviceToHost));
+    // fixed order: particles in their sorted order, each particle's entries in order
+    for (int64_t i = 0; i < d.n; ++i)
+      for (int32_t e = wrow[i]; e < wrow[i + 1]; ++e) {
+        double f[3];
+        if (c->fp64) { double4 q = ((double4*)fr.data())[e]; f[0] = q.x; f[1] = q.y; f[2] = q.z; }
+        else { float4 q = ((float4*)fr.data())[e]; f[0] = q.x; f[1] = q.y; f[2] = q.z; }
+        double* o = &out[((size_t)smp[i] * DEM_MAX_WALLS + wid[e]) * 3];
+        for (int k = 0; k < 3; ++k) o[k] -= f[k];   // the particle's push on the wall
+      }
+  }
+  HIPCHK(hipMemcpy(force, out.data(), sizeof(double) * out.size(), hipMemcpyDefault));
+  return DEM_OK;
+}
+
+dem_status dem_set_walls(dem_ctx* c, int32_t sample, int32_t n_walls, const dem_wall* walls) {
+  if (!c || !walls || sample < 0 || sample >= c->d.nsamples) return DEM_E_INVAL;
+  dem_params p = c->params[sample];
+  if (n_walls != p.n_walls) return DEM_E_INVAL;
+  for (int w = 0; w < n_walls; ++w) p.walls[w] = walls[w];
+  if (validate(p) != DEM_OK) return DEM_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return DEM_E_DEVICE;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->params[sample] = p;
+  SampleConst& k = c->sc[sample];
+  for (int w = 0; w < n_walls; ++w) {
+    k.walls[w].kind = walls[w].kind;
+    for (int q = 0; q < 6; ++q) k.walls[w].p[q] = walls[w].p[q];
+  }
+  HIPCHK(hipMemcpy(c->d.sc + sample, &k, sizeof(SampleConst), hipMemcpyHostToDevice));
+  // the wall lists hold the walls within the skin of each particle: find them again
+  c->force_rebuild = 1;
   return DEM_OK;
 }
 

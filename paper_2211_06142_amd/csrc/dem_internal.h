@@ -139,6 +139,8 @@ struct DevState {
   int32_t *wrow, *wcnt, *wid, *wrow_o, *wid_o;
   void *wdt, *wdt_o;               // R4
   uint8_t *wfl, *wfl_o;
+  void* wfrc;                      // R4 per wall entry: the wall's force on the particle at the
+                                   // last evaluation (zero out of contact)
   // fluid
   int64_t ncell, ndual;
   int32_t* cell_sample;

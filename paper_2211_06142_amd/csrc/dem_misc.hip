@@ -60,7 +60,7 @@ template void launch_unpermute<float>(DevState&, double*, double*, double*, doub
 // Aggregates in two fixed-order passes: kAggChunks blocks per sample each
 // reduce one contiguous slice of the sample's particles and half-pair slots
 // (tree in LDS), then one thread per sample sums its slices in order.
-constexpr int kAggChunks = 64;
+constexpr int kAggChunks = 256;   // 256 blocks fill the chip for one sample
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_aggregate_part(DevState d, const int64_t* soff, double* part) {

@@ -173,6 +173,7 @@ __device__ __forceinline__ void particle_finish(const DevState& d, const StepArg
   const double m = c.rho * (4.0 / 3.0) * M_PI * pi.w * pi.w * pi.w;
   const auto WDT = G((R4<R>*)d.wdt);
   const auto WFL = G((uint8_t*)d.wfl);
+  const auto WFR = G((R4<R>*)d.wfrc);
   const int32_t w1 = fin.w1;
   for (int32_t e = fin.w0 + sub; e < w1; e += kGroup) {
     R4<R> h4 = gld((gptr<const R4<R>>)(WDT + e));
@@ -181,6 +182,7 @@ __device__ __forceinline__ void particle_finish(const DevState& d, const StepArg
     if (!wall_geom(wl, pi.x, pi.y, pi.z, sd, nw) || !(sd < pi.w)) {
       gst(WDT + e, mk4<R>(0, 0, 0, 0));
       WFL[e] = 0;
+      gst(WFR + e, mk4<R>(0, 0, 0, 0));
       continue;
     }
     const R delta = (R)(pi.w - sd);
@@ -198,6 +200,7 @@ __device__ __forceinline__ void particle_finish(const DevState& d, const StepArg
     T[2] += r * o.c[2] + o.Tr[2];
     gst(WDT + e, mk4<R>(h[0], h[1], h[2], (R)0));
     WFL[e] = 2;
+    gst(WFR + e, mk4<R>(o.F[0], o.F[1], o.F[2], (R)0));
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {

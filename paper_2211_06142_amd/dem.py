@@ -30,6 +30,7 @@ DEM_PROF_PROLOGUE, DEM_PROF_REBUILD, DEM_PROF_FLUID, DEM_PROF_STEP, DEM_PROF_N =
 PROF_NAMES = ["prologue", "rebuild", "fluid", "step"]
 
 EXPORTS = sorted(["dem_init", "dem_step", "dem_map_fluid", "dem_read_state", "dem_read_pairs",
+                  "dem_read_wall_forces", "dem_set_walls",
                   "dem_read_aggregates", "dem_info", "dem_request_rebuild", "dem_destroy", "dem_status_str",
                   "dem_cg_material", "dem_cg_diameters", "dem_rayleigh_dt", "dem_profile", "dem_read_profile",
                   "dem_read_fault", "dem_mlp_create", "dem_mlp_destroy", "dem_mlp_set_params", "dem_mlp_get_params",
@@ -111,6 +112,10 @@ def lib():
         L.dem_read_pairs.argtypes = [vp, i32, i64, vp, vp, vp, vp]
         L.dem_read_aggregates.restype = i32
         L.dem_read_aggregates.argtypes = [vp, vp, vp, vp, vp]
+        L.dem_read_wall_forces.restype = i32
+        L.dem_read_wall_forces.argtypes = [vp, vp]
+        L.dem_set_walls.restype = i32
+        L.dem_set_walls.argtypes = [vp, i32, i32, vp]
         L.dem_info.restype = i32
         L.dem_info.argtypes = [vp, vp, vp, vp, vp, vp]
         L.dem_request_rebuild.restype = i32
@@ -589,6 +594,22 @@ class Simulation:
         _check(dem_read_aggregates(self.ctx, pm.ctypes.data, z.ctypes.data, bb.ctypes.data, na.ctypes.data),
                "dem_read_aggregates")
         return {"produced_mass": pm, "coordination": z, "broken_bonds": bb, "n_alive": na}
+
+    def wall_forces(self):
+        """(n_samples, DEM_MAX_WALLS, 3): the particles' total force on each wall"""
+        f = np.zeros((len(self.params), DEM_MAX_WALLS, 3))
+        _check(lib().dem_read_wall_forces(self.ctx, f.ctypes.data), "dem_read_wall_forces")
+        return f
+
+    def set_walls(self, walls, sample=0):
+        """replace a sample's walls, given as [(kind, params), ...] (the same count)"""
+        arr = (dem_wall * DEM_MAX_WALLS)()
+        for k, (kind, prm) in enumerate(walls):
+            arr[k].kind = kind
+            for q, val in enumerate(prm):
+                arr[k].p[q] = val
+        _check(lib().dem_set_walls(self.ctx, int(sample), len(walls), ctypes.cast(arr, ctypes.c_void_p)),
+               "dem_set_walls")
 
     def set_size_classes(self, edges):
         """produced-sand size classes by fine-scale diameter (edges in m)"""

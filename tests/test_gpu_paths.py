@@ -281,6 +281,36 @@ def _f2_fluxes(w, K, kind, p):
     return q_in, q_out
 
 
+def test_wall_forces_and_a_moving_plate_fp64():
+    """The particles' force on every wall (fixed-order sums of the wall
+    contacts) against the oracle, then the top plate of c0 moved down onto the
+    bed on both sides, as a servo compresses a sample (section 3.1), and the
+    run continued: forces, wall forces and contact sets at the FP64 bar."""
+    w = synth.c0()
+    g = gpu_for(w, "fp64")
+    o = oracle_for(w, bond_at_init=True)
+    g.step(10)
+    o.step(10)
+    fg, fo = g.wall_forces()[0], o.wall_forces()
+    scale = np.abs(fo).max()
+    assert scale > 0.0
+    np.testing.assert_allclose(fg, fo, rtol=0, atol=1e-12 * scale)
+    top = float(np.max(w["x"][:, 2] + w["r"]))
+    walls = [wl if not (wl[0] == synth.WALL_PLANE and wl[1][2] < 0.0) else (wl[0], (0.0, 0.0, -1.0, -(top - 2e-6)))
+             for wl in w["walls"]]
+    g.set_walls(walls)
+    o.set_walls(walls)
+    for k in range(3):
+        g.step(10)
+        o.step(10)
+        compare_fp64(g, o, what="moving plate step %d" % (10 * (k + 1)))
+        fg, fo = g.wall_forces()[0], o.wall_forces()
+        np.testing.assert_allclose(fg, fo, rtol=0, atol=1e-11 * np.abs(fo).max())
+    assert fo[5][2] > 0.0 and fg[5][2] > 0.0   # the bed pushes the plate up
+    with pytest.raises(dem.DemError):
+        g.set_walls(walls[:-1])
+
+
 def test_produced_mass_by_size_class_matches_oracle():
     """Fig. 11's observable: produced mass per class of diameter, counted at
     every removal; equals the masses of the oracle's removed spheres grouped by

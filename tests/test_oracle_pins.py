@@ -1008,3 +1008,30 @@ def test_outlet_above_level_removes_and_counts_mass():
     st = sim.state()
     assert list(st["alive"]) == [0, 1, 1]
     assert sim.scalars()["produced_mass"] == pytest.approx(RHO * 4 / 3 * math.pi * r[0] ** 3, rel=1e-15)
+
+
+def test_wall_forces_are_the_reactions_and_walls_move():
+    """The particles' force on a wall is minus the wall's Hertz forces on them
+    (Newton's third law, 4/3 E* sqrt(r) delta^(3/2) each): two spheres pressed
+    into the floor and one into a side wall.  Then the floor is moved up by
+    d (set_walls, as a servo moves a plate between calls): the next step's
+    force follows the new overlap delta + d."""
+    r, delta, d = 1e-4, 2e-6, 1e-6
+    floor = (oracle.WALL_PLANE, (0.0, 0.0, 1.0, 0.0))
+    side = (oracle.WALL_PLANE, (1.0, 0.0, 0.0, 0.0))
+    x = np.array([[1e-3, 1e-3, r - delta], [2e-3, 1e-3, r - delta], [r - delta, 3e-3, 1e-3]])
+    p = _params(scenes.material(gamma=0.0, e=1.0), 1e-9, g=(0, 0, 0), walls=[floor, side],
+                normal_model=oracle.NORMAL_HERTZ)   # e = 1: no damping
+    sim = oracle.OracleSim(p, x, np.full(3, r), bond_at_init=False)
+    sim.step(1)
+    f = sim.wall_forces()
+    hertz = lambda dd: 4.0 / 3.0 * ES * math.sqrt(r) * dd ** 1.5
+    assert f[0][2] == pytest.approx(-2.0 * hertz(delta), rel=1e-9) and abs(f[0][0]) + abs(f[0][1]) == 0.0
+    assert f[1][0] == pytest.approx(-hertz(delta), rel=1e-9) and abs(f[1][1]) + abs(f[1][2]) == 0.0
+    assert np.all(f[2:] == 0.0)
+    sim.set_walls([(oracle.WALL_PLANE, (0.0, 0.0, 1.0, d)), side])
+    sim.step(1)
+    st = sim.state()   # x is where the step evaluated the force
+    assert st["F"][0][2] == pytest.approx(hertz(r - (st["x"][0][2] - d)), rel=1e-12)
+    with pytest.raises(ValueError):
+        sim.set_walls([side])
