@@ -347,6 +347,8 @@ def main():
                     help="c3k: the ensemble with per-sample coarse-graining k = 1, 2, 3; f2: the paper's own "
                     "setting (18 x 18 x 9 mm box, Table 2 sand, Table 3 material, dt 1e-8 s, top outlet)")
     ap.add_argument("--f2-k", type=int, default=1, help="coarse-graining factor of the f2 run (1 or 2, SSW)")
+    ap.add_argument("--f2-protocol", action="store_true", help="f2 from the paper's stages: the generated bed "
+                    "compressed by the top plate to 1 MPa (servo), then perforated, then the sand-production run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of oracle stepping (cpu_baseline)")
     ap.add_argument("--skin-factor", type=float, default=None,
@@ -381,6 +383,18 @@ def main():
 
     if args.workload == "c1":
         ws = [synth.c1()]
+    elif args.workload == "f2" and args.f2_protocol:
+        from paper_2211_06142_amd import paper_setting
+        bed = synth.f2_bed(args.f2_k)
+        t0 = time.perf_counter()
+        comp = paper_setting.compress(bed, log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        compression = {"stress_pa": comp["stress"], "plate_height_m": comp["plate_z"], "porosity": comp["porosity"],
+                       "cycles": comp["cycles"], "steps": comp["steps"], "converged": comp["converged"],
+                       "wall_s": time.perf_counter() - t0, "grains": len(bed["r"])}
+        ws = [paper_setting.perforate(comp, bed)]
+        comp["sim"].close()
+        print("bench: compressed to %.4g Pa, porosity %.4f, plate %.4f mm" % (comp["stress"], comp["porosity"],
+              comp["plate_z"] * 1e3), file=sys.stderr, flush=True)
     elif args.workload == "f2":
         ws = [synth.f2(args.f2_k)]
     elif args.workload == "c4":
@@ -510,6 +524,8 @@ def main():
         out["config"]["tuned"] = tuned
     if f2_fluid:
         out["config"]["fluid_solve"] = f2_fluid
+    if args.workload == "f2" and args.f2_protocol:
+        out["config"]["compression"] = compression
     if not args.no_closure and len(ws) == 1:
         out["closure"] = closure_block(w, torch)
     sim.close()

@@ -405,6 +405,50 @@ def table2_mean_diameter():
     return float(np.cbrt(w.sum() / np.sum(w / d ** 3)))
 
 
+F2_SIDE, F2_HEIGHT = 18e-3, 9e-3                 # the box of section 3.1 after compression
+F2_R_PERF, F2_R_HOLE = 0.85e-3, 1.3e-3             # perforation tunnel, outlet hole (radii)
+
+
+def _f2_settle(k, scheme, n_fine, seed):
+    """the geometric packing of the paper's box: Table 2 sand settled in the
+    18 x 18 mm box (positions, radii, worst overlap)"""
+    L, H = F2_SIDE, F2_HEIGHT
+    n = int(round(n_fine / k ** 3))
+    rng = np.random.default_rng(SEED0 + 5 + 10 * int(k) + (1 if scheme == "ssp" else 0) + 100 * seed)
+    if scheme == "ssp" and k > 1:
+        d = np.full(n, k * table2_mean_diameter())
+    else:
+        d = k * table2_diameters(rng, n)
+    r = 0.5 * d
+    x, worst = settle(r, 0, (0.0, 0.0, 0.0, L, L, 3.0 * H), rng)
+    return x, r, worst
+
+
+def f2_bed(k=1, scheme="ssw", n_fine=250000, seed=0):
+    """The paper's box before compression (section 3.1, generation stage):
+    every grain of the geometric packing of f2 (nothing cut, no tunnel), five
+    plane walls and a top plate one largest radius above the bed, no outlet,
+    no fluid, the original JKR law of the generation stage (normal_model
+    "orig"), Table 3 material, dt 1e-8 s.  paper_setting.compress moves the plate
+    down to the overburden stress."""
+    L = F2_SIDE
+    name = "f2bed_k%d_%s_n%d_s%d" % (k, scheme, n_fine, seed)
+
+    def make():
+        x, r, worst = _f2_settle(k, scheme, n_fine, seed)
+        return {"x": x, "r": r, "worst": np.array(worst)}
+
+    pk = cached(name, make)
+    x, r = pk["x"], pk["r"]
+    top = float(np.max(x[:, 2] + r)) + float(r.max())
+    walls = [(WALL_PLANE, (1.0, 0.0, 0.0, 0.0)), (WALL_PLANE, (-1.0, 0.0, 0.0, -L)),
+             (WALL_PLANE, (0.0, 1.0, 0.0, 0.0)), (WALL_PLANE, (0.0, -1.0, 0.0, -L)),
+             (WALL_PLANE, (0.0, 0.0, 1.0, 0.0)), (WALL_PLANE, (0.0, 0.0, -1.0, -top))]
+    return dict(name=name, x=x, r=r, material=dict(PAPER_MATERIAL), k=float(k), scheme=scheme, walls=walls,
+                grid=None, u_cell=None, gradp_cell=None, fluid=None, outlet=None, dt=PAPER_DT, g=GRAV,
+                sha256=str(pk["sha256"]), precision="mixed", n_fine=n_fine, normal_model="orig")
+
+
 def f2(k=1, scheme="ssw", n_fine=250000, seed=0):
     """The paper's own setting (section 3.1) after its perforation stage: an
     18 x 18 mm box of height 9 mm, sand of Table 2 (k = 1: n_fine grains; k > 1:
@@ -420,20 +464,13 @@ def f2(k=1, scheme="ssw", n_fine=250000, seed=0):
     removed) instead of pushed open by the penetrometer.  The fluid fields
     start at rest; the run's own pressure solve (model A, dem_fluid_solve with
     f2_cell_kinds) gives them."""
-    L, H = 18e-3, 9e-3
+    L, H = F2_SIDE, F2_HEIGHT
     cx = cy = 0.5 * L
-    r_perf, r_hole = 0.85e-3, 1.3e-3
-    n = int(round(n_fine / k ** 3))
-    rng = np.random.default_rng(SEED0 + 5 + 10 * int(k) + (1 if scheme == "ssp" else 0) + 100 * seed)
+    r_perf, r_hole = F2_R_PERF, F2_R_HOLE
     name = "f2_k%d_%s_n%d_s%d" % (k, scheme, n_fine, seed)
 
     def make():
-        if scheme == "ssp" and k > 1:
-            d = np.full(n, k * table2_mean_diameter())
-        else:
-            d = k * table2_diameters(rng, n)
-        r = 0.5 * d
-        x, worst = settle(r, 0, (0.0, 0.0, 0.0, L, L, 3.0 * H), rng)
+        x, r, worst = _f2_settle(k, scheme, n_fine, seed)
         keep = (x[:, 2] + r <= H) & (np.hypot(x[:, 0] - cx, x[:, 1] - cy) >= r_perf)
         return {"x": x[keep], "r": r[keep], "worst": np.array(worst)}
 

@@ -248,6 +248,35 @@ def test_paper_setting_f2_k2():
         np.testing.assert_array_equal(g.pairs(which=0)["pairs"], ok.pairs()["pairs"])
 
 
+def test_paper_protocol_compression_and_perforation_k2():
+    """The paper's stages at k = 2 (section 3.1): the generated bed (original
+    JKR law) compressed by the servo-driven top plate to the 1 MPa overburden
+    stress, held within 3 % for 5 cycles with the plate below its start; the
+    porosity under the plate is printed (the paper measured 41 %) and asserted
+    to be that of a dense granular packing; then the sample is perforated under
+    the outlet and the sand-production run (modified JKR, the paper's injection
+    field) takes 300 steps: no fault, and alive plus produced mass equals the
+    perforated sample's."""
+    import bench
+    from paper_2211_06142_amd import paper_setting
+    bed = synth.f2_bed(2)
+    res = paper_setting.compress(bed)
+    print("compressed: %d cycles, stress %.4g Pa, plate %.4f mm, porosity %.4f"
+          % (res["cycles"], res["stress"], res["plate_z"] * 1e3, res["porosity"]))
+    assert res["converged"] and abs(res["stress"] - 1e6) <= 0.03e6
+    assert res["plate_z"] < -bed["walls"][-1][1][3]
+    assert 0.3 < res["porosity"] < 0.5
+    w = paper_setting.perforate(res, bed)
+    res["sim"].close()
+    assert 0 < len(w["r"]) < len(bed["r"])
+    g = bench.build_sim([w], bench.SKIN_FACTOR["f2"], bench.LANES, 0)
+    bench.f2_fluid_setup(g, w)
+    m = w["material"]["rho"] * 4.0 / 3.0 * math.pi * w["r"] ** 3
+    g.step(300)
+    st = g.state()
+    assert st["produced_mass"] + m[st["alive"] == 1].sum() == pytest.approx(m.sum(), rel=1e-12)
+
+
 def _f2_fluxes(w, K, kind, p):
     """flux into the open cells through the injection layers and out of them
     through the hole cells, from the face transmissibilities of the pressure
