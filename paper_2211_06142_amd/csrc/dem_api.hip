@@ -792,7 +792,7 @@ dem_status dem_init(dem_ctx** out, const dem_params* params, int32_t n_samples, 
   ok &= dalloc(c, &d.fpart, n) == hipSuccess;
   ok &= dalloc(c, &d.dpart, 32 * (d.ndual + 1)) == hipSuccess;
   ok &= dalloc(c, &d.docc, d.ndual + 1) == hipSuccess && dalloc(c, &d.dual_sample, d.ndual + 1) == hipSuccess;
-  ok &= dalloc(c, &d.dlmem, 32 * (d.ndual + 1)) == hipSuccess && dalloc(c, &d.dlcnt, 8 * (d.ndual + 1)) == hipSuccess;
+  ok &= dalloc(c, &d.dlmem, 64 * (d.ndual + 1)) == hipSuccess && dalloc(c, &d.dlcnt, 8 * (d.ndual + 1)) == hipSuccess;
   ok &= dalloc(c, &d.sc, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.broken, n_samples) == hipSuccess;
   ok &= dalloc(c, &d.produced_fx, n_samples) == hipSuccess;

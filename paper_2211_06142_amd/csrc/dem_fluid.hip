@@ -24,12 +24,17 @@ __global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
   const DevState& d = *dp;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  if (*d.abort) return;
-  const SampleConst& c = sample_const(d.sc, d.sample[i]);
+  // one round trip: the abort flag and the particle's own inputs
+  const int ab = *G((const int32_t*)d.abort);
+  const int32_t sl = G((const int32_t*)d.sample)[i];
+  const uint8_t al = G((const uint8_t*)d.alive[buf])[i];
+  const double4 p = gld(G((const double4*)d.xr[buf]) + i);
+  asm volatile("" ::"s"(ab), "v"(sl), "v"((int)al), "v"(p.x), "v"(p.y), "v"(p.z), "v"(p.w));
+  if (ab) return;
+  const SampleConst& c = sample_const(d.sc, sl);
   int64_t nd = (int64_t)c.dn[0] * c.dn[1] * c.dn[2];
   const int32_t skip = (int32_t)(c.dual_base + nd);
-  const double4 p = d.xr[buf][i];
-  if (!d.alive[buf][i] || !c.fluid_on || !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) {
+  if (!al || !c.fluid_on || !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) {
     d.dkey[i] = skip;
     return;
   }
@@ -90,21 +95,27 @@ __device__ inline void member_bins(const SampleConst& c, int k, int b, int cen, 
 // its own: the members of bucket b are the particles whose key is b, and they
 // lie in the binning cells of member_bins, sorted by binning cell since the last
 // rebuild; a group of 8 lanes scans those cells' particles in increasing index
-// (lane u takes every 8th, starting at u) and adds each member's weighted value
-// to the bucket's 8 corners; the lanes' sums are then added in a fixed tree.  The
-// order of every sum is fixed by the binning and the keys.  Buckets that no
-// particle's key named in this evaluation (the occupancy byte) are skipped.
-// kind 0: solid volume (8 per bucket); it also records each lane's members (up
-// to kLaneMem, in scan order) so that kind 1, the particle drag (24 per bucket),
-// visits the same members in the same order without scanning again (a lane with
-// more members scans again); kind 1 clears the occupancy for the next evaluation.
-constexpr int kLaneMem = 4;
+// (row by row, lane u taking every 8th of a row, starting at u) and adds each
+// member's weighted value to the bucket's 8 corners; the lanes' sums are then
+// added in a fixed tree.  The order of every sum is fixed by the binning and the
+// keys.  Buckets that no particle's key named in this evaluation (the occupancy
+// byte) are skipped.  kind 0: solid volume (8 per bucket); it also records the
+// bucket's members in a list of kGroupMem entries (lane 0's in scan order, then
+// lane 1's, ...; each lane's count in its byte), so that kind 1, the particle
+// drag (24 per bucket), visits the same members in the same order without
+// scanning again; a bucket whose members do not fit (more than kGroupMem, or
+// more than kLaneMem on one lane) is marked (count 255) and scanned again.
+// kind 1 clears the occupancy for the next evaluation.
+constexpr int kLaneMem = 16;   // members a lane holds in registers while it scans
+constexpr int kGroupMem = 64;  // entries of a bucket's list
+// binning-cell rows (runs along x) whose bounds a group stages in LDS; a bucket
+// whose widened extent covers more rows scans them one at a time
+constexpr int kScanRows = 16;
 
+// member q's weighted value added to the bucket's corners (fr: its fractions and
+// volume, fp: its drag)
 template <int kKind>
-__device__ inline void add_member(const DevState& d, int32_t q, double* acc) {
-  const double4 fr = gld(G((const double4*)d.dfr) + q);
-  double4 fp = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (kKind == 1) fp = gld(G((const double4*)d.fpart) + q);
+__device__ inline void add_weighted(const double4& fr, const double4& fp, double* acc) {
 #pragma unroll
   for (int corner = 0; corner < 8; ++corner) {
     const double w = corner_w(fr, corner & 1, (corner >> 1) & 1, corner >> 2);
@@ -116,6 +127,67 @@ __device__ inline void add_member(const DevState& d, int32_t q, double* acc) {
       acc[3 * corner + 2] += w * fp.z;
     }
   }
+}
+
+template <int kKind>
+__device__ inline void add_member(const DevState& d, int32_t q, double* acc) {
+  const double4 fr = gld(G((const double4*)d.dfr) + q);
+  double4 fp = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (kKind == 1) fp = gld(G((const double4*)d.fpart) + q);
+  add_weighted<kKind>(fr, fp, acc);
+}
+
+// Members q[0 .. cnt) in order, four at a time: the inputs of four members
+// are fetched before the first of them is added.
+constexpr int kChunk = 4;
+
+template <int kKind>
+__device__ inline void add_chunk(const DevState& d, const int32_t (&q)[kChunk], int cnt, double* acc) {
+  const auto FR = G((const double4*)d.dfr);
+  const auto FP = G((const double4*)d.fpart);
+  double4 fr[kChunk], fp[kChunk];
+#pragma unroll
+  for (int v = 0; v < kChunk; ++v) {
+    const int32_t qq = v < cnt ? q[v] : 0;   // particle 0 exists: an unused, in-bounds read
+    fr[v] = gld(FR + qq);
+    fp[v] = kKind == 1 ? gld(FP + qq) : make_double4(0.0, 0.0, 0.0, 0.0);
+  }
+#pragma unroll
+  for (int v = 0; v < kChunk; ++v)
+    if (v < cnt) add_weighted<kKind>(fr[v], fp[v], acc);
+}
+
+// the members a lane recorded in registers (kind 0)
+template <int kKind>
+__device__ inline void add_held(const DevState& d, const int32_t (&q)[kLaneMem], int cnt, double* acc) {
+#pragma unroll
+  for (int c0 = 0; c0 < kLaneMem; c0 += kChunk) {
+    if (c0 >= cnt) break;
+    const int32_t qc[kChunk] = {q[c0], q[c0 + 1], q[c0 + 2], q[c0 + 3]};
+    add_chunk<kKind>(d, qc, cnt - c0, acc);
+  }
+}
+
+// the members list[0 .. cnt) of a bucket's list (kind 1)
+template <int kKind>
+__device__ inline void add_list(const DevState& d, gptr<const int32_t> list, int cnt, double* acc) {
+  for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+    int32_t qc[kChunk];
+#pragma unroll
+    for (int v = 0; v < kChunk; ++v) qc[v] = c0 + v < cnt ? list[c0 + v] : 0;
+    add_chunk<kKind>(d, qc, cnt - c0, acc);
+  }
+}
+
+// exclusive prefix sum of v over the 8 lanes of a group (lane u of the group)
+__device__ inline int group8_excl(int v, int u) {
+  int s = v;
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) {
+    const int t = __shfl_up(s, off, 8);
+    if (u >= off) s += t;
+  }
+  return s - v;
 }
 
 // Sum over the 8 lanes of a group of each of M values (M a multiple of 8) in a
@@ -146,38 +218,102 @@ __device__ inline void group8_reduce_scatter(const double (&v)[M], int u, double
   }
 }
 
-// Lane u of bucket b's group: call fn(q) for every member q among the
-// candidates it takes (every 8th, starting at u) in scan order.
-template <typename Fn>
-__device__ inline void scan_members(const DevState& d, const SampleConst& c, int64_t b, int u, Fn&& fn) {
+// The binning cells that can hold a member of bucket b (member_bins along each
+// axis): rows (runs along x) in increasing (z, y).
+struct ScanBox {
+  int q0[3], q1[3];
+  int ny, nr;
+};
+
+__device__ inline ScanBox scan_box(const SampleConst& c, int64_t b) {
+  ScanBox sb;
   const int64_t l = b - c.dual_base;
   const int D[3] = {(int)(l % c.dn[0]), (int)((l / c.dn[0]) % c.dn[1]), (int)(l / ((int64_t)c.dn[0] * c.dn[1]))};
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
-  int q0[3], q1[3];
-  for (int k = 0; k < 3; ++k) member_bins(c, k, D[k], cen, q0[k], q1[k]);
-  const auto KEY = G((const int32_t*)d.dkey);
+  for (int k = 0; k < 3; ++k) member_bins(c, k, D[k], cen, sb.q0[k], sb.q1[k]);
+  sb.ny = sb.q1[1] - sb.q0[1] + 1;
+  sb.nr = sb.ny * (sb.q1[2] - sb.q0[2] + 1);
+  return sb;
+}
+
+__device__ inline int64_t scan_row(const SampleConst& c, const ScanBox& sb, int k) {
+  return c.bin_base + ((int64_t)(sb.q0[2] + k / sb.ny) * c.bn[1] + (sb.q0[1] + k % sb.ny)) * c.bn[0];
+}
+
+// The group's lanes load the bounds [first particle, end) of the box's rows
+// together into `rows` (the group's kScanRows LDS entries; every lane of the
+// group takes part, then the wave syncs before any lane reads them).
+__device__ inline void stage_rows(const DevState& d, const SampleConst& c, const ScanBox& sb, int u, int2* rows) {
   const auto CS = G((const int32_t*)d.cell_start);
-  for (int bz = q0[2]; bz <= q1[2]; ++bz)
-    for (int by = q0[1]; by <= q1[1]; ++by) {
-      const int64_t row = c.bin_base + ((int64_t)bz * c.bn[1] + by) * c.bn[0];
-      const int32_t m1 = CS[row + q1[0] + 1];
-      // four candidates per lane and round: all key loads before any use
-      constexpr int kU = 4;
-      for (int32_t m0 = CS[row + q0[0]] + u; m0 < m1; m0 += 8 * kU) {
-        int32_t ks[kU];
-#pragma unroll
-        for (int v = 0; v < kU; ++v) ks[v] = m0 + 8 * v < m1 ? KEY[m0 + 8 * v] : -1;
-#pragma unroll
-        for (int v = 0; v < kU; ++v)
-          if (ks[v] == (int32_t)b) fn(m0 + 8 * v);
-      }
+  if (sb.nr <= kScanRows)
+    for (int k = u; k < sb.nr; k += 8) {
+      const int64_t row = scan_row(c, sb, k);
+      rows[k] = make_int2(CS[row + sb.q0[0]], CS[row + sb.q1[0] + 1]);
     }
+}
+
+// Lane u of bucket b's group: call fn(q) for every member q among the
+// candidates it takes (of each row, every 8th, starting at u) in scan order.
+// With the rows staged (at most kScanRows), the lane fetches the keys of kU
+// candidates at a time, across row ends, before testing any; otherwise it
+// walks the rows one at a time.
+template <typename Fn>
+__device__ inline void scan_members(const DevState& d, const SampleConst& c, int64_t b, int u, const ScanBox& sb,
+                                    const int2* rows, Fn&& fn) {
+  const auto KEY = G((const int32_t*)d.dkey);
+  const int nr = sb.nr;
+  if (nr <= kScanRows) {
+    // the lane's next candidate: m in row r (r == nr: none left)
+    int r = 0;
+    int2 cur = rows[0];
+    int32_t m = cur.x + u;
+    while (m >= cur.y && ++r < nr) {
+      cur = rows[r];
+      m = cur.x + u;
+    }
+    constexpr int kU = 8;
+    while (r < nr) {
+      int32_t cand[kU], ks[kU];
+#pragma unroll
+      for (int v = 0; v < kU; ++v) {
+        cand[v] = r < nr ? m : -1;
+        if (r < nr) {
+          m += 8;
+          while (m >= cur.y && ++r < nr) {
+            cur = rows[r];
+            m = cur.x + u;
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < kU; ++v) ks[v] = cand[v] >= 0 ? KEY[cand[v]] : -1;
+#pragma unroll
+      for (int v = 0; v < kU; ++v)
+        if (ks[v] == (int32_t)b) fn(cand[v]);
+    }
+    return;
+  }
+  const auto CS = G((const int32_t*)d.cell_start);
+  for (int k = 0; k < nr; ++k) {
+    const int64_t row = scan_row(c, sb, k);
+    const int32_t m1 = CS[row + sb.q1[0] + 1];
+    // four candidates per lane and round: all key loads before any use
+    constexpr int kU = 4;
+    for (int32_t m0 = CS[row + sb.q0[0]] + u; m0 < m1; m0 += 8 * kU) {
+      int32_t ks[kU];
+#pragma unroll
+      for (int v = 0; v < kU; ++v) ks[v] = m0 + 8 * v < m1 ? KEY[m0 + 8 * v] : -1;
+#pragma unroll
+      for (int v = 0; v < kU; ++v)
+        if (ks[v] == (int32_t)b) fn(m0 + 8 * v);
+    }
+  }
 }
 
 template <int kKind>
 __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restrict__ dp) {
+  __shared__ int2 rows_lds[256 / 8][kScanRows];
   const DevState& d = *dp;
-  if (*d.abort) return;
   constexpr int m = kKind == 0 ? 8 : 24;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t b = gid >> 3;
@@ -185,7 +321,17 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
   if (b >= d.ndual) return;   // whole group
   const auto OCC = G((uint8_t*)d.docc);
   const auto PART = G(d.dpart + (kKind == 0 ? 0 : 8 * (d.ndual + 1)));
-  if (!OCC[b]) {   // no member: zero partials (lane u writes outputs u, u + 8, ...)
+  const auto LIST = G((int32_t*)d.dlmem) + b * kGroupMem;
+  const auto LN = G((uint8_t*)d.dlcnt);
+  // one round trip: the abort flag, the occupancy, the bucket's sample and
+  // (kind 1) the lane's member count
+  const int ab = *G((const int32_t*)d.abort);
+  const uint8_t occ = OCC[b];
+  const int32_t smp = G((const int32_t*)d.dual_sample)[b];
+  const int listed = kKind == 1 ? (int)LN[gid] : 255;
+  asm volatile("" ::"s"(ab), "v"((int)occ), "v"(smp), "v"(listed));
+  if (ab) return;
+  if (!occ) {   // no member: zero partials (lane u writes outputs u, u + 8, ...)
 #pragma unroll
     for (int j = 0; j < m / 8; ++j) PART[m * b + 8 * j + u] = 0.0;
     return;
@@ -193,22 +339,58 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
   double acc[m];
 #pragma unroll
   for (int k = 0; k < m; ++k) acc[k] = 0.0;
-  const auto LM = G((int32_t*)d.dlmem) + gid * kLaneMem;
-  const auto LN = G((uint8_t*)d.dlcnt);
-  {
-    const int listed = kKind == 1 ? LN[gid] : 255;
-    if (listed <= kLaneMem) {
-      for (int v = 0; v < listed; ++v) add_member<kKind>(d, LM[v], acc);
+  // the group scans (kind 0 always; kind 1 when its bucket's list overflowed:
+  // the count is the same on all the group's lanes then)
+  const bool scan = listed == 255;
+  const SampleConst& c = sample_const(d.sc, smp);
+  int2* rows = rows_lds[threadIdx.x >> 3];
+  ScanBox sb;
+  if (scan) {
+    sb = scan_box(c, b);
+    stage_rows(d, c, sb, u, rows);
+  }
+  wave_lds_sync();
+  if (kKind == 1) {
+    if (!scan) {
+      add_list<kKind>(d, LIST + group8_excl(listed, u), listed, acc);
     } else {
-      const SampleConst& c = sample_const(d.sc, G((const int32_t*)d.dual_sample)[b]);
-      int found = 0;
-      scan_members(d, c, b, u, [&](int32_t q) {
-        add_member<kKind>(d, q, acc);
-        if (kKind == 0 && found < kLaneMem) LM[found] = q;
-        ++found;
-      });
-      if (kKind == 0) LN[gid] = (uint8_t)(found < 255 ? found : 255);
+      scan_members(d, c, b, u, sb, rows, [&](int32_t q) { add_member<kKind>(d, q, acc); });
     }
+  } else {
+    // record up to kLaneMem members in registers, add them, then (more
+    // members) scan again for the rest, in scan order
+    int32_t q[kLaneMem];
+#pragma unroll
+    for (int t = 0; t < kLaneMem; ++t) q[t] = 0;
+    int found = 0;
+    scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
+#pragma unroll
+      for (int t = 0; t < kLaneMem; ++t)
+        if (found == t) q[t] = p;
+      ++found;
+    });
+    add_held<kKind>(d, q, found < kLaneMem ? found : kLaneMem, acc);
+    if (found > kLaneMem) {
+      int seen = 0;
+      scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
+        if (seen >= kLaneMem) add_member<kKind>(d, p, acc);
+        ++seen;
+      });
+    }
+    // the bucket's list for kind 1: lane-major, if every lane's members were
+    // held and all fit
+    const int excl = group8_excl(found, u);
+    const int all = __shfl(excl + found, 7, 8);
+    int most = found;
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off, 8));
+    const bool fits = all <= kGroupMem && most <= kLaneMem;
+    if (fits) {
+#pragma unroll
+      for (int t = 0; t < kLaneMem; ++t)
+        if (t < found) LIST[excl + t] = q[t];
+    }
+    LN[gid] = (uint8_t)(fits ? found : 255);
   }
   // the 8 lanes' sums in a fixed tree; lane u writes outputs u, u + 8, ...
   double tot[m / 8];
@@ -233,7 +415,15 @@ __global__ __launch_bounds__(256) void k_fluid_cells(const DevState* __restrict_
   const int64_t C = gid >> 3;
   const int u = (int)(gid & 7);
   if (C >= d.ncell) return;   // whole group
-  const SampleConst& c = sample_const(d.sc, d.cell_sample[C]);
+  // one round trip: the abort flag, the cell's sample and (kind 0) its inflow
+  const int ab = *G((const int32_t*)d.abort);
+  const int32_t smp = G((const int32_t*)d.cell_sample)[C];
+  double uin[3] = {0.0, 0.0, 0.0};
+  if (kKind == 0)
+    for (int k = 0; k < 3; ++k) uin[k] = G((const double*)d.u_in)[3 * C + k];
+  asm volatile("" ::"s"(ab), "v"(smp), "v"(uin[0]), "v"(uin[1]), "v"(uin[2]));
+  if (ab) return;
+  const SampleConst& c = sample_const(d.sc, smp);
   const int64_t l = C - c.cell_base;
   const int cc[3] = {(int)(l % c.gn[0]), (int)((l / c.gn[0]) % c.gn[1]), (int)(l / ((int64_t)c.gn[0] * c.gn[1]))};
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
@@ -279,41 +469,59 @@ __global__ __launch_bounds__(256) void k_fluid_cells(const DevState* __restrict_
     if (nn < c.n_min) nn = c.n_min;
     if (nn > 1.0) nn = 1.0;
     d.cell_n[C] = nn;
-    for (int k = 0; k < 3; ++k) d.cell_u[3 * C + k] = c.u_superficial ? d.u_in[3 * C + k] / nn : d.u_in[3 * C + k];
+    for (int k = 0; k < 3; ++k) d.cell_u[3 * C + k] = c.u_superficial ? uin[k] / nn : uin[k];
   } else {
     for (int k = 0; k < 3; ++k) d.fdc[3 * C + k] = s[k] / c.vcell;
   }
 }
 
-// Porosity, fluid velocity and dynamic pressure gradient at particle i, with
-// the weights of its deposition (trilinear over the 8 surrounding cell centres,
-// or its own cell for centroid deposition)
-__device__ inline void particle_fluid(const DevState& d, const SampleConst& c, int64_t i, double& np, double u[3],
-                                      double gp[3]) {
+// Porosity, fluid velocity and dynamic pressure gradient at a particle with
+// bucket key `key` and fractions fr, with the weights of its deposition
+// (trilinear over the 8 surrounding cell centres, or its own cell for centroid
+// deposition).  The 8 corners' fields are fetched before the first is added (a
+// corner outside the grid reads the sample's first cell and adds nothing); the
+// sums run in corner order.
+__device__ inline void particle_fluid(const DevState& d, const SampleConst& c, int32_t key, const double4& fr,
+                                      double& np, double u[3], double gp[3]) {
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
-  int64_t l = d.dkey[i] - c.dual_base;
+  int64_t l = key - c.dual_base;
   int b[3] = {(int)(l % c.dn[0]), (int)((l / c.dn[0]) % c.dn[1]), (int)(l / ((int64_t)c.dn[0] * c.dn[1]))};
-  double4 fr = d.dfr[i];
   double f[3] = {fr.x, fr.y, fr.z};
+  const int up = cen ? 1 : 2;
+  const auto CN = G((const double*)d.cell_n);
+  const auto CU = G((const double*)d.cell_u);
+  const auto GP = G((const double*)d.gp_in);
+  bool ok[8];
+  double cn[8], cu[8][3], cg[8][3];
+#pragma unroll
+  for (int corner = 0; corner < 8; ++corner) {
+    const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
+    const int kx = b[0] + dx, ky = b[1] + dy, kz = b[2] + dz;
+    ok[corner] = dx < up && dy < up && dz < up && kx < c.gn[0] && ky < c.gn[1] && kz < c.gn[2];
+    const int64_t C = ok[corner] ? c.cell_base + ((int64_t)kz * c.gn[1] + ky) * c.gn[0] + kx : c.cell_base;
+    cn[corner] = CN[C];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cu[corner][k] = CU[3 * C + k];
+      cg[corner][k] = GP[3 * C + k];
+    }
+  }
   np = 0.0;
   for (int k = 0; k < 3; ++k) { u[k] = 0.0; gp[k] = 0.0; }
-  int up = cen ? 1 : 2;
-  for (int dz = 0; dz < up; ++dz)
-    for (int dy = 0; dy < up; ++dy)
-      for (int dx = 0; dx < up; ++dx) {
-        int kx = b[0] + dx, ky = b[1] + dy, kz = b[2] + dz;
-        if (kx >= c.gn[0] || ky >= c.gn[1] || kz >= c.gn[2]) continue;
-        double wx = cen ? 1.0 : (dx ? f[0] : 1.0 - f[0]);
-        double wy = cen ? 1.0 : (dy ? f[1] : 1.0 - f[1]);
-        double wz = cen ? 1.0 : (dz ? f[2] : 1.0 - f[2]);
-        double w = (wx * wy) * wz;
-        int64_t C = c.cell_base + ((int64_t)kz * c.gn[1] + ky) * c.gn[0] + kx;
-        np += w * d.cell_n[C];
-        for (int k = 0; k < 3; ++k) {
-          u[k] += w * d.cell_u[3 * C + k];
-          gp[k] += w * d.gp_in[3 * C + k];
-        }
-      }
+#pragma unroll
+  for (int corner = 0; corner < 8; ++corner) {
+    if (!ok[corner]) continue;
+    const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
+    double wx = cen ? 1.0 : (dx ? f[0] : 1.0 - f[0]);
+    double wy = cen ? 1.0 : (dy ? f[1] : 1.0 - f[1]);
+    double wz = cen ? 1.0 : (dz ? f[2] : 1.0 - f[2]);
+    double w = (wx * wy) * wz;
+    np += w * cn[corner];
+    for (int k = 0; k < 3; ++k) {
+      u[k] += w * cu[corner][k];
+      gp[k] += w * cg[corner][k];
+    }
+  }
 }
 
 // Learned-closure features of particle i (an extension): porosity at the
@@ -321,7 +529,7 @@ __device__ inline void particle_fluid(const DevState& d, const SampleConst& c, i
 // (eq 11, fine diameter d/k), k, and the mean of delta/R* over the pairs that
 // took part in the last force evaluation, with their count.  Dead: zeros.
 template <typename R>
-__global__ void k_closure_features(const DevState* __restrict__ dp, int buf) {
+__global__ __launch_bounds__(256) void k_closure_features(const DevState* __restrict__ dp, int buf) {
   const DevState& d = *dp;
   if (*d.abort) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -333,7 +541,7 @@ __global__ void k_closure_features(const DevState* __restrict__ dp, int buf) {
     return;
   }
   double np, u[3], gp[3];
-  particle_fluid(d, c, i, np, u, gp);
+  particle_fluid(d, c, d.dkey[i], d.dfr[i], np, u, gp);
   const double4 v = d.vel[buf][i];
   const double4 pi = d.xr[buf][i];
   double s[3] = {u[0] - v.x, u[1] - v.y, u[2] - v.z};
@@ -405,22 +613,32 @@ __device__ inline void drag_force(const SampleConst& c, double np, const double 
 }
 
 template <typename R>
-__global__ void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
+__global__ __launch_bounds__(256) void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
   const DevState& d = *dp;
   if (*d.abort) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  const SampleConst& c = sample_const(d.sc, d.sample[i]);
-  if (!d.alive[buf][i] || !c.fluid_on) {
+  // one round trip: the abort flag and every input of particle i
+  const int ab = *G((const int32_t*)d.abort);
+  const int32_t sl = G((const int32_t*)d.sample)[i];
+  const uint8_t al = G((const uint8_t*)d.alive[buf])[i];
+  const int32_t key = G((const int32_t*)d.dkey)[i];
+  const double4 fr = gld(G((const double4*)d.dfr) + i);
+  const double4 v = gld(G((const double4*)d.vel[buf]) + i);
+  const double r = G((const double*)d.xr[buf])[4 * i + 3];
+  const double cdr = d.cdrag ? G((const double*)d.cdrag)[i] : 1.0;
+  asm volatile("" ::"s"(ab), "v"(sl), "v"((int)al), "v"(key));
+  if (ab) return;
+  const SampleConst& c = sample_const(d.sc, sl);
+  if (!al || !c.fluid_on) {
     ((R4<R>*)d.fdr)[i] = mk4<R>(0, 0, 0, 0);
     d.fpart[i] = make_double4(0, 0, 0, 0);
     return;
   }
   double np, u[3], gp[3];
-  particle_fluid(d, c, i, np, u, gp);
-  const double4 fr = d.dfr[i];
+  particle_fluid(d, c, key, fr, np, u, gp);
   double fd[3], fb[3];
-  drag_force(c, np, u, gp, d.vel[buf][i], d.xr[buf][i].w, fr.w, d.cdrag ? d.cdrag[i] : 1.0, fd, fb);
+  drag_force(c, np, u, gp, v, r, fr.w, cdr, fd, fb);
   d.fpart[i] = make_double4(fd[0], fd[1], fd[2], 0.0);
   ((R4<R>*)d.fdr)[i] = mk4<R>((R)(fd[0] + fb[0]), (R)(fd[1] + fb[1]), (R)(fd[2] + fb[2]), (R)0);
 }

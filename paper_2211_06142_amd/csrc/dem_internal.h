@@ -151,8 +151,8 @@ struct DevState {
                                    // 8 * (ndual + 1) on) 24 drag corner partials
   int32_t* dkey;
   uint8_t* docc;                   // ndual: bucket named by some particle's key in this evaluation
-  int32_t* dlmem;                  // 8 * ndual * 4: members found by each lane of a bucket's group
-  uint8_t* dlcnt;                  // 8 * ndual: their count (more than 4: the lane scans again)
+  int32_t* dlmem;                  // 64 * ndual: each bucket's members, lane-major in scan order
+  uint8_t* dlcnt;                  // 8 * ndual: each lane's count (255: the list overflowed, scan again)
   int32_t* dual_sample;            // ndual: sample of each bucket
   double4* dfr;                    // CIC fractions (fx, fy, fz, volume)
   double4* fpart;                  // particle drag of the latest evaluation
