@@ -292,7 +292,8 @@ def learned_cg_block(horizon, ks=(2, 3), c4=False):
         report = (synth.c4(1), synth.c4(k)) if c4 else (synth.c1(seed=2), synth.c2(k, seed=2))
         layer = parcel_layer_mass(report[1]) if c4 else None
         res = ct.gain_test(train, judge, report, horizon=horizon, window=500, epochs=30,
-                           report_mass=None if layer is None else 10.0 * layer)
+                           report_mass=None if layer is None else 10.0 * layer,
+                           log=lambda s: print("bench: learned-CG k=%d: %s" % (k, s), file=sys.stderr, flush=True))
         if layer is not None:
             res["parcel_layer_mass_kg"] = layer
         for key in ("net", "norm"):

@@ -228,15 +228,22 @@ def train_net(X, Y, norm, epochs=30, batch=4096, lr=2e-3, seed=0, init_scale=0.5
     return net, losses
 
 
-def _timed_run(w, steps, closure=None, norm=None):
-    """wall time of `steps` steps (one dem_step call, synchronised) from the
-    initial packing, and the produced mass at the end"""
+def _timed_run(w, steps, closure=None, norm=None, log=None, chunk=20000):
+    """wall time of `steps` steps (dem_step calls of `chunk` steps,
+    synchronised at the end) from the initial packing, and the produced mass
+    at the end; log: a line after every call"""
     import torch
     sim = make_sim(w, closure, norm)
     sim.step(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(steps)
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        sim.step(n)
+        done += n
+        if log:
+            log("%s: timed %d of %d steps" % (w["name"], done, steps))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     m = float(sim.state()["produced_mass"])
@@ -244,17 +251,26 @@ def _timed_run(w, steps, closure=None, norm=None):
     return wall, m
 
 
-def _mass_series(w, steps, window, closure=None, norm=None, until_mass=None, max_steps=None):
+def _mass_series(w, steps, window, closure=None, norm=None, until_mass=None, max_steps=None, log=None,
+                 log_every=40):
     """produced mass at the end of every window of a run from the initial
     packing; with until_mass: windows until the produced mass reaches it (at
-    most max_steps), the horizon then being the steps taken"""
+    most max_steps), the horizon then being the steps taken; log: a progress
+    line every log_every windows"""
     rec = Recorder(w, make_sim(w, closure, norm))
+
+    def progress():
+        if log and len(rec.mass) % log_every == 0:
+            log("%s: %d steps, produced %.4g kg" % (w["name"], len(rec.mass) * window, rec.mass[-1][1]))
+
     if until_mass is None:
         for _ in range(steps // window):
             rec.run_window(window, keep=False)
+            progress()
     else:
         while True:
             rec.run_window(window, keep=False)
+            progress()
             done = len(rec.mass) * window
             if rec.mass[-1][1] >= until_mass or done >= max_steps:
                 break
@@ -298,13 +314,13 @@ def gain_test(train, judge, report, horizon=20000, window=500, epochs=40, batch=
            "packings": {"train": wf["name"], "judge": judge[0]["name"], "report": report[0]["name"]}}
     for role, (f, c) in (("judge", judge), ("report", report)):
         if role == "report" and report_mass is not None:
-            mf = _mass_series(f, 0, window, until_mass=report_mass, max_steps=report_max_steps)
+            mf = _mass_series(f, 0, window, until_mass=report_mass, max_steps=report_max_steps, log=log)
             out["report_horizon_steps"] = int(len(mf) * window)
         else:
-            mf = _mass_series(f, horizon, window)
+            mf = _mass_series(f, horizon, window, log=log)
         steps = len(mf) * window
-        mp = _mass_series(c, steps, window)
-        ml = _mass_series(c, steps, window, net, norm)
+        mp = _mass_series(c, steps, window, log=log)
+        ml = _mass_series(c, steps, window, net, norm, log=log)
         ep, rp = _errors(mf, mp)
         el, rl = _errors(mf, ml)
         out[role] = {"mass_fine": float(mf[-1]), "mass_plain_cg": float(mp[-1]), "mass_learned_cg": float(ml[-1]),
@@ -315,8 +331,9 @@ def gain_test(train, judge, report, horizon=20000, window=500, epochs=40, batch=
     out["closure_accepted"] = accepted
     rf, rc = report
     rsteps = out.get("report_horizon_steps", horizon)
-    wall_fine, _ = _timed_run(rf, rsteps)
-    wall_cg, _ = _timed_run(rc, rsteps, net if accepted else None, norm if accepted else None)
+    say("timing the fine and the kept coarse model over %d steps" % rsteps)
+    wall_fine, _ = _timed_run(rf, rsteps, log=log)
+    wall_cg, _ = _timed_run(rc, rsteps, net if accepted else None, norm if accepted else None, log=log)
     out.update(wall_fine_s=wall_fine, wall_cg_s=wall_cg, speedup_vs_fine=wall_fine / wall_cg, net=net, norm=norm)
     # the model the rule keeps, on the reporting packing
     r = out["report"]
