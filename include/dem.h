@@ -97,7 +97,8 @@ typedef struct {
 } dem_wall;
 
 /* Cell-centred fluid grid: n[0]*n[1]*n[2] cells of equal size covering
- * [lo, hi]; cell (ix, iy, iz) has linear index (iz*n[1] + iy)*n[0] + ix. */
+ * [lo, hi]; cell (ix, iy, iz) has linear index (iz*n[1] + iy)*n[0] + ix.
+ * At most 2^30 cells per sample (DEM_E_INVAL otherwise). */
 typedef struct {
   double lo[3], hi[3];
   int32_t n[3];

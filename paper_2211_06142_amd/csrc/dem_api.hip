@@ -163,6 +163,8 @@ dem_status validate(const dem_params& p) {
   if (p.fluid_on) {
     for (int c = 0; c < 3; ++c)
       if (p.grid.n[c] < 1 || !(p.grid.hi[c] > p.grid.lo[c])) return DEM_E_INVAL;
+    // a sample's cells are indexed in 32 bits on the device
+    if ((int64_t)p.grid.n[0] * p.grid.n[1] * p.grid.n[2] > (int64_t)1 << 30) return DEM_E_INVAL;
     if (!(p.rho_f > 0.0) || !(p.mu_f > 0.0) || !(p.n_min > 0.0 && p.n_min <= 1.0)) return DEM_E_INVAL;
     if (p.couple_every < 1) return DEM_E_INVAL;
     if (p.voidfrac != DEM_VOID_CIC && p.voidfrac != DEM_VOID_CENTROID) return DEM_E_INVAL;

@@ -67,6 +67,17 @@ __global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
   d.dfr[i] = make_double4(f[0], f[1], f[2], V);
 }
 
+// (x, y, z) of the local index l of a cell or bucket of an nx x ny grid layer
+// stack (l < 2^30: a sample's grid is limited to that many cells), in 32-bit
+// arithmetic
+__device__ inline void unflatten3(int64_t l, int nx, int ny, int (&o)[3]) {
+  const int32_t q = (int32_t)l;
+  const int32_t t = q / nx;
+  o[0] = q - t * nx;
+  o[2] = t / ny;
+  o[1] = t - o[2] * ny;
+}
+
 // trilinear weight of corner (kx, ky, kz) in {0,1}^3 of a bucket
 __device__ inline double corner_w(const double4& fr, int kx, int ky, int kz) {
   double wx = kx ? fr.x : 1.0 - fr.x;
@@ -228,7 +239,8 @@ struct ScanBox {
 __device__ inline ScanBox scan_box(const SampleConst& c, int64_t b) {
   ScanBox sb;
   const int64_t l = b - c.dual_base;
-  const int D[3] = {(int)(l % c.dn[0]), (int)((l / c.dn[0]) % c.dn[1]), (int)(l / ((int64_t)c.dn[0] * c.dn[1]))};
+  int D[3];
+  unflatten3(l, c.dn[0], c.dn[1], D);
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
   for (int k = 0; k < 3; ++k) member_bins(c, k, D[k], cen, sb.q0[k], sb.q1[k]);
   sb.ny = sb.q1[1] - sb.q0[1] + 1;
@@ -425,7 +437,8 @@ __global__ __launch_bounds__(256) void k_fluid_cells(const DevState* __restrict_
   if (ab) return;
   const SampleConst& c = sample_const(d.sc, smp);
   const int64_t l = C - c.cell_base;
-  const int cc[3] = {(int)(l % c.gn[0]), (int)((l / c.gn[0]) % c.gn[1]), (int)(l / ((int64_t)c.gn[0] * c.gn[1]))};
+  int cc[3];
+  unflatten3(l, c.gn[0], c.gn[1], cc);
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
   int lo[3], hi[3];
   for (int k = 0; k < 3; ++k) {
@@ -485,7 +498,8 @@ __device__ inline void particle_fluid(const DevState& d, const SampleConst& c, i
                                       double& np, double u[3], double gp[3]) {
   const int cen = c.voidfrac == DEM_VOID_CENTROID;
   int64_t l = key - c.dual_base;
-  int b[3] = {(int)(l % c.dn[0]), (int)((l / c.dn[0]) % c.dn[1]), (int)(l / ((int64_t)c.dn[0] * c.dn[1]))};
+  int b[3];
+  unflatten3(l, c.dn[0], c.dn[1], b);
   double f[3] = {fr.x, fr.y, fr.z};
   const int up = cen ? 1 : 2;
   const auto CN = G((const double*)d.cell_n);
