@@ -341,3 +341,200 @@ double settle_packing_jacobi(int64_t n, double* x, const double* r, int kind, co
   free(rr); free(tmp); free(xref); free(disp); free(rowp); free(cols);
   return worst;
 }
+
+/* build_pairs in two parallel passes (counts per larger sphere, then the
+ * pairs at their offsets): the same list in the same order */
+static int64_t build_pairs_par(int64_t n, const double* x, const double* rr, double h, double skin,
+                               int64_t** pi, int64_t** pj, int64_t* cap) {
+  grid_t g;
+  grid_build(&g, n, x, h);
+  int64_t* cnt = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+      if (cnt[n] > *cap) {
+        *cap = cnt[n] + cnt[n] / 4 + 1024;
+        *pi = (int64_t*)realloc(*pi, sizeof(int64_t) * (size_t)*cap);
+        *pj = (int64_t*)realloc(*pj, sizeof(int64_t) * (size_t)*cap);
+      }
+    }
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+      double R = 2.0 * rr[i] + skin;
+      int64_t k0[3], k1[3];
+      for (int c = 0; c < 3; ++c) {
+        k0[c] = clampi((int64_t)floor((x[3 * i + c] - R - g.lo[c]) / h), 0, g.nc[c] - 1);
+        k1[c] = clampi((int64_t)floor((x[3 * i + c] + R - g.lo[c]) / h), 0, g.nc[c] - 1);
+      }
+      int64_t at = pass == 1 ? cnt[i] : 0, m = 0;
+      for (int64_t kz = k0[2]; kz <= k1[2]; ++kz)
+        for (int64_t ky = k0[1]; ky <= k1[1]; ++ky)
+          for (int64_t kx = k0[0]; kx <= k1[0]; ++kx) {
+            int64_t cid = (kz * g.nc[1] + ky) * g.nc[0] + kx;
+            for (int64_t q = g.start[cid]; q < g.start[cid + 1]; ++q) {
+              int64_t j = g.idx[q];
+              if (j == i) continue;
+              if (rr[j] > rr[i] || (rr[j] == rr[i] && j < i)) continue;
+              double d2 = 0.0;
+              for (int c = 0; c < 3; ++c) { double d = x[3 * j + c] - x[3 * i + c]; d2 += d * d; }
+              double cc = rr[i] + rr[j] + skin;
+              if (d2 >= cc * cc) continue;
+              if (pass == 1) { (*pi)[at + m] = i; (*pj)[at + m] = j; }
+              ++m;
+            }
+          }
+      if (pass == 0) cnt[i + 1] = m;
+    }
+  }
+  int64_t np = cnt[n];
+  free(cnt);
+  grid_free(&g);
+  return np;
+}
+
+/*
+ * settle_packing_colored: settle_packing with the overlap sweep spread over
+ * threads (OpenMP), still Gauss-Seidel (every correction sees the positions the
+ * corrections before it left) and deterministic for any thread count.  At
+ * every pair-list rebuild each pair goes to the block (a cube of side B, more
+ * than the longest pair reach 2 r_max + skin) that holds its larger sphere, in
+ * list order; a block's colour is its coordinates mod 3, and a sweep takes the
+ * 27 colours in turn.  Two blocks of one colour are at least 2 B apart, so no
+ * sphere is within reach of both: the spheres their pairs move are distinct
+ * (the pairs are fixed between rebuilds), and the blocks of a colour run in
+ * parallel, each through its pairs in list order.
+ */
+double settle_packing_colored(int64_t n, double* x, const double* r, int kind, const double* prm,
+                              double shrink, int iters, int settle_iters, double drop, double relax) {
+  double* rr = (double*)malloc(sizeof(double) * (size_t)n);
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)n);
+  double* xref = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    rr[i] = r[i] * shrink;
+    tmp[i] = rr[i];
+    if (rr[i] > rmax) rmax = rr[i];
+  }
+  qsort(tmp, (size_t)n, sizeof(double), cmpd);
+  double rmed = tmp[n / 2];
+  double h = 2.0 * rmed;
+  double skin = 0.5 * rmed;
+  double B = 1.05 * (2.0 * rmax + skin);
+  int64_t *pi = NULL, *pj = NULL, cap = 0, np = 0;
+  int64_t *si = NULL, *sj = NULL, *bstart = NULL, *cblk = NULL, ccnt[28];
+  double cum = 0.0;
+  int need = 1;
+  double worst = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    double dz = 0.0;
+    if (it < settle_iters) dz = drop * (1.0 - (double)it / (double)settle_iters);
+    cum += dz;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      x[3 * i + 2] -= dz;
+      confine(kind, prm, rr[i], &x[3 * i]);
+    }
+    if (!need) {
+      double m2 = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : m2)
+      for (int64_t i = 0; i < n; ++i) {
+        double d0 = x[3 * i] - xref[3 * i], d1 = x[3 * i + 1] - xref[3 * i + 1];
+        double d2 = x[3 * i + 2] - (xref[3 * i + 2] - cum);
+        double q = d0 * d0 + d1 * d1 + d2 * d2;
+        if (q > m2) m2 = q;
+      }
+      if (m2 > 0.25 * skin * skin) need = 1;
+    }
+    if (need) {
+      np = build_pairs_par(n, x, rr, h, skin, &pi, &pj, &cap);
+      memcpy(xref, x, sizeof(double) * 3 * (size_t)n);
+      cum = 0.0;
+      need = 0;
+      // blocks of the larger spheres, a stable counting sort of the pairs by
+      // block, and the non-empty blocks listed by colour
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) {
+          if (x[3 * i + c] < lo[c]) lo[c] = x[3 * i + c];
+          if (x[3 * i + c] > hi[c]) hi[c] = x[3 * i + c];
+        }
+      int64_t nb[3], tot = 1;
+      for (int c = 0; c < 3; ++c) {
+        nb[c] = (int64_t)floor((hi[c] - lo[c]) / B) + 1;
+        tot *= nb[c];
+      }
+      int64_t* blk = (int64_t*)malloc(sizeof(int64_t) * (size_t)(np > 0 ? np : 1));
+      free(bstart);
+      bstart = (int64_t*)calloc((size_t)tot + 1, sizeof(int64_t));
+      for (int64_t k = 0; k < np; ++k) {
+        const double* p = &x[3 * pi[k]];
+        int64_t b[3];
+        for (int c = 0; c < 3; ++c) b[c] = clampi((int64_t)floor((p[c] - lo[c]) / B), 0, nb[c] - 1);
+        blk[k] = (b[2] * nb[1] + b[1]) * nb[0] + b[0];
+        bstart[blk[k] + 1]++;
+      }
+      for (int64_t b = 0; b < tot; ++b) bstart[b + 1] += bstart[b];
+      free(si); free(sj);
+      si = (int64_t*)malloc(sizeof(int64_t) * (size_t)(np > 0 ? np : 1));
+      sj = (int64_t*)malloc(sizeof(int64_t) * (size_t)(np > 0 ? np : 1));
+      {
+        int64_t* at = (int64_t*)malloc(sizeof(int64_t) * (size_t)tot);
+        memcpy(at, bstart, sizeof(int64_t) * (size_t)tot);
+        for (int64_t k = 0; k < np; ++k) {
+          int64_t q = at[blk[k]]++;
+          si[q] = pi[k];
+          sj[q] = pj[k];
+        }
+        free(at);
+      }
+      free(blk);
+      free(cblk);
+      cblk = (int64_t*)malloc(sizeof(int64_t) * (size_t)tot);
+      int64_t m = 0;
+      for (int col = 0; col < 27; ++col) {
+        ccnt[col] = m;
+        for (int64_t bz = col / 9; bz < nb[2]; bz += 3)
+          for (int64_t by = (col / 3) % 3; by < nb[1]; by += 3)
+            for (int64_t bx = col % 3; bx < nb[0]; bx += 3) {
+              int64_t b = (bz * nb[1] + by) * nb[0] + bx;
+              if (bstart[b + 1] > bstart[b]) cblk[m++] = b;
+            }
+      }
+      ccnt[27] = m;
+    }
+    worst = 0.0;
+    for (int col = 0; col < 27; ++col) {
+      double w = 0.0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(max : w)
+      for (int64_t q = ccnt[col]; q < ccnt[col + 1]; ++q) {
+        const int64_t b = cblk[q];
+        for (int64_t k = bstart[b]; k < bstart[b + 1]; ++k) {
+          int64_t i = si[k], j = sj[k];
+          double d[3], d2 = 0.0;
+          for (int c = 0; c < 3; ++c) { d[c] = x[3 * j + c] - x[3 * i + c]; d2 += d[c] * d[c]; }
+          double cc = rr[i] + rr[j];
+          if (d2 >= cc * cc) continue;
+          double dist = sqrt(d2);
+          double ov = cc - dist;
+          double rel = ov / (rr[j] < rr[i] ? rr[j] : rr[i]);
+          if (rel > w) w = rel;
+          double nn[3];
+          if (dist > 0.0) { for (int c = 0; c < 3; ++c) nn[c] = d[c] / dist; }
+          else { nn[0] = 0.0; nn[1] = 0.0; nn[2] = 1.0; }
+          double vi = rr[i] * rr[i] * rr[i], vj = rr[j] * rr[j] * rr[j];
+          double s_i = relax * ov * vj / (vi + vj), s_j = relax * ov * vi / (vi + vj);
+          for (int c = 0; c < 3; ++c) {
+            x[3 * i + c] -= s_i * nn[c];
+            x[3 * j + c] += s_j * nn[c];
+          }
+        }
+      }
+      if (w > worst) worst = w;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) confine(kind, prm, rr[i], &x[3 * i]);
+  }
+  free(rr); free(tmp); free(xref); free(pi); free(pj);
+  free(si); free(sj); free(bstart); free(cblk);
+  return worst;
+}
