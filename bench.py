@@ -101,9 +101,10 @@ def host_cpu():
 
 
 def cpu_baseline(w, budget_s=25.0):
-    """The FP64 oracle on the same workload, single thread, bounded sample
-    (about 1.5 s per step at 200 000 spheres on a 2.7 GHz Xeon core, so the
-    budget holds some 15-20 steps, one or two coupling evaluations)."""
+    """The FP64 oracle on the same workload, single thread, bounded sample:
+    the workload's own run length (c0: its 1 000 steps) or as many steps as the
+    budget holds (about 1.5 s per step at 200 000 spheres, so some 15-20 steps,
+    one or two coupling evaluations)."""
     import oracle
     from oracle import cg
     mat = cg.scale_material(w["material"], w.get("k", 1.0))
@@ -119,7 +120,7 @@ def cpu_baseline(w, budget_s=25.0):
         sim.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or steps >= 200:
+        if el > budget_s or steps >= w.get("steps", 200):
             break
     nal = int(sim.state()["alive"].sum())
     return {"value": nal * steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
