@@ -68,6 +68,9 @@ def _L():
         L.settle_packing_jacobi.argtypes = L.settle_packing.argtypes
         L.settle_packing_colored.restype = ctypes.c_double
         L.settle_packing_colored.argtypes = L.settle_packing.argtypes
+        L.deep_overlaps.restype = ctypes.c_int64
+        L.deep_overlaps.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                    ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -155,6 +158,17 @@ def relax(x, r, region_kind, region, sweeps, chunk=100, shrink=0.998, log=None):
         if log:
             log("relax: %d of %d sweeps, largest overlap %.4f" % (done + k, sweeps, worst))
     return x, worst
+
+
+def deep_overlap_mask(x, r, thresh):
+    """True for the smaller sphere of every pair overlapping by more than
+    thresh times the smaller radius"""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    flags = np.zeros(len(r), np.uint8)
+    _L().deep_overlaps(len(r), x.ctypes.data_as(ctypes.c_void_p), r.ctypes.data_as(ctypes.c_void_p), thresh,
+                       flags.ctypes.data_as(ctypes.c_void_p))
+    return flags.astype(bool)
 
 
 def _cache_path(name):
@@ -284,6 +298,10 @@ def cylinder_workload(n, seed, name, k=1.0, scheme="ssw", R=12e-3, r_cav=2e-3, H
         if relax_sweeps:
             x, worst = relax(x, r, 1, (0.0, 0.0, r_cav, R, 0.0, H), relax_sweeps,
                              log=lambda s: print("%s %s" % (name, s), flush=True))
+            # spheres still wedged deep into a neighbour (against a wall, where
+            # the confinement undoes the projection) are taken out
+            keep = ~deep_overlap_mask(x, r, DEEP_OVERLAP)
+            x, r = np.ascontiguousarray(x[keep]), np.ascontiguousarray(r[keep])
         return {"x": x, "r": r, "worst": np.array(worst)}
 
     pk = cached(name, make)
@@ -327,6 +345,7 @@ def c2(k=2, scheme="ssw", n_fine=200000, seed=0):
 # schedule moves it further per sweep and leaves its lower part compressed; this
 # many more projection sweeps relax it
 C4_RELAX_SWEEPS = 1000
+DEEP_OVERLAP = 0.2   # overlap / smaller radius above which the relaxed column drops the smaller sphere
 
 
 def c4(k=1, scheme="ssw"):

@@ -538,3 +538,45 @@ double settle_packing_colored(int64_t n, double* x, const double* r, int kind, c
   free(si); free(sj); free(bstart); free(cblk);
   return worst;
 }
+
+/*
+ * deep_overlaps: flags[k] = 1 for the smaller sphere (ties: the higher index)
+ * of every pair whose overlap exceeds `thresh` times the smaller radius;
+ * returns the number of flagged spheres.
+ */
+int64_t deep_overlaps(int64_t n, const double* x, const double* r, double thresh, uint8_t* flags) {
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    flags[i] = 0;
+    if (r[i] > rmax) rmax = r[i];
+  }
+  const double h = 2.0 * rmax;
+  grid_t g;
+  grid_build(&g, n, x, h);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t k0[3], k1[3];
+    for (int c = 0; c < 3; ++c) {
+      k0[c] = clampi((int64_t)floor((x[3 * i + c] - h - g.lo[c]) / h), 0, g.nc[c] - 1);
+      k1[c] = clampi((int64_t)floor((x[3 * i + c] + h - g.lo[c]) / h), 0, g.nc[c] - 1);
+    }
+    for (int64_t kz = k0[2]; kz <= k1[2]; ++kz)
+      for (int64_t ky = k0[1]; ky <= k1[1]; ++ky)
+        for (int64_t kx = k0[0]; kx <= k1[0]; ++kx) {
+          int64_t cid = (kz * g.nc[1] + ky) * g.nc[0] + kx;
+          for (int64_t q = g.start[cid]; q < g.start[cid + 1]; ++q) {
+            int64_t j = g.idx[q];
+            // i is the smaller sphere of the pair (ties: the higher index)
+            if (j == i || r[j] < r[i] || (r[j] == r[i] && j > i)) continue;
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) { double d = x[3 * j + c] - x[3 * i + c]; d2 += d * d; }
+            double ov = r[i] + r[j] - sqrt(d2);
+            if (ov > thresh * r[i]) flags[i] = 1;
+          }
+        }
+  }
+  grid_free(&g);
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) m += flags[i];
+  return m;
+}
