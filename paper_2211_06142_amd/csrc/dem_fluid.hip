@@ -322,7 +322,7 @@ __device__ inline void scan_members(const DevState& d, const SampleConst& c, int
   }
 }
 
-template <int kKind>
+template <int kKind, bool kDense>
 __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restrict__ dp) {
   __shared__ int2 rows_lds[256 / 8][kScanRows];
   const DevState& d = *dp;
@@ -369,25 +369,30 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
       scan_members(d, c, b, u, sb, rows, [&](int32_t q) { add_member<kKind>(d, q, acc); });
     }
   } else {
-    // record up to kLaneMem members in registers, add them, then (more
-    // members) scan again for the rest, in scan order
+    // hold the first kLaneMem members in registers for the bucket's list.
+    // Sparse buckets: add the held ones after the scan, their loads issued
+    // together, then (more members) scan again for the rest.  Dense buckets
+    // (kDense): add every member as the scan finds it.  Both add in scan order.
     int32_t q[kLaneMem];
 #pragma unroll
     for (int t = 0; t < kLaneMem; ++t) q[t] = 0;
     int found = 0;
     scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
+      if (kDense) add_member<kKind>(d, p, acc);
 #pragma unroll
       for (int t = 0; t < kLaneMem; ++t)
         if (found == t) q[t] = p;
       ++found;
     });
-    add_held<kKind>(d, q, found < kLaneMem ? found : kLaneMem, acc);
-    if (found > kLaneMem) {
-      int seen = 0;
-      scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
-        if (seen >= kLaneMem) add_member<kKind>(d, p, acc);
-        ++seen;
-      });
+    if (!kDense) {
+      add_held<kKind>(d, q, found < kLaneMem ? found : kLaneMem, acc);
+      if (found > kLaneMem) {
+        int seen = 0;
+        scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
+          if (seen >= kLaneMem) add_member<kKind>(d, p, acc);
+          ++seen;
+        });
+      }
     }
     // the bucket's list for kind 1: lane-major, if every lane's members were
     // held and all fit
@@ -659,14 +664,19 @@ __global__ __launch_bounds__(256) void k_fluid_drag(const DevState* __restrict__
 
 template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
   hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
-  hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
+  // more than 32 particles per bucket on average: many lanes find more members
+  // than they hold, so the solid-volume pass adds them as it finds them
+  if (d.n > 32 * d.ndual)
+    hipLaunchKernelGGL((k_fluid_partials<0, true>), dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
+  else
+    hipLaunchKernelGGL((k_fluid_partials<0, false>), dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell * 8)), dim3(kBlock), 0, s, d.self);
   if (d.closure_on) {
     hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
     launch_closure_infer(d, s);
   }
   hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
-  hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
+  hipLaunchKernelGGL((k_fluid_partials<1, false>), dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell * 8)), dim3(kBlock), 0, s, d.self);
 }
 template void launch_fluid<double>(DevState&, int, hipStream_t);
