@@ -17,21 +17,25 @@
 
 namespace dem {
 
+// fn(s) for the active lanes of each sample of the wave in turn, with the
+// sample index s in a scalar register: the sample's constants are then scalar
+// loads through the constant cache.  Lanes of one sample stay together, so the
+// groups of 8 lanes of a bucket or a cell (one sample each) stay whole.
+template <typename Fn>
+__device__ inline void per_sample(int sl, Fn&& fn) {
+  uint64_t todo = __ballot(1);
+  while (todo) {
+    const int first = __builtin_ctzll(todo);
+    const bool mine = sl == __builtin_amdgcn_readlane(sl, first);
+    if (mine) fn(opaque_readlane(sl, first));
+    todo &= ~__ballot(mine);
+  }
+}
+
 // Key (bucket) and trilinear fractions of every particle; dead particles, and
 // every particle of a sample without fluid, get their sample's skip key, which
 // no cell reads.
-__global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
-  const DevState& d = *dp;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  // one round trip: the abort flag and the particle's own inputs
-  const int ab = *G((const int32_t*)d.abort);
-  const int32_t sl = G((const int32_t*)d.sample)[i];
-  const uint8_t al = G((const uint8_t*)d.alive[buf])[i];
-  const double4 p = gld(G((const double4*)d.xr[buf]) + i);
-  asm volatile("" ::"s"(ab), "v"(sl), "v"((int)al), "v"(p.x), "v"(p.y), "v"(p.z), "v"(p.w));
-  if (ab) return;
-  const SampleConst& c = sample_const(d.sc, sl);
+__device__ inline void fluid_key(const DevState& d, const SampleConst& c, int64_t i, uint8_t al, const double4& p) {
   int64_t nd = (int64_t)c.dn[0] * c.dn[1] * c.dn[2];
   const int32_t skip = (int32_t)(c.dual_base + nd);
   if (!al || !c.fluid_on || !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z)) {
@@ -65,6 +69,20 @@ __global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
   d.docc[key] = 1;   // the bucket has a member in this evaluation
   const double V = (4.0 / 3.0) * M_PI * p.w * p.w * p.w;
   d.dfr[i] = make_double4(f[0], f[1], f[2], V);
+}
+
+__global__ void k_fluid_key(const DevState* __restrict__ dp, int buf) {
+  const DevState& d = *dp;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  // one round trip: the abort flag and the particle's own inputs
+  const int ab = *G((const int32_t*)d.abort);
+  const int32_t sl = G((const int32_t*)d.sample)[i];
+  const uint8_t al = G((const uint8_t*)d.alive[buf])[i];
+  const double4 p = gld(G((const double4*)d.xr[buf]) + i);
+  asm volatile("" ::"s"(ab), "v"(sl), "v"((int)al), "v"(p.x), "v"(p.y), "v"(p.z), "v"(p.w));
+  if (ab) return;
+  per_sample(sl, [&](int s) { fluid_key(d, sample_const(d.sc, s), i, al, p); });
 }
 
 // (x, y, z) of the local index l of a cell or bucket of an nx x ny grid layer
@@ -427,7 +445,6 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
 template <int kKind>
 __global__ __launch_bounds__(256) void k_fluid_cells(const DevState* __restrict__ dp) {
   const DevState& d = *dp;
-  if (*d.abort) return;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t C = gid >> 3;
   const int u = (int)(gid & 7);
@@ -440,57 +457,59 @@ __global__ __launch_bounds__(256) void k_fluid_cells(const DevState* __restrict_
     for (int k = 0; k < 3; ++k) uin[k] = G((const double*)d.u_in)[3 * C + k];
   asm volatile("" ::"s"(ab), "v"(smp), "v"(uin[0]), "v"(uin[1]), "v"(uin[2]));
   if (ab) return;
-  const SampleConst& c = sample_const(d.sc, smp);
-  const int64_t l = C - c.cell_base;
-  int cc[3];
-  unflatten3(l, c.gn[0], c.gn[1], cc);
-  const int cen = c.voidfrac == DEM_VOID_CENTROID;
-  int lo[3], hi[3];
-  for (int k = 0; k < 3; ++k) {
-    if (cen) { lo[k] = hi[k] = cc[k]; }
-    else if (c.gn[k] == 1) { lo[k] = hi[k] = 0; }
-    else { lo[k] = cc[k] - 1 < 0 ? 0 : cc[k] - 1; hi[k] = cc[k] > c.gn[k] - 2 ? c.gn[k] - 2 : cc[k]; }
-  }
-  constexpr int m = kKind == 0 ? 8 : 24, nv = m / 8;
-  const double* part = d.dpart + (kKind == 0 ? 0 : 8 * (d.ndual + 1));
-  const int Dx = lo[0] + (u & 1), Dy = lo[1] + ((u >> 1) & 1), Dz = lo[2] + (u >> 2);
-  double s[nv];
-  for (int v = 0; v < nv; ++v) s[v] = 0.0;
-  if (Dx <= hi[0] && Dy <= hi[1] && Dz <= hi[2]) {
-    const int64_t key = c.dual_base + ((int64_t)Dz * c.dn[1] + Dy) * c.dn[0] + Dx;
-    // corner of this cell in the bucket; a direction of one cell folds both
-    // trilinear weights onto the only cell
-    const int kx = (cen || c.gn[0] == 1) ? -1 : cc[0] - Dx;
-    const int ky = (cen || c.gn[1] == 1) ? -1 : cc[1] - Dy;
-    const int kz = (cen || c.gn[2] == 1) ? -1 : cc[2] - Dz;
-    for (int cz = 0; cz < 2; ++cz) {
-      if (kz >= 0 ? cz != kz : (cen && cz != 0)) continue;
-      for (int cy = 0; cy < 2; ++cy) {
-        if (ky >= 0 ? cy != ky : (cen && cy != 0)) continue;
-        for (int cx = 0; cx < 2; ++cx) {
-          if (kx >= 0 ? cx != kx : (cen && cx != 0)) continue;
-          const int corner = (cz << 2) | (cy << 1) | cx;
-          for (int v = 0; v < nv; ++v) s[v] += part[m * key + nv * corner + v];
+  per_sample(smp, [&](int sc) {
+    const SampleConst& c = sample_const(d.sc, sc);
+    const int64_t l = C - c.cell_base;
+    int cc[3];
+    unflatten3(l, c.gn[0], c.gn[1], cc);
+    const int cen = c.voidfrac == DEM_VOID_CENTROID;
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      if (cen) { lo[k] = hi[k] = cc[k]; }
+      else if (c.gn[k] == 1) { lo[k] = hi[k] = 0; }
+      else { lo[k] = cc[k] - 1 < 0 ? 0 : cc[k] - 1; hi[k] = cc[k] > c.gn[k] - 2 ? c.gn[k] - 2 : cc[k]; }
+    }
+    constexpr int m = kKind == 0 ? 8 : 24, nv = m / 8;
+    const double* part = d.dpart + (kKind == 0 ? 0 : 8 * (d.ndual + 1));
+    const int Dx = lo[0] + (u & 1), Dy = lo[1] + ((u >> 1) & 1), Dz = lo[2] + (u >> 2);
+    double s[nv];
+    for (int v = 0; v < nv; ++v) s[v] = 0.0;
+    if (Dx <= hi[0] && Dy <= hi[1] && Dz <= hi[2]) {
+      const int64_t key = c.dual_base + ((int64_t)Dz * c.dn[1] + Dy) * c.dn[0] + Dx;
+      // corner of this cell in the bucket; a direction of one cell folds both
+      // trilinear weights onto the only cell
+      const int kx = (cen || c.gn[0] == 1) ? -1 : cc[0] - Dx;
+      const int ky = (cen || c.gn[1] == 1) ? -1 : cc[1] - Dy;
+      const int kz = (cen || c.gn[2] == 1) ? -1 : cc[2] - Dz;
+      for (int cz = 0; cz < 2; ++cz) {
+        if (kz >= 0 ? cz != kz : (cen && cz != 0)) continue;
+        for (int cy = 0; cy < 2; ++cy) {
+          if (ky >= 0 ? cy != ky : (cen && cy != 0)) continue;
+          for (int cx = 0; cx < 2; ++cx) {
+            if (kx >= 0 ? cx != kx : (cen && cx != 0)) continue;
+            const int corner = (cz << 2) | (cy << 1) | cx;
+            for (int v = 0; v < nv; ++v) s[v] += part[m * key + nv * corner + v];
+          }
         }
       }
     }
-  }
-#pragma unroll
-  for (int v = 0; v < nv; ++v)
-#pragma unroll
-    for (int off = 4; off > 0; off >>= 1) s[v] += __shfl_xor(s[v], off, 8);
-  if (u != 0) return;
-  if (kKind == 0) {
-    const double eps = s[0] / c.vcell;
-    d.eps[C] = eps;
-    double nn = 1.0 - eps;
-    if (nn < c.n_min) nn = c.n_min;
-    if (nn > 1.0) nn = 1.0;
-    d.cell_n[C] = nn;
-    for (int k = 0; k < 3; ++k) d.cell_u[3 * C + k] = c.u_superficial ? uin[k] / nn : uin[k];
-  } else {
-    for (int k = 0; k < 3; ++k) d.fdc[3 * C + k] = s[k] / c.vcell;
-  }
+  #pragma unroll
+    for (int v = 0; v < nv; ++v)
+  #pragma unroll
+      for (int off = 4; off > 0; off >>= 1) s[v] += __shfl_xor(s[v], off, 8);
+    if (u != 0) return;
+    if (kKind == 0) {
+      const double eps = s[0] / c.vcell;
+      d.eps[C] = eps;
+      double nn = 1.0 - eps;
+      if (nn < c.n_min) nn = c.n_min;
+      if (nn > 1.0) nn = 1.0;
+      d.cell_n[C] = nn;
+      for (int k = 0; k < 3; ++k) d.cell_u[3 * C + k] = c.u_superficial ? uin[k] / nn : uin[k];
+    } else {
+      for (int k = 0; k < 3; ++k) d.fdc[3 * C + k] = s[k] / c.vcell;
+    }
+  });
 }
 
 // Porosity, fluid velocity and dynamic pressure gradient at a particle with
@@ -634,7 +653,6 @@ __device__ inline void drag_force(const SampleConst& c, double np, const double 
 template <typename R>
 __global__ __launch_bounds__(256) void k_fluid_drag(const DevState* __restrict__ dp, int buf) {
   const DevState& d = *dp;
-  if (*d.abort) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   // one round trip: the abort flag and every input of particle i
@@ -648,18 +666,20 @@ __global__ __launch_bounds__(256) void k_fluid_drag(const DevState* __restrict__
   const double cdr = d.cdrag ? G((const double*)d.cdrag)[i] : 1.0;
   asm volatile("" ::"s"(ab), "v"(sl), "v"((int)al), "v"(key));
   if (ab) return;
-  const SampleConst& c = sample_const(d.sc, sl);
-  if (!al || !c.fluid_on) {
-    ((R4<R>*)d.fdr)[i] = mk4<R>(0, 0, 0, 0);
-    d.fpart[i] = make_double4(0, 0, 0, 0);
-    return;
-  }
-  double np, u[3], gp[3];
-  particle_fluid(d, c, key, fr, np, u, gp);
-  double fd[3], fb[3];
-  drag_force(c, np, u, gp, v, r, fr.w, cdr, fd, fb);
-  d.fpart[i] = make_double4(fd[0], fd[1], fd[2], 0.0);
-  ((R4<R>*)d.fdr)[i] = mk4<R>((R)(fd[0] + fb[0]), (R)(fd[1] + fb[1]), (R)(fd[2] + fb[2]), (R)0);
+  per_sample(sl, [&](int sc) {
+    const SampleConst& c = sample_const(d.sc, sc);
+    if (!al || !c.fluid_on) {
+      ((R4<R>*)d.fdr)[i] = mk4<R>(0, 0, 0, 0);
+      d.fpart[i] = make_double4(0, 0, 0, 0);
+      return;
+    }
+    double np, u[3], gp[3];
+    particle_fluid(d, c, key, fr, np, u, gp);
+    double fd[3], fb[3];
+    drag_force(c, np, u, gp, v, r, fr.w, cdr, fd, fb);
+    d.fpart[i] = make_double4(fd[0], fd[1], fd[2], 0.0);
+    ((R4<R>*)d.fdr)[i] = mk4<R>((R)(fd[0] + fb[0]), (R)(fd[1] + fb[1]), (R)(fd[2] + fb[2]), (R)0);
+  });
 }
 
 template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
