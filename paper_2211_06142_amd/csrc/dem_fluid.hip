@@ -366,73 +366,75 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
     for (int j = 0; j < m / 8; ++j) PART[m * b + 8 * j + u] = 0.0;
     return;
   }
-  double acc[m];
+  per_sample(smp, [&](int sc) {
+    const SampleConst& c = sample_const(d.sc, sc);
+    double acc[m];
 #pragma unroll
-  for (int k = 0; k < m; ++k) acc[k] = 0.0;
-  // the group scans (kind 0 always; kind 1 when its bucket's list overflowed:
-  // the count is the same on all the group's lanes then)
-  const bool scan = listed == 255;
-  const SampleConst& c = sample_const(d.sc, smp);
-  int2* rows = rows_lds[threadIdx.x >> 3];
-  ScanBox sb;
-  if (scan) {
-    sb = scan_box(c, b);
-    stage_rows(d, c, sb, u, rows);
-  }
-  wave_lds_sync();
-  if (kKind == 1) {
-    if (!scan) {
-      add_list<kKind>(d, LIST + group8_excl(listed, u), listed, acc);
-    } else {
-      scan_members(d, c, b, u, sb, rows, [&](int32_t q) { add_member<kKind>(d, q, acc); });
+    for (int k = 0; k < m; ++k) acc[k] = 0.0;
+    // the group scans (kind 0 always; kind 1 when its bucket's list overflowed:
+    // the count is the same on all the group's lanes then)
+    const bool scan = listed == 255;
+    int2* rows = rows_lds[threadIdx.x >> 3];
+    ScanBox sb;
+    if (scan) {
+      sb = scan_box(c, b);
+      stage_rows(d, c, sb, u, rows);
     }
-  } else {
-    // hold the first kLaneMem members in registers for the bucket's list.
-    // Sparse buckets: add the held ones after the scan, their loads issued
-    // together, then (more members) scan again for the rest.  Dense buckets
-    // (kDense): add every member as the scan finds it.  Both add in scan order.
-    int32_t q[kLaneMem];
-#pragma unroll
-    for (int t = 0; t < kLaneMem; ++t) q[t] = 0;
-    int found = 0;
-    scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
-      if (kDense) add_member<kKind>(d, p, acc);
-#pragma unroll
-      for (int t = 0; t < kLaneMem; ++t)
-        if (found == t) q[t] = p;
-      ++found;
-    });
-    if (!kDense) {
-      add_held<kKind>(d, q, found < kLaneMem ? found : kLaneMem, acc);
-      if (found > kLaneMem) {
-        int seen = 0;
-        scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
-          if (seen >= kLaneMem) add_member<kKind>(d, p, acc);
-          ++seen;
-        });
+    wave_lds_sync();
+    if (kKind == 1) {
+      if (!scan) {
+        add_list<kKind>(d, LIST + group8_excl(listed, u), listed, acc);
+      } else {
+        scan_members(d, c, b, u, sb, rows, [&](int32_t q) { add_member<kKind>(d, q, acc); });
       }
+    } else {
+      // hold the first kLaneMem members in registers for the bucket's list.
+      // Sparse buckets: add the held ones after the scan, their loads issued
+      // together, then (more members) scan again for the rest.  Dense buckets
+      // (kDense): add every member as the scan finds it.  Both add in scan order.
+      int32_t q[kLaneMem];
+#pragma unroll
+      for (int t = 0; t < kLaneMem; ++t) q[t] = 0;
+      int found = 0;
+      scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
+        if (kDense) add_member<kKind>(d, p, acc);
+#pragma unroll
+        for (int t = 0; t < kLaneMem; ++t)
+          if (found == t) q[t] = p;
+        ++found;
+      });
+      if (!kDense) {
+        add_held<kKind>(d, q, found < kLaneMem ? found : kLaneMem, acc);
+        if (found > kLaneMem) {
+          int seen = 0;
+          scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
+            if (seen >= kLaneMem) add_member<kKind>(d, p, acc);
+            ++seen;
+          });
+        }
+      }
+      // the bucket's list for kind 1: lane-major, if every lane's members were
+      // held and all fit
+      const int excl = group8_excl(found, u);
+      const int all = __shfl(excl + found, 7, 8);
+      int most = found;
+#pragma unroll
+      for (int off = 4; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off, 8));
+      const bool fits = all <= kGroupMem && most <= kLaneMem;
+      if (fits) {
+#pragma unroll
+        for (int t = 0; t < kLaneMem; ++t)
+          if (t < found) LIST[excl + t] = q[t];
+      }
+      LN[gid] = (uint8_t)(fits ? found : 255);
     }
-    // the bucket's list for kind 1: lane-major, if every lane's members were
-    // held and all fit
-    const int excl = group8_excl(found, u);
-    const int all = __shfl(excl + found, 7, 8);
-    int most = found;
+    // the 8 lanes' sums in a fixed tree; lane u writes outputs u, u + 8, ...
+    double tot[m / 8];
+    group8_reduce_scatter<m>(acc, u, tot);
 #pragma unroll
-    for (int off = 4; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off, 8));
-    const bool fits = all <= kGroupMem && most <= kLaneMem;
-    if (fits) {
-#pragma unroll
-      for (int t = 0; t < kLaneMem; ++t)
-        if (t < found) LIST[excl + t] = q[t];
-    }
-    LN[gid] = (uint8_t)(fits ? found : 255);
-  }
-  // the 8 lanes' sums in a fixed tree; lane u writes outputs u, u + 8, ...
-  double tot[m / 8];
-  group8_reduce_scatter<m>(acc, u, tot);
-#pragma unroll
-  for (int j = 0; j < m / 8; ++j) PART[m * b + 8 * j + u] = tot[j];
-  if (kKind == 1 && u == 0) OCC[b] = 0;
+    for (int j = 0; j < m / 8; ++j) PART[m * b + 8 * j + u] = tot[j];
+    if (kKind == 1 && u == 0) OCC[b] = 0;
+  });
 }
 
 // Per fluid cell: the sum of the corner partials of the (up to 8) adjacent
@@ -493,9 +495,9 @@ __global__ __launch_bounds__(256) void k_fluid_cells(const DevState* __restrict_
         }
       }
     }
-  #pragma unroll
+#pragma unroll
     for (int v = 0; v < nv; ++v)
-  #pragma unroll
+#pragma unroll
       for (int off = 4; off > 0; off >>= 1) s[v] += __shfl_xor(s[v], off, 8);
     if (u != 0) return;
     if (kKind == 0) {
