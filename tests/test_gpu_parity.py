@@ -180,6 +180,33 @@ def test_c0_fluid_cells_fp64():
     np.testing.assert_allclose(fd, of["fdrag_cell"], rtol=0, atol=1e-12 * fs)
 
 
+@pytest.mark.parametrize("gn", [4, 5])
+def test_coarse_grid_bucket_overflow_fp64(gn):
+    """The c0 bed on a coarse fluid grid, so that buckets hold far more members
+    than a bucket's list (64) or a lane (16) keeps: gn 5 is the sparse path of
+    the solid-volume pass (31 particles per bucket on average, up to 163 in a
+    bucket: its second scan, and the drag pass scanning overflowed buckets
+    again), gn 4 the dense one (74 on average, up to 275).  Porosity and cell
+    drag source against the oracle after one step (eq 6, eq 7)."""
+    w = dict(c0_sub())
+    lo, hi, _ = w["grid"]
+    w["grid"] = (lo, hi, (gn, gn, gn))
+    w["u_cell"], w["gradp_cell"] = synth.uniform_field(w["grid"], (0.0, 0.0, 0.05))
+    ndual = (gn - 1) ** 3
+    assert (len(w["r"]) > 32 * ndual) == (gn == 4)
+    g = gpu_for(w, "fp64")
+    o = oracle_for(w, bond_at_init=True)
+    g.step(1)
+    o.step(1)
+    eps, fd = g.fluid_out()
+    of = o.fluid()
+    np.testing.assert_allclose(eps, of["eps_s"], rtol=1e-12, atol=1e-15)
+    fs = np.abs(of["fdrag_cell"]).max()
+    np.testing.assert_allclose(fd, of["fdrag_cell"], rtol=0, atol=1e-12 * fs)
+    gs, os_ = g.state(), o.state()
+    assert scaled_err(gs["F"], os_["F"], os_["fscale"]) < 1e-12
+
+
 def test_c0_mixed_one_step():
     w = c0_sub()
     g = gpu_for(w, "mixed")
