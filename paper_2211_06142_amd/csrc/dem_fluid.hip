@@ -270,24 +270,25 @@ __device__ inline int64_t scan_row(const SampleConst& c, const ScanBox& sb, int 
   return c.bin_base + ((int64_t)(sb.q0[2] + k / sb.ny) * c.bn[1] + (sb.q0[1] + k % sb.ny)) * c.bn[0];
 }
 
-// The group's lanes load the bounds [first particle, end) of the box's rows
-// together into `rows` (the group's kScanRows LDS entries; every lane of the
-// group takes part, then the wave syncs before any lane reads them).
+// The group's kLanes lanes load the bounds [first particle, end) of the box's
+// rows together into `rows` (the group's kScanRows LDS entries; every lane of
+// the group takes part, then the wave syncs before any lane reads them).
+template <int kLanes = 8>
 __device__ inline void stage_rows(const DevState& d, const SampleConst& c, const ScanBox& sb, int u, int2* rows) {
   const auto CS = G((const int32_t*)d.cell_start);
   if (sb.nr <= kScanRows)
-    for (int k = u; k < sb.nr; k += 8) {
+    for (int k = u; k < sb.nr; k += kLanes) {
       const int64_t row = scan_row(c, sb, k);
       rows[k] = make_int2(CS[row + sb.q0[0]], CS[row + sb.q1[0] + 1]);
     }
 }
 
-// Lane u of bucket b's group: call fn(q) for every member q among the
-// candidates it takes (of each row, every 8th, starting at u) in scan order.
-// With the rows staged (at most kScanRows), the lane fetches the keys of kU
-// candidates at a time, across row ends, before testing any; otherwise it
-// walks the rows one at a time.
-template <typename Fn>
+// Lane u of bucket b's group of kLanes lanes: call fn(q) for every member q
+// among the candidates it takes (of each row, every kLanes-th, starting at u) in
+// scan order.  With the rows staged (at most kScanRows), the lane fetches the
+// keys of kU candidates at a time, across row ends, before testing any;
+// otherwise it walks the rows one at a time.
+template <int kLanes = 8, typename Fn>
 __device__ inline void scan_members(const DevState& d, const SampleConst& c, int64_t b, int u, const ScanBox& sb,
                                     const int2* rows, Fn&& fn) {
   const auto KEY = G((const int32_t*)d.dkey);
@@ -308,7 +309,7 @@ __device__ inline void scan_members(const DevState& d, const SampleConst& c, int
       for (int v = 0; v < kU; ++v) {
         cand[v] = r < nr ? m : -1;
         if (r < nr) {
-          m += 8;
+          m += kLanes;
           while (m >= cur.y && ++r < nr) {
             cur = rows[r];
             m = cur.x + u;
@@ -329,18 +330,18 @@ __device__ inline void scan_members(const DevState& d, const SampleConst& c, int
     const int32_t m1 = CS[row + sb.q1[0] + 1];
     // four candidates per lane and round: all key loads before any use
     constexpr int kU = 4;
-    for (int32_t m0 = CS[row + sb.q0[0]] + u; m0 < m1; m0 += 8 * kU) {
+    for (int32_t m0 = CS[row + sb.q0[0]] + u; m0 < m1; m0 += kLanes * kU) {
       int32_t ks[kU];
 #pragma unroll
-      for (int v = 0; v < kU; ++v) ks[v] = m0 + 8 * v < m1 ? KEY[m0 + 8 * v] : -1;
+      for (int v = 0; v < kU; ++v) ks[v] = m0 + kLanes * v < m1 ? KEY[m0 + kLanes * v] : -1;
 #pragma unroll
       for (int v = 0; v < kU; ++v)
-        if (ks[v] == (int32_t)b) fn(m0 + 8 * v);
+        if (ks[v] == (int32_t)b) fn(m0 + kLanes * v);
     }
   }
 }
 
-template <int kKind, bool kDense>
+template <int kKind>
 __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restrict__ dp) {
   __shared__ int2 rows_lds[256 / 8][kScanRows];
   const DevState& d = *dp;
@@ -388,30 +389,26 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
         scan_members(d, c, b, u, sb, rows, [&](int32_t q) { add_member<kKind>(d, q, acc); });
       }
     } else {
-      // hold the first kLaneMem members in registers for the bucket's list.
-      // Sparse buckets: add the held ones after the scan, their loads issued
-      // together, then (more members) scan again for the rest.  Dense buckets
-      // (kDense): add every member as the scan finds it.  Both add in scan order.
+      // hold the first kLaneMem members in registers for the bucket's list,
+      // add them after the scan (their loads issued together), then (more
+      // members) scan again for the rest, in scan order
       int32_t q[kLaneMem];
 #pragma unroll
       for (int t = 0; t < kLaneMem; ++t) q[t] = 0;
       int found = 0;
       scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
-        if (kDense) add_member<kKind>(d, p, acc);
 #pragma unroll
         for (int t = 0; t < kLaneMem; ++t)
           if (found == t) q[t] = p;
         ++found;
       });
-      if (!kDense) {
-        add_held<kKind>(d, q, found < kLaneMem ? found : kLaneMem, acc);
-        if (found > kLaneMem) {
-          int seen = 0;
-          scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
-            if (seen >= kLaneMem) add_member<kKind>(d, p, acc);
-            ++seen;
-          });
-        }
+      add_held<kKind>(d, q, found < kLaneMem ? found : kLaneMem, acc);
+      if (found > kLaneMem) {
+        int seen = 0;
+        scan_members(d, c, b, u, sb, rows, [&](int32_t p) {
+          if (seen >= kLaneMem) add_member<kKind>(d, p, acc);
+          ++seen;
+        });
       }
       // the bucket's list for kind 1: lane-major, if every lane's members were
       // held and all fit
@@ -435,6 +432,55 @@ __global__ __launch_bounds__(256) void k_fluid_partials(const DevState* __restri
     for (int j = 0; j < m / 8; ++j) PART[m * b + 8 * j + u] = tot[j];
     if (kKind == 1 && u == 0) OCC[b] = 0;
   });
+}
+
+// Dense buckets (more than 32 particles per bucket on average: a coarse grid
+// over many grains, where the groups of 8 would leave most of the chip idle and
+// their lists would overflow): a whole wave per bucket.  Lane u scans every
+// 64th candidate of each row and adds its members as it finds them (scan
+// order); the lanes' sums are then added in a fixed xor butterfly (partners 32,
+// 16, ..., 1), which leaves every lane with the same totals, and lane j writes
+// output j.  Both passes scan (no member lists); the drag pass clears the
+// occupancy.
+template <int kKind>
+__global__ __launch_bounds__(256) void k_fluid_partials_wave(const DevState* __restrict__ dp) {
+  __shared__ int2 rows_lds[256 / 64][kScanRows];
+  const DevState& d = *dp;
+  constexpr int m = kKind == 0 ? 8 : 24;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = gid >> 6;
+  const int u = (int)(gid & 63);
+  if (b >= d.ndual) return;   // whole wave
+  const auto OCC = G((uint8_t*)d.docc);
+  const auto PART = G(d.dpart + (kKind == 0 ? 0 : 8 * (d.ndual + 1)));
+  // one round trip: the abort flag, the occupancy and the bucket's sample
+  const int ab = *G((const int32_t*)d.abort);
+  const uint8_t occ = OCC[b];
+  const int32_t smp = G((const int32_t*)d.dual_sample)[b];
+  asm volatile("" ::"s"(ab), "v"((int)occ), "v"(smp));
+  if (ab) return;
+  if (!occ) {   // no member: zero partials
+    if (u < m) PART[m * b + u] = 0.0;
+    return;
+  }
+  const SampleConst& c = sample_const(d.sc, opaque_readlane(smp, 0));   // one bucket per wave
+  double acc[m];
+#pragma unroll
+  for (int k = 0; k < m; ++k) acc[k] = 0.0;
+  int2* rows = rows_lds[threadIdx.x >> 6];
+  const ScanBox sb = scan_box(c, b);
+  stage_rows<64>(d, c, sb, u, rows);
+  wave_lds_sync();
+  scan_members<64>(d, c, b, u, sb, rows, [&](int32_t q) { add_member<kKind>(d, q, acc); });
+  double out = 0.0;
+#pragma unroll
+  for (int k = 0; k < m; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    if (u == k) out = acc[k];
+  }
+  if (u < m) PART[m * b + u] = out;
+  if (kKind == 1 && u == 0) OCC[b] = 0;
 }
 
 // Per fluid cell: the sum of the corner partials of the (up to 8) adjacent
@@ -686,19 +732,22 @@ __global__ __launch_bounds__(256) void k_fluid_drag(const DevState* __restrict__
 
 template <typename R> void launch_fluid(DevState& d, int buf, hipStream_t s) {
   hipLaunchKernelGGL(k_fluid_key, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
-  // more than 32 particles per bucket on average: many lanes find more members
-  // than they hold, so the solid-volume pass adds them as it finds them
-  if (d.n > 32 * d.ndual)
-    hipLaunchKernelGGL((k_fluid_partials<0, true>), dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
+  // more than 32 particles per bucket on average: a wave per bucket
+  const bool dense = d.n > 32 * d.ndual;
+  if (dense)
+    hipLaunchKernelGGL(k_fluid_partials_wave<0>, dim3(nblk(d.ndual * 64)), dim3(kBlock), 0, s, d.self);
   else
-    hipLaunchKernelGGL((k_fluid_partials<0, false>), dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
+    hipLaunchKernelGGL(k_fluid_partials<0>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<0>, dim3(nblk(d.ncell * 8)), dim3(kBlock), 0, s, d.self);
   if (d.closure_on) {
     hipLaunchKernelGGL(k_closure_features<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
     launch_closure_infer(d, s);
   }
   hipLaunchKernelGGL(k_fluid_drag<R>, dim3(nblk(d.n)), dim3(kBlock), 0, s, d.self, buf);
-  hipLaunchKernelGGL((k_fluid_partials<1, false>), dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
+  if (dense)
+    hipLaunchKernelGGL(k_fluid_partials_wave<1>, dim3(nblk(d.ndual * 64)), dim3(kBlock), 0, s, d.self);
+  else
+    hipLaunchKernelGGL(k_fluid_partials<1>, dim3(nblk(d.ndual * 8)), dim3(kBlock), 0, s, d.self);
   if (d.ncell > 0) hipLaunchKernelGGL(k_fluid_cells<1>, dim3(nblk(d.ncell * 8)), dim3(kBlock), 0, s, d.self);
 }
 template void launch_fluid<double>(DevState&, int, hipStream_t);
