@@ -53,3 +53,21 @@ def test_traffic_summary_needs_matching_sources(tmp_path, monkeypatch, cls):
     d3 = dict(d, source_hash="f" * 16)
     (prof / ("%s_c1_pmc.json" % cls)).write_text(json.dumps(d3))
     assert bench.load_traffic(cls, "c1") == d["traffic_bytes_per_launch"]
+
+
+def test_uncompressed_paper_sample_at_full_size_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "f2"], capture_output=True,
+                       text=True, timeout=300)
+    assert p.returncode == 2
+    assert "--f2-protocol" in p.stderr
+
+
+def test_ensemble_baseline_in_worker_processes_counts_every_sample():
+    import synth
+    ws = [synth.c3_crop(s, 120, 0.5) for s in range(3)]
+    one = bench.cpu_baseline_ensemble(ws, budget_s=60.0, steps=2, workers=1)
+    many = bench.cpu_baseline_ensemble(ws, budget_s=60.0, steps=2, workers=2)
+    assert one["cores"] == 1 and many["cores"] == 2
+    for b in (one, many):
+        assert b["kind"] == "oracle" and b["value"] > 0.0
+        assert b["sample"].startswith("3 of 3 samples, 2 steps each")
